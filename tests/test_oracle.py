@@ -1,0 +1,342 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Each test names what fixes the expected value: a brute-force plane-wave
+convolution, a closed form, an invariant of Eq. (chi0), the exact band sum that
+Eqs. (chi02)/(energyintegration) reduce to, the paper's printed tables, the
+free-electron state count, a second factorisation, or finite differences.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import grad as og
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def tiny(nd=12, rw=3, ng=27, nv=3, nc=5, seed=7):
+    gw = synth.wf_sphere(nd, rw)
+    cell = np.eye(3) * 7.0
+    gc = synth.chi_sphere(ng, (0.01, 0, 0), cell)
+    rows = synth.gaussian_columns(99, 30 + seed, range(nv + nc), gw.shape[0])
+    q = synth.orthonormalize(rows)
+    r = np.random.default_rng(seed)
+    e_v = np.sort(r.uniform(-0.4, -0.05, nv))
+    e_c = np.sort(r.uniform(0.2, 1.5, nc))
+    return dict(gw=gw, gc=gc, cv=q[:nv], cc=q[nv:], e_v=e_v, e_c=e_c, nd=(nd, nd, nd), cell=cell)
+
+
+# ---------------------------------------------------------------- matrix element
+def test_pair_density_fft_equals_direct_convolution():
+    t = tiny()
+    pv = oracle.psi_real_space(t["cv"], t["gw"], t["nd"])
+    pc = oracle.psi_real_space(t["cc"], t["gw"], t["nd"])
+    m_fft = oracle.pair_density_fft(pv, pc, t["gc"])
+    m_dir = oracle.pair_density_direct(t["cv"], t["cc"], t["gw"], t["gc"])
+    assert np.abs(m_fft - m_dir).max() < 1e-14
+
+
+def test_pair_density_plane_wave_closed_form():
+    # c_v = e_{G_a}, c_c = e_{G_b}  =>  M(G) = 1 if G = G_a - G_b else 0
+    gw = synth.wf_sphere(12, 3)
+    gc = synth.chi_sphere(27, (0.01, 0, 0), np.eye(3) * 7.0)
+    pa, pb = [5, 17, 40], [2, 9, 33, 60]
+    cv = synth.plane_wave_bands(gw, pa)
+    cc = synth.plane_wave_bands(gw, pb)
+    m = oracle.pair_density_fft(oracle.psi_real_space(cv, gw, (12,) * 3),
+                                oracle.psi_real_space(cc, gw, (12,) * 3), gc)
+    for i, a in enumerate(pa):
+        for j, b in enumerate(pb):
+            want = np.array([1.0 if tuple(g) == tuple(gw[a] - gw[b]) else 0.0 for g in gc.tolist()])
+            assert np.abs(m[i, j] - want).max() < 1e-14
+
+
+def test_pair_density_head_is_overlap():
+    # M_nm(G=0) = <n|m>: identity for an orthonormal set
+    t = tiny()
+    allc = np.concatenate([t["cv"], t["cc"]])
+    p = oracle.psi_real_space(allc, t["gw"], t["nd"])
+    g0 = np.array([[0, 0, 0]], dtype=np.int32)
+    m = oracle.pair_density_fft(p, p, g0)[:, :, 0]
+    assert np.abs(m - np.eye(len(allc))).max() < 1e-14
+
+
+def test_pair_density_parseval():
+    t = tiny()
+    nd = t["nd"][0]
+    a = np.arange(-nd // 2, nd // 2)
+    full = np.stack(np.meshgrid(a, a, a, indexing="ij"), -1).reshape(-1, 3).astype(np.int32)
+    pv = oracle.psi_real_space(t["cv"][:1], t["gw"], t["nd"])
+    pc = oracle.psi_real_space(t["cc"][:2], t["gw"], t["nd"])
+    m = oracle.pair_density_fft(pv, pc, full)
+    lhs = (np.abs(m[0]) ** 2).sum(1)
+    rhs = (np.abs(pv[0])[None] ** 2 * np.abs(pc) ** 2).reshape(2, -1).sum(1) / nd ** 3
+    assert np.allclose(lhs, rhs, rtol=1e-13)
+
+
+def test_alias_free_bound():
+    gw = synth.wf_sphere(12, 3)
+    gc = synth.chi_sphere(27, (0.01, 0, 0), np.eye(3) * 7.0)
+    assert oracle.alias_free(gw, gc, (12, 12, 12))
+    assert not oracle.alias_free(gw, gc, (7, 12, 12))
+
+
+# ---------------------------------------------------------------- weights
+def test_weights_static_limit_and_symmetry():
+    r = np.random.default_rng(3)
+    e_v = -r.uniform(0.05, 0.5, 4)
+    e_c = r.uniform(0.2, 2.0, 6)
+    n = r.uniform(0.5, 3, 6)
+    ws = oracle.weights_static(e_v, e_c, n)
+    assert np.allclose(ws, n[None] / (e_v[:, None] - e_c[None]), rtol=1e-15)
+    assert np.all(ws < 0)
+    w0 = oracle.weights(e_v, e_c, n, 0.0, 0.0)
+    assert np.abs(w0 - ws).max() == 0.0
+    for om in (0.01, 0.2, 1.3):
+        wp = oracle.weights(e_v, e_c, n, om, 0.004)
+        wm = oracle.weights(e_v, e_c, n, -om, 0.004)
+        assert np.allclose(wp, wm, rtol=1e-14, atol=0)
+
+
+def test_weights_below_gap_closed_form():
+    # |w| below the gap, delta = 0: n/2 (1/(x-w) + 1/(x+w)) = n x/(x^2 - w^2) < 0
+    e_v = np.array([-0.3, -0.1])
+    e_c = np.array([0.25, 0.6])
+    x = e_v[:, None] - e_c[None]
+    for om in (0.05, 0.2, 0.3):
+        w = oracle.weights(e_v, e_c, None, om, 0.0)
+        assert np.allclose(w.real, x / (x * x - om * om), rtol=1e-14)
+        assert np.all(w.imag == 0) and np.all(w.real < 0)
+
+
+# ---------------------------------------------------------------- chi0
+def test_chi0_static_hermitian_negative_semidefinite():
+    t = tiny(nv=4, nc=9)
+    chi = oracle.chi0_bands(t["cv"], t["e_v"], t["cc"], t["e_c"], t["gw"], t["gc"], t["nd"])[0]
+    assert np.abs(chi - chi.conj().T).max() < 1e-15 * np.abs(chi).max() * 10
+    ev = np.linalg.eigvalsh(chi)
+    assert ev.max() <= 1e-13 * np.abs(ev).max()
+    # head row and column vanish: M_vc(G=0) = <v|c> = 0
+    assert np.abs(chi[0]).max() < 1e-14 and np.abs(chi[:, 0]).max() < 1e-14
+
+
+def test_chi0_plane_waves_is_lindhard_sum():
+    # plane-wave states: chi0_GG' = delta_GG' sum_{v,c: G_v - G_c = G} w_vc (discrete Lindhard sum)
+    gw = synth.wf_sphere(12, 3)
+    gc = synth.chi_sphere(27, (0.01, 0, 0), np.eye(3) * 7.0)
+    pv, pc = [0, 1, 2, 3], [7, 8, 9, 10, 20, 30]
+    e_v = np.array([-0.5, -0.4, -0.35, -0.2])
+    e_c = np.array([0.3, 0.31, 0.5, 0.9, 1.1, 1.7])
+    n_c = np.array([1.0, 2.0, 1.0, 0.5, 1.0, 3.0])
+    for om, d in ((0.0, 0.0), (0.15, 0.01)):
+        chi = oracle.chi0_bands(synth.plane_wave_bands(gw, pv), e_v, synth.plane_wave_bands(gw, pc), e_c,
+                                gw, gc, (12,) * 3, omegas=(om,), delta=d, n_col=n_c)[0]
+        want = np.zeros(len(gc), dtype=np.complex128)
+        gl = [tuple(g) for g in gc.tolist()]
+        for i, a in enumerate(pv):
+            for j, b in enumerate(pc):
+                dg = tuple(gw[a] - gw[b])
+                if dg in gl:
+                    x = e_v[i] - e_c[j]
+                    want[gl.index(dg)] += n_c[j] * 0.5 * (1 / (x - om + 1j * d) + 1 / (x + om + 1j * d))
+        assert np.abs(chi - np.diag(want)).max() < 1e-14
+
+
+def test_chi0_dynamic_symmetries():
+    t = tiny(nv=3, nc=6)
+    args = (t["cv"], t["e_v"], t["cc"], t["e_c"], t["gw"], t["gc"], t["nd"])
+    om = [0.07, -0.07]
+    chi = oracle.chi0_bands(*args, omegas=om, delta=0.003)
+    assert np.abs(chi[0] - chi[1]).max() < 1e-14 * np.abs(chi).max()
+    # below the gap with delta = 0 the dynamic chi0 is Hermitian and NSD
+    gap = t["e_c"].min() - t["e_v"].max()
+    chi_b = oracle.chi0_bands(*args, omegas=[0.5 * gap], delta=0.0)[0]
+    assert np.abs(chi_b - chi_b.conj().T).max() < 1e-14 * np.abs(chi_b).max()
+    assert np.linalg.eigvalsh(chi_b).max() <= 1e-13 * np.abs(chi_b).max()
+
+
+def test_chi0_linear_in_column_chunks():
+    t = tiny(nv=3, nc=8)
+    args = (t["cv"], t["e_v"])
+    whole = oracle.chi0_bands(*args, t["cc"], t["e_c"], t["gw"], t["gc"], t["nd"])[0]
+    a = oracle.chi0_bands(*args, t["cc"][:3], t["e_c"][:3], t["gw"], t["gc"], t["nd"])[0]
+    b = oracle.chi0_bands(*args, t["cc"][3:], t["e_c"][3:], t["gw"], t["gc"], t["nd"])[0]
+    assert np.abs(whole - a - b).max() < 1e-15 * np.abs(whole).max() * 10
+    # chunk size of the internal loop does not matter
+    c = oracle.chi0_bands(*args, t["cc"], t["e_c"], t["gw"], t["gc"], t["nd"], c_chunk=1)[0]
+    assert np.abs(whole - c).max() < 1e-15 * np.abs(whole).max() * 10
+
+
+def test_chi0_trace_identity():
+    # Tr chi0 = sum_p w_p ||m_p||^2
+    t = tiny(nv=2, nc=4)
+    chi = oracle.chi0_bands(t["cv"], t["e_v"], t["cc"], t["e_c"], t["gw"], t["gc"], t["nd"])[0]
+    m = oracle.pair_density_direct(t["cv"], t["cc"], t["gw"], t["gc"])
+    w = t["e_v"][:, None] - t["e_c"][None]
+    assert np.isclose(np.trace(chi).real, ((np.abs(m) ** 2).sum(-1) / w).sum(), rtol=1e-13)
+
+
+# ---------------------------------------------------------------- grouping
+def test_grouping_one_band_per_window_reproduces_exact_sum():
+    t = tiny(nv=3, nc=7)
+    e0, de, nwin = 0.5, 0.1, 4
+    # 3 explicit bands below E_0, then exactly one band at each window midpoint
+    e_c = np.concatenate([[0.2, 0.3, 0.5], [e0 + (k + 0.5) * de for k in range(nwin)]])
+    col, e_col, n_col, n0 = oracle.group_windows(e_c, e0, de, nwin)
+    assert n0 == 3 and list(col) == list(range(7)) and np.all(n_col == 1.0)
+    assert np.all(e_col == e_c)
+    exact = oracle.chi0_bands(t["cv"], t["e_v"], t["cc"], e_c, t["gw"], t["gc"], t["nd"])[0]
+    grouped = oracle.chi0_grouped_static(t["cv"], t["e_v"], t["cc"], e_c, t["gw"], t["gc"], t["nd"], e0, de, nwin)
+    assert np.abs(grouped - exact).max() < 1e-14 * np.abs(exact).max()
+
+
+def test_grouping_counts_and_representatives():
+    r = np.random.default_rng(11)
+    e_c = r.uniform(0.1, 2.0, 500)
+    e0, de, nwin = 1.1, 0.09, 10   # top = 2.0
+    col, e_col, n_col, n0 = oracle.group_windows(e_c, e0, de, nwin)
+    assert n0 == int((e_c <= e0).sum())
+    assert list(col[:n0]) == [i for i in range(500) if e_c[i] <= e0]
+    assert n_col[n0:].sum() == 500 - n0
+    for j in range(n0, len(col)):
+        k = int(round((e_col[j] - e0) / de - 0.5))
+        lo, hi = e0 + k * de, e0 + (k + 1) * de
+        mem = [i for i in range(500) if lo < e_c[i] and (e_c[i] < hi or (k == nwin - 1 and e_c[i] <= hi))]
+        assert len(mem) == n_col[j]
+        d = [abs(e_c[i] - e_col[j]) for i in mem]
+        assert abs(e_c[col[j]] - e_col[j]) == min(d)
+    # no windows: explicit columns only; everything above the last window is rejected
+    col2, _, _, n02 = oracle.group_windows(e_c[e_c <= e0], e0, de, nwin)
+    assert n02 == len(col2)
+    with pytest.raises(ValueError):
+        oracle.group_windows(np.array([0.5, 2.5]), e0, de, nwin)
+
+
+def test_speedup_matches_printed_tables():
+    with open(os.path.join(HERE, "golden", "paper_tables.json")) as f:
+        tab = json.load(f)
+    t1 = tab["table1"]
+    for n, s in zip(t1["n0_plus_ne"], t1["speedup"]):
+        assert round(oracle.speedup_factor(t1["n_c"], n), 1) == s
+    t2 = tab["table2"]
+    for nc, n, s in zip(t2["n_c"], t2["n0_plus_ne"], t2["speedup"]):
+        assert round(oracle.speedup_factor(nc, n), 1) == s
+
+
+def test_free_electron_dos_counts_plane_waves():
+    # integral_0^E g = number of spin-degenerate plane-wave states with |G|^2/2 <= E
+    a = 40.0
+    b = 2 * math.pi / a
+    r = 22
+    n = np.arange(-r, r + 1)
+    n1, n2, n3 = np.meshgrid(n, n, n, indexing="ij")
+    kin = 0.5 * b * b * (n1 ** 2 + n2 ** 2 + n3 ** 2)
+    for e in (2.0, 3.0, 4.5):
+        count = 2 * int((kin <= e).sum())
+        es = np.linspace(0, e, 20001)
+        integ = np.trapezoid(oracle.free_electron_dos(es, a ** 3), es)
+        assert abs(integ - count) / count < 0.01
+        assert np.isclose(integ, a ** 3 * (2 * e) ** 1.5 / (3 * math.pi ** 2), rtol=1e-6)
+
+
+# ---------------------------------------------------------------- dielectric
+def test_eps_inv_routes_agree_and_properties():
+    t = tiny(nv=4, nc=9)
+    chi = oracle.chi0_bands(t["cv"], t["e_v"], t["cc"], t["e_c"], t["gw"], t["gc"], t["nd"])[0]
+    v = synth.coulomb(t["gc"], (0.01, 0, 0), t["cell"])
+    z = oracle.eps_inv(chi, v)
+    z2 = oracle.eps_inv_static_cholesky(chi, v)
+    assert np.abs(z - z2).max() < 1e-12 * np.abs(z).max()
+    eps = oracle.eps_matrix(chi, v)
+    assert np.abs(eps @ z - np.eye(len(v))).max() < 1e-12
+    assert np.abs(np.diagonal(z).imag).max() < 1e-14
+    s = np.sqrt(v)
+    zt = z * s[None] / s[:, None]          # symmetrised inverse (eps~)^-1
+    ev = np.linalg.eigvalsh(0.5 * (zt + zt.conj().T))
+    assert ev.min() > 0 and ev.max() <= 1 + 1e-12
+    assert np.abs(oracle.eps_inv(np.zeros_like(chi), v) - np.eye(len(v))).max() == 0
+    assert oracle.eps_inf(z) == pytest.approx(1.0)       # head row/column of chi0 vanish
+
+
+# ---------------------------------------------------------------- gradients
+def _loss_static(t, v, head, e_v, e_c, n_c):
+    chi = oracle.chi0_bands(t["cv"], e_v, t["cc"], e_c, t["gw"], t["gc"], t["nd"], n_col=n_c)[0]
+    return og.head_block_loss(oracle.eps_inv(chi, v), head)
+
+
+def test_gradients_static_match_finite_differences():
+    t = tiny(nv=3, nc=5)
+    v = synth.coulomb(t["gc"], (0.01, 0, 0), t["cell"])
+    head = synth.loss_head_block(t["gc"])
+    e_v, e_c, n_c = t["e_v"], t["e_c"], np.array([1.0, 2.0, 1.5, 1.0, 0.7])
+    chi = oracle.chi0_bands(t["cv"], e_v, t["cc"], e_c, t["gw"], t["gc"], t["nd"], n_col=n_c)[0]
+    z = oracle.eps_inv(chi, v)
+    gchi = og.grad_eps_inv(z, v, og.head_block_loss_grad(len(v), head))
+    gv, gc, gn = og.grad_chi0_energies(t["cv"], e_v, t["cc"], e_c, t["gw"], t["gc"], t["nd"], gchi[None],
+                                       n_col=n_c)
+    h = 1e-5
+    for arr, g, name in ((e_v, gv, "ev"), (e_c, gc, "ec"), (n_c, gn, "n")):
+        for i in range(len(arr)):
+            p, m = arr.copy(), arr.copy()
+            p[i] += h
+            m[i] -= h
+            kw = dict(e_v=e_v, e_c=e_c, n_c=n_c)
+            key = {"ev": "e_v", "ec": "e_c", "n": "n_c"}[name]
+            lp = _loss_static(t, v, head, **{**kw, key: p})
+            lm = _loss_static(t, v, head, **{**kw, key: m})
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])), (name, i, fd, g[i])
+
+
+def test_gradients_dynamic_match_finite_differences():
+    t = tiny(nv=2, nc=4)
+    r = np.random.default_rng(5)
+    ng = len(t["gc"])
+    bmat = r.standard_normal((2, ng, ng)) + 1j * r.standard_normal((2, ng, ng))
+    om, d = [0.05, 0.4], 0.01
+
+    def loss(e_v, e_c):
+        chi = oracle.chi0_bands(t["cv"], e_v, t["cc"], e_c, t["gw"], t["gc"], t["nd"], omegas=om, delta=d)
+        return float(np.real(np.sum(np.conj(bmat) * chi)))
+
+    gv, gc, _ = og.grad_chi0_energies(t["cv"], t["e_v"], t["cc"], t["e_c"], t["gw"], t["gc"], t["nd"], bmat,
+                                      omegas=om, delta=d)
+    h = 1e-6
+    for i in range(2):
+        p, m = t["e_v"].copy(), t["e_v"].copy()
+        p[i] += h
+        m[i] -= h
+        fd = (loss(p, t["e_c"]) - loss(m, t["e_c"])) / (2 * h)
+        assert abs(fd - gv[i]) <= 1e-6 * max(1.0, abs(gv[i]))
+    for i in range(4):
+        p, m = t["e_c"].copy(), t["e_c"].copy()
+        p[i] += h
+        m[i] -= h
+        fd = (loss(t["e_v"], p) - loss(t["e_v"], m)) / (2 * h)
+        assert abs(fd - gc[i]) <= 1e-6 * max(1.0, abs(gc[i]))
+
+
+def test_grad_eps_inv_general_matches_finite_differences():
+    r = np.random.default_rng(8)
+    ng = 6
+    chi = 0.05 * (r.standard_normal((ng, ng)) + 1j * r.standard_normal((ng, ng)))
+    v = r.uniform(0.5, 2.0, ng)
+    bmat = r.standard_normal((ng, ng)) + 1j * r.standard_normal((ng, ng))
+
+    def loss(c):
+        return float(np.real(np.sum(np.conj(bmat) * oracle.eps_inv(c, v))))
+
+    g = og.grad_eps_inv(oracle.eps_inv(chi, v), v, bmat)
+    h = 1e-6
+    for (i, j) in ((0, 0), (1, 4), (5, 2)):
+        for unit, part in ((1.0, np.real), (1j, np.imag)):
+            p, m = chi.copy(), chi.copy()
+            p[i, j] += unit * h
+            m[i, j] -= unit * h
+            fd = (loss(p) - loss(m)) / (2 * h)
+            assert abs(fd - part(g[i, j])) < 1e-7
