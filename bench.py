@@ -1,0 +1,180 @@
+#!/usr/bin/env python3
+"""Benchmark of the chi0 band sum on one MI355X.
+
+Workload: the 64-atom-MgO-shaped static polarizability -- 72^3 FFT grid, 24,405-plane-wave
+wavefunction sphere, 128 valence x 4,000 conduction bands (512,000 band pairs), 2,000
+G-vectors in the dielectric sphere, q = (0.01, 0, 0), exact band sum (Eq. (chi0) at w = 0).
+Seeded synthetic inputs (orthonormal random coefficients, sqrt(E) conduction spectrum)
+stand in for the paper's MgO wavefunctions.
+
+One step = one gw_chi0_build: band transforms, pair transforms, weights and the
+contraction, with every input already in HBM.  The float64 path is the headline
+(`value`); the float32 path is timed the same way and its error against float64 is
+reported.  A bounded sample of the same workload runs through the CPU oracle as a
+reported baseline.  Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "chi0 build TFLOP/s + band-pairs/s, FP64 vs mixed vs oracle, err vs FP64"
+PEAK = {"fp64_vec": 78.6, "fp64_mfma": 78.6, "fp32_mfma": 157.3, "fp32_vec_nopk": 78.6, "bf16_mfma": 2500.0,
+        "hbm": 8000.0}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def flops_model(nd, k, ng, npair, nband):
+    """Algorithmic flop counts: pruned forward transform per pair (three passes over
+    N, N K/N_d and N K^2/N_d^2 points at 5 n log2 n), the product (6 N), the band
+    transforms (5 N log2 N each) and the Hermitian contraction (4 NG^2 per pair)."""
+    n = nd ** 3
+    lg = math.log2(nd)
+    planes = 5.0 * n * lg * (1.0 + k / nd) + 6.0 * n
+    finish = 5.0 * n * lg * (k * k / nd ** 2)
+    band = 5.0 * n * math.log2(n)
+    contract = 4.0 * ng * ng
+    return {"planes": planes * npair, "finish": finish * npair, "band": band * nband, "contract": contract * npair,
+            "total": (planes + finish + contract) * npair + band * nband}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--modes", default="fp64,fp32")
+    ap.add_argument("--cpu-sample", type=int, default=8, help="valence bands in the oracle sample (0 = skip)")
+    ap.add_argument("--cpu-cols", type=int, default=64)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the band sum shards over "
+                                   "pairs, see the design notes)"}))
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_1601_06767_amd as p
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    cfg = synth.config(1)
+    nd = cfg.nd
+    gw = synth.wf_sphere(nd)
+    gc = synth.chi_sphere(cfg.ng[0], cfg.qs[0], cfg.cell)
+    t0 = time.time()
+    bands = synth.make_bands(cfg, gvec_wf=gw, device="cuda")
+    log(f"inputs: npw={len(gw)} ng={len(gc)} nv={cfg.nv} nc={cfg.nc} generated in {time.time() - t0:.1f}s")
+
+    ctx = p.gw_ctx_create(0)
+    geom = p.gw_geom_create(ctx, (nd,) * 3, gw, gc)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    cv, ev, cc, ec = t(bands.coef_v), t(bands.e_v), t(bands.coef_c), t(bands.e_c)
+    prob = p.make_problem(geom, cv, ev, cc, ec)
+    ng = len(gc)
+    k = 2 * int(np.abs(gc).max()) + 1
+    npair = cfg.nv * cfg.nc
+    fl = flops_model(nd, k, ng, npair, cfg.nv + cfg.nc)
+    modes = [m for m in args.modes.split(",") if m]
+    wsb = max(p.gw_chi0_workspace_size(ctx, [prob], 1, p.PRECISIONS[m]) for m in modes)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    log(f"workspace {wsb / 2**30:.2f} GiB")
+    results = {}
+    chis = {}
+    stream = torch.cuda.current_stream()
+    for m in modes:
+        out = torch.empty(ng * ng, dtype=torch.complex128, device=dev)
+        run = lambda: p.gw_chi0_build(ctx, [prob], [ng], [0.0], 0.0, p.PRECISIONS[m], workspace=ws, out=out)
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        p.gw_ctx_stage_times(ctx, reset=True)
+        p.gw_ctx_set_timing(ctx, True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        tw = time.perf_counter()
+        e0.record(stream)
+        for i in range(args.steps):
+            run()
+            log(f"{m}: step {i + 1}/{args.steps} enqueued")
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - tw
+        p.gw_ctx_set_timing(ctx, False)
+        stages = p.gw_ctx_stage_times(ctx, reset=True)
+        ms = e0.elapsed_time(e1) / args.steps
+        chis[m] = out.view(ng, ng).cpu().numpy()
+        results[m] = {"ms_per_step": ms, "wall_s": wall, "tflops": fl["total"] / (ms * 1e-3) / 1e12,
+                      "band_pairs_per_s": npair / (ms * 1e-3),
+                      "stages_ms_per_step": {s: v[0] / args.steps for s, v in stages.items() if v[1]},
+                      "stage_launches_per_step": {s: v[1] / args.steps for s, v in stages.items() if v[1]}}
+        log(f"{m}: {ms:.1f} ms/step, {results[m]['tflops']:.2f} TFLOP/s, stages {results[m]['stages_ms_per_step']}")
+    if "fp64" in chis:
+        ref = chis["fp64"]
+        nrm = np.linalg.norm(ref)
+        for m in chis:
+            results[m]["err_vs_fp64"] = float(np.linalg.norm(chis[m] - ref) / nrm)
+        results["fp64"]["hermitian_residual"] = float(np.abs(ref - ref.conj().T).max() / np.abs(ref).max())
+
+    head = modes[0]
+    hr = results[head]
+    # dominant kernel of the headline mode and its roofline
+    st = hr["stages_ms_per_step"]
+    dom = max(st, key=st.get)
+    launches = hr["stage_launches_per_step"][dom]
+    avg_ms = st[dom] / launches
+    if dom == "contract":
+        bound, peak = "mfma", (PEAK["fp64_mfma"] if head == "fp64" else PEAK["fp32_mfma"])
+        work = fl["contract"] / launches
+    else:
+        bound, peak = "alu", PEAK["fp64_vec"]
+        work = fl[dom if dom in fl else "planes"] / launches
+    achieved = work / (avg_ms * 1e-3) / 1e12
+    roofline = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None, "avg_launch_ms": avg_ms,
+                "algorithmic_work_per_launch": work}
+
+    cpu = None
+    if args.cpu_sample > 0:
+        import oracle
+        cores = len(os.sched_getaffinity(0))
+        vs = np.linspace(0, cfg.nv - 1, args.cpu_sample).astype(int)
+        cs = np.arange(args.cpu_cols) * (cfg.nc // args.cpu_cols)
+        t1 = time.perf_counter()
+        ref = oracle.chi0_bands(bands.coef_v[vs], bands.e_v[vs], bands.coef_c[cs], bands.e_c[cs], gw, gc,
+                                (nd,) * 3)[0]
+        dt = time.perf_counter() - t1
+        sp = len(vs) * len(cs)
+        fs = flops_model(nd, k, ng, sp, len(vs) + len(cs))
+        # the same sample through the GPU path
+        sub = p.make_problem(geom, t(bands.coef_v[vs]), t(bands.e_v[vs]), t(bands.coef_c[cs]), t(bands.e_c[cs]))
+        gchi = p.gw_chi0_build(ctx, [sub], [ng], [0.0], 0.0, p.GW_FP64)[0][0].cpu().numpy()
+        cpu = {"value": fs["total"] / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+               "band_pairs_per_s": sp / dt, "seconds": dt,
+               "sample": f"{len(vs)} valence x {len(cs)} conduction bands ({sp} pairs) of the same workload, "
+                         f"full grid and dielectric sphere, scipy.fft workers={cores}",
+               "gpu_fp64_err_on_sample": float(np.linalg.norm(gchi - ref) / np.linalg.norm(ref))}
+        log(f"oracle sample: {dt:.1f}s, {cpu['value'] * 1e3:.3f} GFLOP/s")
+
+    line = {"metric": METRIC, "value": hr["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": hr["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64" if head == "fp64" else "f32", "data": "synthetic",
+            "config": {"workload": cfg.name, "grid": nd, "npw": len(gw), "nv": cfg.nv, "ncol": cfg.nc, "ng": ng,
+                       "pairs": npair, "q": list(cfg.qs[0]), "omega": 0.0},
+            "band_pairs_per_s": hr["band_pairs_per_s"], "modes": results, "roofline": roofline,
+            "cpu_baseline": cpu}
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

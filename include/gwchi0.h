@@ -1,0 +1,198 @@
+/*
+ * gwchi0 -- RPA polarizability band sum on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the library libgwchi0.so.  It computes the independent-particle
+ * polarizability of Gao, Xia, Gao & Zhang, "Towards Fully Converged GW
+ * Calculations for Large Systems" (arXiv:1601.06767):
+ *
+ *   Eq. (chi0):  chi0_GG'(q,w) = 1/2 sum_{c,v} M_vc(G) M*_vc(G')
+ *                  [1/(E_v - E_c - w + i delta) + 1/(E_v - E_c + w + i delta)]
+ *   with the matrix element M_vc(G) = <v,k+q| exp(i(q+G).r) |c,k>, formed here as
+ *   M_vc(G) = (1/N) sum_r conj(u_v(r)) u_c(r) exp(iG.r) on an N-point FFT grid,
+ *
+ * the grouped form of Eqs. (chi02) and (energyintegration) (each conduction
+ * "column" carries an energy and a multiplicity, so an energy window's
+ * representative state with weight g(E_i) dE_i is just another column), and the
+ * RPA dielectric matrix eps = 1 - v chi0 with its inverse (the relation stated
+ * before Eq. (chi0); Table 3 uses [eps^-1]_00).
+ *
+ * Conventions shared by every entry point
+ *  - Energies and frequencies are in Hartree; all inputs are float64 / complex128
+ *    (complex = two interleaved doubles, re then im).
+ *  - "device" pointers are HIP device memory on the context's device, owned by the
+ *    caller; "host" pointers are ordinary host memory, read before the call returns.
+ *  - Work is enqueued on the context's stream; calls return after enqueue.  A kernel
+ *    fault is reported as GW_EDEVICE by a later call or by the caller's sync.
+ *  - Every function returns a gw_status; on failure the context keeps a message,
+ *    readable with gw_last_error.  Nothing throws across the ABI.
+ *  - One context per stream.  A context is not re-entrant: calls on one context must
+ *    not overlap from several host threads.
+ */
+#ifndef GWCHI0_H
+#define GWCHI0_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GW_OK = 0,
+  GW_EINVAL = -1,        /* bad argument: shapes, ranges, aliasing, workspace too small */
+  GW_ENOMEM = -2,        /* a library-internal allocation failed (set-up calls only) */
+  GW_EDEVICE = -3,       /* a HIP runtime call failed */
+  GW_ESINGULAR = -4,     /* a pivot of the dielectric matrix was zero or non-finite */
+  GW_EUNSUPPORTED = -5   /* a size or mode with no compiled kernel */
+} gw_status;
+
+/* Arithmetic of the pair transform and of the contraction.  The band energies,
+ * the weights of Eq. (chi0), the final accumulation and eps^-1 are float64 in
+ * every mode.
+ *   GW_FP64   wavefunctions, pair transforms and contraction in float64.
+ *   GW_FP32   wavefunctions and pair transforms in float32; contraction on float32
+ *             MFMA, accumulated in float32 within a chunk of band pairs and in
+ *             float64 across chunks.
+ *   GW_BF16X3 as GW_FP32, but the contraction splits each float32 operand into a
+ *             bfloat16 high and low part and sums hi*hi + hi*lo + lo*hi on bf16 MFMA
+ *             with float32 accumulation. */
+typedef enum { GW_FP64 = 0, GW_FP32 = 1, GW_BF16X3 = 2 } gw_precision;
+
+typedef struct gw_ctx gw_ctx;
+typedef struct gw_geom gw_geom;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *out is set on success. */
+gw_status gw_ctx_create(int device, void* hip_stream, gw_ctx** out);
+gw_status gw_ctx_destroy(gw_ctx* ctx);
+/* Message of the last failing call on ctx ("" if none).  With ctx == NULL: the
+ * message of the last failing gw_ctx_create in this process. */
+const char* gw_last_error(const gw_ctx* ctx);
+/* Library version string, e.g. "gwchi0 0.1 gfx950". */
+const char* gw_version(void);
+
+/* Stage timers (diagnostics, not part of any result).  With enable != 0, later calls
+ * record a HIP event pair on the context's stream around each group of launches and
+ * accumulate the device time per stage:
+ *   0 band -> real-space transforms   1 pair planes (product, x3 and x2 transforms)
+ *   2 pair finish (x1 transform, sphere gather)   3 weights   4 contraction
+ *   5 finalize (split sum, Hermitian mirror)   6 eps^-1   7 backward
+ * gw_ctx_stage_times waits for the recorded events and copies 8 accumulated
+ * milliseconds and launch-group counts; reset != 0 clears the accumulators. */
+gw_status gw_ctx_set_timing(gw_ctx* ctx, int enable);
+gw_status gw_ctx_stage_times(gw_ctx* ctx, double* ms, long long* counts, int reset);
+
+/* ---------------------------------------------------------------- geometry */
+
+/* Plane-wave geometry of one q-point (set-up; synchronises the stream).
+ *   n_fft[3]   FFT grid N1, N2, N3 (host).  The kernels need N1 = N2 = N3 in
+ *              {24, 32, 48, 64, 72, 96, 128}; other grids give GW_EUNSUPPORTED.
+ *   npw, gvec_wf   wavefunction sphere: npw x 3 int32 Miller indices (host), the
+ *              order in which coefficient rows are stored.
+ *   ng, gvec_chi   dielectric sphere: ng x 3 int32 Miller indices (host), the row and
+ *              column order of chi0 and eps^-1.
+ * Checks: indices distinct modulo the grid, and the alias-free bound
+ * 2 max|n_wf,i| + max|n_chi,i| < N_i per axis, which makes the grid evaluation of
+ * M_vc(G) equal to the plane-wave convolution sum_G' conj(c_v(G'+G)) c_c(G')
+ * (reading of Eq. (chi0)'s matrix element, whose exponent is printed without ".r").
+ * The geometry keeps its own device copies of the index tables. */
+gw_status gw_geom_create(gw_ctx* ctx, const int n_fft[3], int npw, const int32_t* gvec_wf, int ng,
+                         const int32_t* gvec_chi, gw_geom** out);
+gw_status gw_geom_destroy(gw_geom* geom);
+
+/* ---------------------------------------------------------------- chi0 */
+
+/* One q-point's band data (all arrays device memory, read-only).
+ *   nv, coef_v, e_v       valence states at k+q: nv x npw complex128 row-major, energies nv.
+ *   nband, coef_c         conduction states at k: nband x npw complex128 row-major.
+ *   ncol, col_band        the columns summed over: column j uses coefficient row
+ *                         col_band[j] (int32, NULL = identity, then ncol <= nband).
+ *   e_col, n_col          column energy E_c (a band energy, or a window energy E_i) and
+ *                         multiplicity (1 for a band, g(E_i) dE_i for a window);
+ *                         n_col NULL = all 1.  Eq. (energyintegration) is then the
+ *                         plain column sum.
+ * Values are not inspected on the host; a zero denominator E_v - E_col with
+ * omega = delta = 0 gives non-finite output. */
+typedef struct {
+  const gw_geom* geom;
+  int nv;
+  const void* coef_v;
+  const double* e_v;
+  int nband;
+  const void* coef_c;
+  int ncol;
+  const int32_t* col_band;
+  const double* e_col;
+  const double* n_col;
+} gw_chi0_problem;
+
+/* Workspace bytes gw_chi0_build / gw_chi0_backward need for these problems. */
+gw_status gw_chi0_workspace_size(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega,
+                                 gw_precision prec, size_t* bytes);
+
+/* chi0 of Eq. (chi0) for nprob q-points and nomega real frequencies.
+ *   omega   host, nomega doubles (read before the call returns).  omega[i] == 0 with
+ *           delta == 0 is the static case of Eq. (chi02): a Hermitian, negative
+ *           semidefinite matrix.  With delta == 0 every chi0(omega) is Hermitian.
+ *   delta   broadening, >= 0 (both terms carry +i delta, as printed).
+ *   workspace, ws_bytes   device scratch of at least gw_chi0_workspace_size bytes.
+ *   chi0    device output, complex128: for each problem p in order, nomega blocks of
+ *           ng_p x ng_p row-major, [p][omega][G][G'].
+ * GW_EINVAL: nprob < 1, nomega < 1, delta < 0, nv < 1, ncol < 1, NULL data pointers,
+ * ncol > nband without col_band, workspace too small. */
+gw_status gw_chi0_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, const double* omega,
+                        double delta, gw_precision prec, void* workspace, size_t ws_bytes, void* chi0);
+
+/* Workspace bytes for gw_pair_density with an nvs x ncs block. */
+gw_status gw_pair_density_workspace_size(gw_ctx* ctx, const gw_chi0_problem* prob, int nvs, int ncs,
+                                         gw_precision prec, size_t* bytes);
+
+/* Pair densities M_vc(G) of Eq. (chi0) for one problem and a block of pairs
+ * v in [v0, v0+nvs), columns j in [c0, c0+ncs):
+ *   m_out   device complex128, (nvs * ncs) x ng row-major, pair index (v - v0) * ncs + (j - c0).
+ * Uses the same kernels as gw_chi0_build; nvs * ncs must fit one pass (GW_EINVAL otherwise,
+ * about 32768 pairs). */
+gw_status gw_pair_density(gw_ctx* ctx, const gw_chi0_problem* prob, int v0, int nvs, int c0, int ncs,
+                          gw_precision prec, void* workspace, size_t ws_bytes, void* m_out);
+
+/* ---------------------------------------------------------------- dielectric */
+
+/* eps^-1 = (I - diag(v) chi0)^-1 for nbatch matrices, in float64 (RPA relation before
+ * Eq. (chi0); Table 3's eps_inf = 1/[eps^-1]_00).
+ *   vcoul     device, nbatch x ng doubles, v(q+G) including its normalisation.
+ *   chi0      device complex128, nbatch x ng x ng row-major.
+ *   eps_inv   device complex128 output, same shape; may not alias chi0.
+ *   workspace device scratch of at least gw_eps_inv_workspace_size bytes.
+ * Gauss-Jordan elimination with partial pivoting on the stream.  GW_ESINGULAR is
+ * reported by gw_eps_inv_status after the stream has run. */
+gw_status gw_eps_inv_workspace_size(gw_ctx* ctx, int ng, int nbatch, size_t* bytes);
+gw_status gw_eps_inv(gw_ctx* ctx, int ng, int nbatch, const double* vcoul, const void* chi0, void* workspace,
+                     size_t ws_bytes, void* eps_inv);
+/* Synchronises the stream; GW_ESINGULAR if the last gw_eps_inv met a zero pivot. */
+gw_status gw_eps_inv_status(gw_ctx* ctx);
+
+/* ---------------------------------------------------------------- grouping */
+
+/* Columns of Eq. (energyintegration) from a conduction spectrum (host arrays).
+ *   e_band    nband band energies (any order).
+ *   e0, de, nwin   windows [e0 + i de, e0 + (i+1) de), i < nwin, the last one closed
+ *             at e0 + nwin de.  Bands with E <= e0 are explicit columns (index order,
+ *             multiplicity 1).
+ *   mode      0 = count (multiplicity = number of bands in the window),
+ *             1 = dos (multiplicity = dos_a * sqrt(E_i - dos_v0) * de, the weight
+ *             g(E_i) dE_i with g of the form printed after Eq. (chi02)).
+ * Each non-empty window gives one column: the band nearest its midpoint E_i =
+ * e0 + (i + 1/2) de (lower index on a tie), energy E_i.
+ * Outputs (host, capacity >= nband + nwin): col_band, e_col, n_col; *ncol_out columns,
+ * *n0_out explicit ones.  GW_EINVAL if a band lies above the last window. */
+gw_status gw_group_windows(int nband, const double* e_band, double e0, double de, int nwin, int mode, double dos_a,
+                           double dos_v0, int32_t* col_band, double* e_col, double* n_col, int* ncol_out,
+                           int* n0_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GWCHI0_H */

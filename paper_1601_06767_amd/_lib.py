@@ -1,0 +1,247 @@
+"""ctypes binding of libgwchi0.so (argument marshalling only).
+
+The functions keep the names of the C ABI in include/gwchi0.h and take torch
+tensors for device buffers; every computation runs in the library's HIP kernels.
+The library must have been built (``python paper_1601_06767_amd/build.py``);
+importing this module without it raises ImportError -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgwchi0.so")
+
+GW_OK, GW_EINVAL, GW_ENOMEM, GW_EDEVICE, GW_ESINGULAR, GW_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+GW_FP64, GW_FP32, GW_BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": GW_FP64, "fp32": GW_FP32, "bf16x3": GW_BF16X3}
+STATUS_NAMES = {0: "GW_OK", -1: "GW_EINVAL", -2: "GW_ENOMEM", -3: "GW_EDEVICE", -4: "GW_ESINGULAR",
+                -5: "GW_EUNSUPPORTED"}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1601_06767_amd/build.py`")
+lib = C.CDLL(LIB_PATH)
+
+vp = C.c_void_p
+i32p = C.POINTER(C.c_int32)
+dp = C.POINTER(C.c_double)
+
+
+class gw_chi0_problem(C.Structure):
+    _fields_ = [("geom", vp), ("nv", C.c_int), ("coef_v", vp), ("e_v", vp), ("nband", C.c_int), ("coef_c", vp),
+                ("ncol", C.c_int), ("col_band", vp), ("e_col", vp), ("n_col", vp)]
+
+
+def _sig(name, res, args):
+    f = getattr(lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_sig("gw_version", C.c_char_p, [])
+_sig("gw_ctx_create", C.c_int, [C.c_int, vp, C.POINTER(vp)])
+_sig("gw_ctx_destroy", C.c_int, [vp])
+_sig("gw_last_error", C.c_char_p, [vp])
+_sig("gw_geom_create", C.c_int, [vp, C.POINTER(C.c_int), C.c_int, i32p, C.c_int, i32p, C.POINTER(vp)])
+_sig("gw_geom_destroy", C.c_int, [vp])
+_sig("gw_chi0_workspace_size", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, C.c_int,
+                                         C.POINTER(C.c_size_t)])
+_sig("gw_chi0_build", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, dp, C.c_double, C.c_int, vp,
+                                C.c_size_t, vp])
+_sig("gw_pair_density_workspace_size", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, C.c_int,
+                                                 C.POINTER(C.c_size_t)])
+_sig("gw_pair_density", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                  vp, C.c_size_t, vp])
+_sig("gw_eps_inv_workspace_size", C.c_int, [vp, C.c_int, C.c_int, C.POINTER(C.c_size_t)])
+_sig("gw_eps_inv", C.c_int, [vp, C.c_int, C.c_int, vp, vp, vp, C.c_size_t, vp])
+_sig("gw_eps_inv_status", C.c_int, [vp])
+_sig("gw_group_windows", C.c_int, [C.c_int, dp, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double, C.c_double,
+                                   i32p, dp, dp, C.POINTER(C.c_int), C.POINTER(C.c_int)])
+
+_sig("gw_ctx_set_timing", C.c_int, [vp, C.c_int])
+_sig("gw_ctx_stage_times", C.c_int, [vp, dp, C.POINTER(C.c_longlong), C.c_int])
+
+STAGES = ["band", "planes", "finish", "weights", "contract", "finalize", "eps_inv", "backward"]
+
+EXPORTED = ["gw_ctx_set_timing", "gw_ctx_stage_times",
+            "gw_version", "gw_ctx_create", "gw_ctx_destroy", "gw_last_error", "gw_geom_create", "gw_geom_destroy",
+            "gw_chi0_workspace_size", "gw_chi0_build", "gw_pair_density_workspace_size", "gw_pair_density",
+            "gw_eps_inv_workspace_size", "gw_eps_inv", "gw_eps_inv_status", "gw_group_windows"]
+
+
+class GwError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(status: int, ctx=None):
+    if status != GW_OK:
+        m = lib.gw_last_error(ctx)
+        raise GwError(status, m.decode() if m else "")
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def gw_version() -> str:
+    return lib.gw_version().decode()
+
+
+# ---------------------------------------------------------------- context / geometry
+def gw_ctx_create(device: int = 0, stream=None):
+    """Context on `device` enqueueing on `stream` (a torch.cuda.Stream; default: torch's current stream)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    out = vp()
+    _check(lib.gw_ctx_create(device, vp(stream.cuda_stream), C.byref(out)), None)
+    return out
+
+
+def gw_ctx_destroy(ctx) -> None:
+    _check(lib.gw_ctx_destroy(ctx))
+
+
+def gw_last_error(ctx=None) -> str:
+    return lib.gw_last_error(ctx).decode()
+
+
+def gw_ctx_set_timing(ctx, enable: bool) -> None:
+    _check(lib.gw_ctx_set_timing(ctx, 1 if enable else 0), ctx)
+
+
+def gw_ctx_stage_times(ctx, reset: bool = False) -> dict:
+    """{stage: (milliseconds, launch groups)} accumulated while timing was on."""
+    ms = (C.c_double * 8)()
+    n = (C.c_longlong * 8)()
+    _check(lib.gw_ctx_stage_times(ctx, ms, n, 1 if reset else 0), ctx)
+    return {s: (ms[i], n[i]) for i, s in enumerate(STAGES)}
+
+
+def gw_geom_create(ctx, n_fft: Sequence[int], gvec_wf: np.ndarray, gvec_chi: np.ndarray):
+    gw_ = np.ascontiguousarray(gvec_wf, dtype=np.int32)
+    gc = np.ascontiguousarray(gvec_chi, dtype=np.int32)
+    nf = (C.c_int * 3)(*[int(x) for x in n_fft])
+    out = vp()
+    _check(lib.gw_geom_create(ctx, nf, gw_.shape[0], gw_.ctypes.data_as(i32p), gc.shape[0], gc.ctypes.data_as(i32p),
+                              C.byref(out)), ctx)
+    return out
+
+
+def gw_geom_destroy(geom) -> None:
+    _check(lib.gw_geom_destroy(geom))
+
+
+# ---------------------------------------------------------------- problems
+def make_problem(geom, coef_v, e_v, coef_c, e_col, n_col=None, col_band=None) -> gw_chi0_problem:
+    """Problem record over torch device tensors (complex128 coefficients, float64 energies, int32 col_band)."""
+    for t in (coef_v, coef_c):
+        assert t.dtype.is_complex and t.element_size() == 16 and t.is_contiguous()
+    return gw_chi0_problem(geom, coef_v.shape[0], _ptr(coef_v), _ptr(e_v), coef_c.shape[0], _ptr(coef_c),
+                           e_col.shape[0], _ptr(col_band), _ptr(e_col), _ptr(n_col))
+
+
+def _probs(problems) -> "C.Array":
+    if isinstance(problems, gw_chi0_problem):
+        problems = [problems]
+    arr = (gw_chi0_problem * len(problems))(*problems)
+    return arr
+
+
+def gw_chi0_workspace_size(ctx, problems, nomega: int, prec: int) -> int:
+    arr = _probs(problems)
+    n = C.c_size_t()
+    _check(lib.gw_chi0_workspace_size(ctx, arr, len(arr), nomega, prec, C.byref(n)), ctx)
+    return n.value
+
+
+def gw_chi0_build(ctx, problems, ngs: Sequence[int], omegas: Sequence[float], delta: float, prec: int,
+                  workspace=None, out=None):
+    """chi0 for each problem: returns a list of (nomega, ng, ng) complex128 tensors (views of one buffer)."""
+    import torch
+    arr = _probs(problems)
+    om = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64))
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if workspace is None:
+        workspace = torch.empty(gw_chi0_workspace_size(ctx, arr, len(om), prec), dtype=torch.uint8, device=dev)
+    total = sum(len(om) * g * g for g in ngs)
+    if out is None:
+        out = torch.empty(total, dtype=torch.complex128, device=dev)
+    _check(lib.gw_chi0_build(ctx, arr, len(arr), len(om), om.ctypes.data_as(dp), float(delta), prec,
+                             _ptr(workspace), workspace.numel(), _ptr(out)), ctx)
+    res, o = [], 0
+    for g in ngs:
+        res.append(out[o: o + len(om) * g * g].view(len(om), g, g))
+        o += len(om) * g * g
+    return res
+
+
+def gw_pair_density_workspace_size(ctx, problem, nvs: int, ncs: int, prec: int) -> int:
+    n = C.c_size_t()
+    _check(lib.gw_pair_density_workspace_size(ctx, C.byref(problem), nvs, ncs, prec, C.byref(n)), ctx)
+    return n.value
+
+
+def gw_pair_density(ctx, problem, v0: int, nvs: int, c0: int, ncs: int, ng: int, prec: int, workspace=None):
+    """M_vc(G) for v in [v0, v0+nvs), columns [c0, c0+ncs): (nvs, ncs, ng) complex128 tensor."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if workspace is None:
+        workspace = torch.empty(gw_pair_density_workspace_size(ctx, problem, nvs, ncs, prec), dtype=torch.uint8,
+                                device=dev)
+    out = torch.empty((nvs, ncs, ng), dtype=torch.complex128, device=dev)
+    _check(lib.gw_pair_density(ctx, C.byref(problem), v0, nvs, c0, ncs, prec, _ptr(workspace), workspace.numel(),
+                               _ptr(out)), ctx)
+    return out
+
+
+# ---------------------------------------------------------------- dielectric
+def gw_eps_inv_workspace_size(ctx, ng: int, nbatch: int) -> int:
+    n = C.c_size_t()
+    _check(lib.gw_eps_inv_workspace_size(ctx, ng, nbatch, C.byref(n)), ctx)
+    return n.value
+
+
+def gw_eps_inv(ctx, vcoul, chi0, workspace=None, out=None):
+    """(I - diag(v) chi0)^-1 for chi0 of shape (nbatch, ng, ng) (or (ng, ng)), vcoul (nbatch, ng) or (ng,)."""
+    import torch
+    squeeze = chi0.dim() == 2
+    c = chi0.reshape(-1, chi0.shape[-1], chi0.shape[-1]).contiguous()
+    nb, ng = c.shape[0], c.shape[-1]
+    v = vcoul.reshape(-1, ng).expand(nb, ng).contiguous()
+    if workspace is None:
+        workspace = torch.empty(max(1, gw_eps_inv_workspace_size(ctx, ng, nb)),
+                                dtype=torch.uint8, device=c.device)
+    if out is None:
+        out = torch.empty_like(c)
+    _check(lib.gw_eps_inv(ctx, ng, nb, _ptr(v), _ptr(c), _ptr(workspace), workspace.numel(), _ptr(out)), ctx)
+    return out[0] if squeeze else out
+
+
+def gw_eps_inv_status(ctx) -> None:
+    _check(lib.gw_eps_inv_status(ctx), ctx)
+
+
+# ---------------------------------------------------------------- grouping (host)
+def gw_group_windows(e_band: np.ndarray, e0: float, de: float, nwin: int, mode: int = 0, dos_a: float = 0.0,
+                     dos_v0: float = 0.0):
+    """Columns of Eq. (energyintegration): (col_band int32, e_col, n_col, n0) as numpy arrays."""
+    e = np.ascontiguousarray(e_band, dtype=np.float64)
+    cap = len(e) + nwin
+    col = np.zeros(cap, dtype=np.int32)
+    ec = np.zeros(cap)
+    nc = np.zeros(cap)
+    ncol, n0 = C.c_int(), C.c_int()
+    st = lib.gw_group_windows(len(e), e.ctypes.data_as(dp), e0, de, nwin, mode, dos_a, dos_v0, col.ctypes.data_as(i32p),
+                              ec.ctypes.data_as(dp), nc.ctypes.data_as(dp), C.byref(ncol), C.byref(n0))
+    if st != GW_OK:
+        raise GwError(st, "gw_group_windows: invalid arguments or a band above the last window")
+    k = ncol.value
+    return col[:k].copy(), ec[:k].copy(), nc[:k].copy(), n0.value

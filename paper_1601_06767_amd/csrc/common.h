@@ -1,0 +1,135 @@
+// Device helpers shared by the gwchi0 kernels: complex arithmetic on HIP vector
+// types, unit roots exp(+2 pi i m / R) as compile-time constants, and short
+// unrolled DFTs of the sizes the pruned transforms are built from.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace gw {
+
+template <typename T> struct cx_t;
+template <> struct cx_t<double> { using type = double2; };
+template <> struct cx_t<float> { using type = float2; };
+template <typename T> using cx = typename cx_t<T>::type;
+
+template <typename V> __device__ __forceinline__ V cadd(V a, V b) { return V{a.x + b.x, a.y + b.y}; }
+template <typename V> __device__ __forceinline__ V csub(V a, V b) { return V{a.x - b.x, a.y - b.y}; }
+template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
+  return V{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// conj(a) * b
+template <typename V> __device__ __forceinline__ V cmulc(V a, V b) {
+  return V{a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+}
+// acc += a * b
+template <typename V> __device__ __forceinline__ void cmac(V& acc, V a, V b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
+
+// ---------------------------------------------------------------- unit roots
+// cos and sin of k pi / 16 for k = 0..4 (first octant), correctly rounded decimals.
+constexpr double kOctC[5] = {1.0, 0.98078528040323044913, 0.92387953251128675613, 0.83146961230254523708,
+                             0.70710678118654752440};
+constexpr double kOctS[5] = {0.0, 0.19509032201612826785, 0.38268343236508977173, 0.55557023301960222474,
+                             0.70710678118654752440};
+
+// exp(+2 pi i m / 32), exact symmetries of the first octant.
+constexpr double root32_c(int m) {
+  m = ((m % 32) + 32) % 32;
+  const int q = m / 8, r = m % 8;
+  const double c = r <= 4 ? kOctC[r] : kOctS[8 - r];
+  const double s = r <= 4 ? kOctS[r] : kOctC[8 - r];
+  return q == 0 ? c : q == 1 ? -s : q == 2 ? -c : s;
+}
+constexpr double root32_s(int m) {
+  m = ((m % 32) + 32) % 32;
+  const int q = m / 8, r = m % 8;
+  const double c = r <= 4 ? kOctC[r] : kOctS[8 - r];
+  const double s = r <= 4 ? kOctS[r] : kOctC[8 - r];
+  return q == 0 ? s : q == 1 ? c : q == 2 ? -s : -c;
+}
+
+// x * exp(+2 pi i m / R) with R | 32, trivial roots folded at compile time.
+template <int R, int M, typename V> __device__ __forceinline__ V rot(V x) {
+  constexpr int m = ((M % R) + R) % R;
+  if constexpr (m == 0) {
+    return x;
+  } else if constexpr (4 * m == R) {
+    return V{-x.y, x.x};
+  } else if constexpr (2 * m == R) {
+    return V{-x.x, -x.y};
+  } else if constexpr (4 * m == 3 * R) {
+    return V{x.y, -x.x};
+  } else {
+    using T = decltype(x.x);
+    constexpr double c = root32_c(m * (32 / R));
+    constexpr double s = root32_s(m * (32 / R));
+    return V{T(c) * x.x - T(s) * x.y, T(s) * x.x + T(c) * x.y};
+  }
+}
+
+// In-place R-point DFT y[k] = sum_a x[a] exp(+2 pi i k a / R), R a power of two <= 32.
+// Radix-2 decimation in time: bit-reversed reordering, then log2 R butterfly stages.
+template <int R> constexpr int bitrev(int i) {
+  int r = 0;
+  for (int b = 1; b < R; b <<= 1) {
+    r = (r << 1) | (i & 1);
+    i >>= 1;
+  }
+  return r;
+}
+
+template <int R, int L, int I, int J, typename V> __device__ __forceinline__ void bfly(V* x) {
+  if constexpr (I < R) {
+    if constexpr (J < L / 2) {
+      V u = x[I + J];
+      V t = rot<L, J>(x[I + J + L / 2]);
+      x[I + J] = cadd(u, t);
+      x[I + J + L / 2] = csub(u, t);
+      bfly<R, L, I, J + 1>(x);
+    } else {
+      bfly<R, L, I + L, 0>(x);
+    }
+  }
+}
+
+template <int R, int L, typename V> __device__ __forceinline__ void stages(V* x) {
+  if constexpr (L <= R) {
+    bfly<R, L, 0, 0>(x);
+    stages<R, 2 * L>(x);
+  }
+}
+
+template <int R, int I, typename V> __device__ __forceinline__ void bitrev_swap(V* x) {
+  if constexpr (I < R) {
+    constexpr int j = bitrev<R>(I);
+    if constexpr (j > I) {
+      V t = x[I];
+      x[I] = x[j];
+      x[j] = t;
+    }
+    bitrev_swap<R, I + 1>(x);
+  }
+}
+
+template <int R, typename V> __device__ __forceinline__ void dft(V* x) {
+  static_assert(R == 1 || R == 2 || R == 4 || R == 8 || R == 16 || R == 32, "radix");
+  if constexpr (R > 1) {
+    bitrev_swap<R, 0>(x);
+    stages<R, 2>(x);
+  }
+}
+
+// Wrap n into [0, m).
+__host__ __device__ __forceinline__ int wrap(int n, int m) {
+  int r = n % m;
+  return r < 0 ? r + m : r;
+}
+
+}  // namespace gw

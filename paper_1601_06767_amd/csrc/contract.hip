@@ -1,0 +1,249 @@
+// Weights and the dense contraction of Eq. (chi0):
+//   chi0_GG' += sum_p w_p M_p(G) conj(M_p(G')),
+//   w_p = n_c * 1/2 [1/(E_v - E_c - w + i delta) + 1/(E_v - E_c + w + i delta)]   (float64).
+// A complex weight splits into two real ones, chi0 = H_a + i H_b with
+// H_x = sum_p x_p M_p M_p^H Hermitian, so every launch is a Hermitian rank-k update
+// with real per-pair weights, computed for the lower tiles only and mirrored at the end.
+//
+// k_contract: one 64 x 64 tile (G, G') per workgroup, k (pairs) split over ksplit
+// workgroups that own separate float64 partial sums (no atomics, fixed summation
+// order).  Complex products on real MFMA 16x16x4 (f64 or f32):
+//   Re += a.re b.re + a.im b.im,  Im += a.im b.re - a.re b.im   with b = w M(G').
+#include <type_traits>
+
+#include "common.h"
+#include "internal.h"
+
+namespace gw {
+
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+// Output row of accumulator register r in lane group lk = lane / 16 (column = lane % 16);
+// the f64 and f32 16x16x4 instructions differ here.
+template <> struct Mfma<double> {
+  using acc = f64x4;
+  static __device__ __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
+  static __device__ __forceinline__ acc run(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<float> {
+  using acc = f32x4;
+  static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
+  static __device__ __forceinline__ acc run(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+__global__ void k_weights(const double* __restrict__ e_v, int v0, int nv_valid, int nvs,
+                          const double* __restrict__ e_col, const double* __restrict__ n_col, int c0, int nc_valid,
+                          int ncs, double omega, double delta, double* __restrict__ w) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int np = nvs * ncs;
+  if (p >= np) return;
+  const int v = v0 + p / ncs;
+  const int c = c0 + p % ncs;
+  double wr = 0.0, wi = 0.0;
+  if (v < nv_valid && c < nc_valid) {
+    const double n = n_col ? n_col[c] : 1.0;
+    const double x = e_v[v] - e_col[c];
+    if (delta == 0.0 && omega == 0.0) {
+      wr = 0.5 * n * (1.0 / x + 1.0 / x);
+    } else {
+      // 1/(x - w + i d) + 1/(x + w + i d), each as conj(z)/|z|^2
+      const double a = x - omega, b = x + omega;
+      const double da = a * a + delta * delta, db = b * b + delta * delta;
+      wr = 0.5 * n * (a / da + b / db);
+      wi = 0.5 * n * (-delta / da - delta / db);
+    }
+  }
+  w[p] = wr;
+  w[np + p] = wi;
+}
+
+constexpr int KC = 16;   // pairs per LDS stage
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_contract(const cx<T>* __restrict__ m, const double* __restrict__ w, int nk,
+                                                  int ngp, int ksplit, double2* __restrict__ acc) {
+  using V = cx<T>;
+  using A4 = typename Mfma<T>::acc;
+  __shared__ V sA[KC][kTile];
+  __shared__ V sB[KC][kTile];
+
+  const int t = blockIdx.x / ksplit;
+  const int ks = blockIdx.x % ksplit;
+  int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  while (ti * (ti + 1) / 2 > t) --ti;
+  const int tj = t - ti * (ti + 1) / 2;
+  const int g0 = ti * kTile, h0 = tj * kTile;
+
+  const int per = (nk + ksplit - 1) / ksplit;
+  const int k0 = ks * per;
+  const int k1 = min(nk, k0 + per);
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int li = lane & 15, lk = lane >> 4;
+
+  A4 cre[2][2], cim[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cre[i][j] = A4{0, 0, 0, 0};
+      cim[i][j] = A4{0, 0, 0, 0};
+    }
+
+  for (int kk = k0; kk < k1; kk += KC) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < (KC * kTile) / 256; ++r) {
+      const int e = tid + 256 * r;
+      const int k = e / kTile, g = e % kTile;
+      V a{T(0), T(0)}, b{T(0), T(0)};
+      if (kk + k < k1) {
+        const size_t row = (size_t)(kk + k) * ngp;
+        a = m[row + g0 + g];
+        const V bb = m[row + h0 + g];
+        const T s = T(w[kk + k]);
+        b = V{bb.x * s, bb.y * s};
+      }
+      sA[k][g] = a;
+      sB[k][g] = b;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < KC / 4; ++s) {
+      const int k = 4 * s + lk;
+      V a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = sA[k][32 * wr + 16 * i + li];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = sB[k][32 * wc + 16 * j + li];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          cre[i][j] = Mfma<T>::run(a[i].x, b[j].x, cre[i][j]);
+          cre[i][j] = Mfma<T>::run(a[i].y, b[j].y, cre[i][j]);
+          cim[i][j] = Mfma<T>::run(a[i].y, b[j].x, cim[i][j]);
+          cim[i][j] = Mfma<T>::run(-a[i].x, b[j].y, cim[i][j]);
+        }
+    }
+  }
+  // accumulate into this split's float64 partial sum
+  double2* out = acc + (size_t)ks * ngp * ngp;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = g0 + 32 * wr + 16 * i + Mfma<T>::row(lk, r);
+        const int col = h0 + 32 * wc + 16 * j + li;
+        double2* p = out + (size_t)row * ngp + col;
+        double2 o = *p;
+        o.x += (double)cre[i][j][r];
+        o.y += (double)cim[i][j][r];
+        *p = o;
+      }
+}
+
+__global__ void k_finalize(const double2* __restrict__ accA, const double2* __restrict__ accB, int ksplit, int ng,
+                           int ngp, double2* __restrict__ chi) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)ng * ng) return;
+  const int g = (int)(e / ng), h = (int)(e % ng);
+  const bool lower = g >= h;
+  const size_t src = lower ? (size_t)g * ngp + h : (size_t)h * ngp + g;
+  double2 a{0.0, 0.0}, b{0.0, 0.0};
+  for (int k = 0; k < ksplit; ++k) {
+    const double2 x = accA[(size_t)k * ngp * ngp + src];
+    a.x += x.x;
+    a.y += x.y;
+    if (accB) {
+      const double2 y = accB[(size_t)k * ngp * ngp + src];
+      b.x += y.x;
+      b.y += y.y;
+    }
+  }
+  if (!lower) {
+    a.y = -a.y;
+    b.y = -b.y;
+  }
+  chi[e] = double2{a.x - b.y, a.y + b.x};
+}
+
+__global__ void k_zero(uint4* p, size_t n16) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = uint4{0, 0, 0, 0};
+}
+
+// out[(v * ncs + c) * ng + g] = m[(v * ncs_pad + c) * ngp + g] for v < nvs, c < ncs
+template <typename T>
+__global__ void k_copy_m(const cx<T>* __restrict__ m, int nvs, int ncs, int ncs_pad, int ng, int ngp,
+                         double2* __restrict__ out) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)nvs * ncs * ng) return;
+  const size_t p = e / ng, g = e % ng;
+  const size_t v = p / ncs, c = p % ncs;
+  const cx<T> x = m[(v * ncs_pad + c) * ngp + g];
+  out[e] = double2{(double)x.x, (double)x.y};
+}
+
+}  // namespace
+
+hipError_t launch_weights(const double* e_v, int v0, int nv_valid, int nvs, const double* e_col, const double* n_col,
+                          int c0, int nc_valid, int ncs, const double* omega, int iw, double delta, double* w,
+                          hipStream_t st) {
+  const int np = nvs * ncs;
+  k_weights<<<(np + 255) / 256, 256, 0, st>>>(e_v, v0, nv_valid, nvs, e_col, n_col, c0, nc_valid, ncs,
+                                               omega ? omega[iw] : 0.0, delta, w);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_contract(const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
+                           hipStream_t st) {
+  const int nt = ngp / kTile;
+  const int ntl = nt * (nt + 1) / 2;
+  k_contract<T><<<ntl * ksplit, 256, 0, st>>>((const cx<T>*)m, w, nk, ngp, ksplit, acc);
+  return hipGetLastError();
+}
+template hipError_t launch_contract<double>(const void*, const double*, int, int, int, double2*, hipStream_t);
+template hipError_t launch_contract<float>(const void*, const double*, int, int, int, double2*, hipStream_t);
+
+hipError_t launch_finalize(const double2* accA, const double2* accB, int ksplit, int ng, int ngp, double2* chi,
+                           hipStream_t st) {
+  const size_t n = (size_t)ng * ng;
+  k_finalize<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(accA, accB, ksplit, ng, ngp, chi);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+  const size_t n16 = bytes / 16;
+  if (n16 == 0) return hipSuccess;
+  const unsigned nb = (unsigned)std::min<size_t>((n16 + 255) / 256, 65536);
+  k_zero<<<nb, 256, 0, st>>>((uint4*)p, n16);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_m(const void* m, int nvs, int ncs, int ncs_pad, int ng, int ngp, bool fp64, double2* out,
+                         hipStream_t st) {
+  const size_t n = (size_t)nvs * ncs * ng;
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  if (fp64)
+    k_copy_m<double><<<nb, 256, 0, st>>>((const double2*)m, nvs, ncs, ncs_pad, ng, ngp, out);
+  else
+    k_copy_m<float><<<nb, 256, 0, st>>>((const float2*)m, nvs, ncs, ncs_pad, ng, ngp, out);
+  return hipGetLastError();
+}
+
+}  // namespace gw

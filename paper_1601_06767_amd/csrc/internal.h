@@ -1,0 +1,116 @@
+// Internal declarations of the gwchi0 library (host side of the kernels).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/gwchi0.h"
+
+namespace gw {
+enum Stage { kStageBand = 0, kStagePlanes, kStageFinish, kStageWeights, kStageContract, kStageFinalize,
+             kStageEpsInv, kStageBackward, kNumStages };
+}
+
+struct gw_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int* d_pivot_flag = nullptr;   // set by the inversion kernels on a zero pivot
+  // stage timers: events recorded around launches while timing is on
+  bool timing = false;
+  struct Mark {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> marks;
+  double stage_ms[gw::kNumStages] = {};
+  long long stage_n[gw::kNumStages] = {};
+};
+
+namespace gw {
+// Records an event pair around the launches in its scope when the context times stages.
+struct StageScope {
+  gw_ctx* ctx;
+  gw_ctx::Mark m{};
+  bool on;
+  StageScope(gw_ctx* c, int stage) : ctx(c), on(c->timing) {
+    if (on) {
+      m.stage = stage;
+      on = hipEventCreate(&m.a) == hipSuccess && hipEventCreate(&m.b) == hipSuccess &&
+           hipEventRecord(m.a, c->stream) == hipSuccess;
+    }
+  }
+  ~StageScope() {
+    if (on && hipEventRecord(m.b, ctx->stream) == hipSuccess) ctx->marks.push_back(m);
+  }
+};
+}  // namespace gw
+
+namespace gw {
+
+// Line decomposition of an N-point transform, x = b + S a  (a in [0,R), b in [0,S)),
+// stored permuted at p = b R + a so that the R points of one b are contiguous.
+struct LineSplit {
+  int R, S;
+};
+bool line_split(int nd, LineSplit* out);
+constexpr int kRows = 8;   // rows of one x2 group in the pair kernel (x2 = b2 + S2 a2, a2 < 8)
+
+struct Geom {
+  int nd = 0;          // grid points per axis
+  int npw = 0, ng = 0;
+  int rw = 0, W = 0;   // wavefunction sphere half-width, W = 2 rw + 1
+  int rchi = 0, K = 0; // chi sphere half-width, K = 2 rchi + 1
+  int ngp = 0;         // ng rounded up to the contraction tile
+  LineSplit line{};    // split of the x3 (and x1) transforms
+  int32_t* d_wf_map = nullptr;   // W^3 box -> wavefunction index or -1
+  int32_t* d_chi_map = nullptr;  // K^3 box -> chi index or -1
+  double2* d_tw64 = nullptr;     // exp(+2 pi i j / nd), j < nd
+  float2* d_tw32 = nullptr;
+};
+
+// ---------------------------------------------------------------- launches
+// Band -> real space: psi[slot][x1][p2][p3] for nslot bands.  Band of slot s:
+// idx = band0 + s; if idx >= nvalid it is clamped to nvalid - 1; then
+// band = band_idx ? band_idx[idx] : idx.
+template <typename T>
+hipError_t launch_band_to_real(const Geom& g, const double2* coef, int nrows, const int32_t* band_idx, int band0, int nvalid,
+                               int nslot, void* tA, void* tB, void* psi, hipStream_t st);
+size_t band_scratch_bytes(const Geom& g, int nslot, bool fp64);
+
+// Pair planes: Q[pair][p1][j2][j3] for pairs (v, c), v < nvs (multiple of 4), c < ncs (multiple of 8);
+// pair = v * ncs + c.
+template <typename T>
+hipError_t launch_pair_planes(const Geom& g, const void* psi_v, const void* psi_c, int nvs, int ncs, void* q,
+                              hipStream_t st);
+// Pair finish: x1 transforms, 1/N, gather to the chi sphere: m[pair][ngp] (zero padded).
+template <typename T>
+hipError_t launch_pair_finish(const Geom& g, const void* q, int npair, void* m, hipStream_t st);
+bool pair_supported(int nd, int K);
+
+// Weights of Eq. (chi0) per pair p = v * ncs + c (zero for padded pairs):
+// part 0 = Re w, part 1 = Im w, w[part][p].
+hipError_t launch_weights(const double* e_v, int v0, int nv_valid, int nvs, const double* e_col, const double* n_col,
+                          int c0, int nc_valid, int ncs, const double* omega, int iw, double delta, double* w,
+                          hipStream_t st);
+
+// acc[ks][G][G'] (lower tiles) += sum_k m[k][G] w[k] conj(m[k][G'])
+template <typename T>
+hipError_t launch_contract(const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
+                           hipStream_t st);
+hipError_t launch_contract_bf16x3(const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
+                                  hipStream_t st);
+// chi[G][G'] = sum_ks accA + i sum_ks accB (Hermitian parts mirrored), for G, G' < ng.
+hipError_t launch_finalize(const double2* accA, const double2* accB, int ksplit, int ng, int ngp, double2* chi,
+                           hipStream_t st);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+hipError_t launch_copy_m(const void* m, int nvs, int ncs, int ncs_pad, int ng, int ngp, bool fp64, double2* out,
+                         hipStream_t st);
+
+constexpr int kTile = 64;   // contraction tile (G x G')
+
+}  // namespace gw

@@ -1,0 +1,96 @@
+"""Shared test inputs: seeded synthetic problems and their upload to the GPU library.
+
+Only input preparation lives here (generator calls, host->device copies); the
+arithmetic under test runs in the library, the expected values in the oracle."""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+import synth
+
+
+@dataclasses.dataclass
+class Case:
+    cfg: synth.Config
+    nd: int
+    gw: np.ndarray
+    gc: np.ndarray
+    coef_v: np.ndarray
+    e_v: np.ndarray
+    coef_c: np.ndarray
+    e_c: np.ndarray
+    col_band: Optional[np.ndarray] = None
+    e_col: Optional[np.ndarray] = None
+    n_col: Optional[np.ndarray] = None
+
+    def columns(self):
+        if self.e_col is None:
+            return np.arange(len(self.e_c)), self.e_c, np.ones(len(self.e_c))
+        return self.col_band, self.e_col, self.n_col
+
+
+def make_case(cfg_index: int, nv: Optional[int] = None, nc: Optional[int] = None, iq: int = 0,
+              v_stride: int = 1, device: Optional[str] = None, ng: Optional[int] = None) -> Case:
+    cfg = synth.config(cfg_index)
+    gw = synth.wf_sphere(cfg.nd)
+    gc = synth.chi_sphere(ng or cfg.ng[iq], cfg.qs[iq], cfg.cell)
+    nv = cfg.nv if nv is None else nv
+    nc = cfg.nc if nc is None else nc
+    b = synth.make_bands(cfg, v_index=np.arange(0, nv * v_stride, v_stride), c_index=np.arange(nc), gvec_wf=gw,
+                         iq=iq, device=device)
+    return Case(cfg, cfg.nd, gw, gc, b.coef_v, b.e_v, b.coef_c, b.e_c)
+
+
+class Gpu:
+    """One context on cuda:0 plus helpers that keep device copies alive."""
+
+    def __init__(self):
+        import torch
+        import paper_1601_06767_amd as p
+        self.torch = torch
+        self.p = p
+        self.dev = torch.device("cuda", 0)
+        self.ctx = p.gw_ctx_create(0)
+        self._keep = []
+        self._geoms = {}
+
+    def t(self, a, dtype=None):
+        x = self.torch.from_numpy(np.ascontiguousarray(a)).to(self.dev)
+        if dtype is not None:
+            x = x.to(dtype)
+        self._keep.append(x)
+        return x
+
+    def geom(self, case: Case):
+        key = (case.nd, case.gw.tobytes(), case.gc.tobytes())
+        if key not in self._geoms:
+            self._geoms[key] = self.p.gw_geom_create(self.ctx, (case.nd,) * 3, case.gw, case.gc)
+        return self._geoms[key]
+
+    def problem(self, case: Case):
+        col, e_col, n_col = case.columns()
+        return self.p.make_problem(self.geom(case), self.t(case.coef_v), self.t(case.e_v), self.t(case.coef_c),
+                                   self.t(e_col), self.t(n_col),
+                                   None if case.col_band is None else self.t(case.col_band.astype(np.int32)))
+
+    def chi0(self, case: Case, omegas=(0.0,), delta=0.0, prec="fp64"):
+        r = self.p.gw_chi0_build(self.ctx, [self.problem(case)], [len(case.gc)], omegas, delta,
+                                 self.p.PRECISIONS[prec])
+        self.torch.cuda.synchronize()
+        return r[0].cpu().numpy()
+
+    def pair_density(self, case: Case, v0, nvs, c0, ncs, prec="fp64"):
+        m = self.p.gw_pair_density(self.ctx, self.problem(case), v0, nvs, c0, ncs, len(case.gc),
+                                   self.p.PRECISIONS[prec])
+        self.torch.cuda.synchronize()
+        return m.cpu().numpy()
+
+
+def rel_err(a: np.ndarray, b: np.ndarray):
+    """(Frobenius relative error, max abs error / max |b|)."""
+    nb = np.linalg.norm(b)
+    mb = np.abs(b).max()
+    return float(np.linalg.norm(a - b) / nb), float(np.abs(a - b).max() / mb)

@@ -1,0 +1,78 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports every
+function declared in include/gwchi0.h, and its host logic (window grouping,
+argument validation) matches the oracle bit for bit."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    import paper_1601_06767_amd as p
+    return p
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "gwchi0.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(gw_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    p = _lib()
+    names = declared_functions()
+    assert len(names) >= 10
+    missing = [n for n in names if not hasattr(p._lib.lib, n)]
+    assert not missing, missing
+    assert set(names) <= set(p._lib.EXPORTED)
+    assert p.gw_version().startswith("gwchi0")
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_group_windows_matches_oracle(seed):
+    p = _lib()
+    r = np.random.default_rng(seed)
+    e = r.uniform(0.1, 2.2, 700)
+    if seed == 1:
+        e = np.sort(e)
+    e0, de, nwin = 1.1, 0.05, 22   # top = 2.2
+    for mode, a, v0 in ((0, 0.0, 0.0), (1, 37.5, -0.3)):
+        got = p.gw_group_windows(e, e0, de, nwin, mode, a, v0)
+        want = oracle.group_windows(e, e0, de, nwin, "count" if mode == 0 else "dos", a, v0)
+        assert got[3] == want[3]
+        assert np.array_equal(got[0], want[0])
+        assert np.array_equal(got[1], want[1])
+        assert np.array_equal(got[2], want[2])
+
+
+def test_group_windows_edges():
+    p = _lib()
+    e0, de, nwin = 1.0, 0.25, 4
+    # exactly at E_0 -> explicit; exactly at the top -> last window; ties -> lower index
+    e = np.array([1.0, 2.0, 1.125, 1.125, 0.3])
+    col, ec, nc, n0 = p.gw_group_windows(e, e0, de, nwin)
+    want = oracle.group_windows(e, e0, de, nwin)
+    assert n0 == 2 and list(col) == list(want[0])
+    assert col[2] == 2                       # tie at the midpoint of window 0: lower index
+    with pytest.raises(p.GwError):
+        p.gw_group_windows(np.array([2.01]), e0, de, nwin)
+    # no windows at all
+    col, ec, nc, n0 = p.gw_group_windows(np.array([0.2, 0.9]), e0, de, 0)
+    assert list(col) == [0, 1] and n0 == 2
+
+
+def test_context_create_without_gpu_reports_error():
+    p = _lib()
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    import ctypes
+    out = ctypes.c_void_p()
+    st = p._lib.lib.gw_ctx_create(0, None, ctypes.byref(out))
+    assert st != 0 and not out.value
+    assert p.gw_last_error(None)

@@ -1,0 +1,175 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances: FP64 mode 1e-10 relative (Frobenius and max-abs over max |chi0|);
+pair densities 1e-12 relative; FP32 mode 2e-5 relative (float32 pair transform,
+float32 MFMA accumulation within a chunk of pairs)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from cases import Case, Gpu, make_case, rel_err
+
+pytestmark = pytest.mark.gpu
+
+EV = synth.HARTREE_EV
+
+
+@pytest.fixture(scope="module")
+def g(gpu):
+    return Gpu()
+
+
+def ref_chi0(case: Case, omegas=(0.0,), delta=0.0):
+    col, e_col, n_col = case.columns()
+    return oracle.chi0_bands(case.coef_v, case.e_v, case.coef_c, e_col, case.gw, case.gc, (case.nd,) * 3,
+                             omegas, delta, n_col=n_col, col_band=col)
+
+
+def ref_m(case: Case, v0, nvs, c0, ncs):
+    col, _, _ = case.columns()
+    pv = oracle.psi_real_space(case.coef_v[v0:v0 + nvs], case.gw, (case.nd,) * 3)
+    pc = oracle.psi_real_space(case.coef_c[col[c0:c0 + ncs]], case.gw, (case.nd,) * 3)
+    return oracle.pair_density_fft(pv, pc, case.gc)
+
+
+def test_pair_density_c1_fp64(g):
+    case = make_case(0)
+    m = g.pair_density(case, 0, 16, 0, 40)
+    ref = ref_m(case, 0, 16, 0, 40)
+    assert np.abs(m - ref).max() <= 1e-12 * np.abs(ref).max()
+    # orthogonality: M_vc(G = 0) = <v|c> = 0
+    assert np.abs(m[:, :, 0]).max() < 1e-14
+
+
+def test_pair_density_ragged_block_fp64_fp32(g):
+    case = make_case(0)
+    ref = ref_m(case, 3, 5, 101, 13)
+    m64 = g.pair_density(case, 3, 5, 101, 13, "fp64")
+    m32 = g.pair_density(case, 3, 5, 101, 13, "fp32")
+    assert np.abs(m64 - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert np.abs(m32 - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+def test_pair_density_plane_waves_closed_form(g):
+    # c_v = e_{G_a}, c_c = e_{G_b}  =>  M(G) = delta_{G, G_a - G_b}
+    base = make_case(0, nv=4, nc=8)
+    pa, pb = [0, 7, 40, 77], [3, 19, 33, 60, 101, 150, 200, 500]
+    case = Case(base.cfg, base.nd, base.gw, base.gc, synth.plane_wave_bands(base.gw, pa), base.e_v,
+                synth.plane_wave_bands(base.gw, pb), base.e_c)
+    m = g.pair_density(case, 0, 4, 0, 8)
+    gl = {tuple(x): i for i, x in enumerate(base.gc.tolist())}
+    want = np.zeros_like(m)
+    for i, a in enumerate(pa):
+        for j, b in enumerate(pb):
+            k = gl.get(tuple(base.gw[a] - base.gw[b]))
+            if k is not None:
+                want[i, j, k] = 1.0
+    assert np.abs(m - want).max() < 1e-14
+
+
+def test_chi0_c1_fp64(g):
+    case = make_case(0)
+    chi = g.chi0(case)[0]
+    ref = ref_chi0(case)[0]
+    fro, mx = rel_err(chi, ref)
+    assert fro <= 1e-10 and mx <= 1e-10, (fro, mx)
+    assert np.abs(chi - chi.conj().T).max() <= 1e-14 * np.abs(chi).max()
+    assert np.linalg.eigvalsh(chi).max() <= 1e-12 * np.abs(chi).max()
+    assert np.abs(chi[0]).max() <= 1e-13 * np.abs(chi).max()
+
+
+def test_chi0_c1_fp32(g):
+    case = make_case(0)
+    chi = g.chi0(case, prec="fp32")[0]
+    ref = ref_chi0(case)[0]
+    fro, mx = rel_err(chi, ref)
+    assert fro <= 2e-5 and mx <= 2e-5, (fro, mx)
+
+
+@pytest.mark.parametrize("nv,nc", [(1, 1), (5, 13), (7, 65)])
+def test_chi0_ragged_fp64(g, nv, nc):
+    case = make_case(0, nv=nv, nc=nc)
+    chi = g.chi0(case)[0]
+    ref = ref_chi0(case)[0]
+    fro, mx = rel_err(chi, ref)
+    assert fro <= 1e-10 and mx <= 1e-10, (fro, mx)
+
+
+def test_chi0_dynamic_fp64(g):
+    case = make_case(0, nv=8, nc=60)
+    om = np.array([0.0, 0.3, 7.0, 25.0]) / EV
+    d = 0.1 / EV
+    chi = g.chi0(case, omegas=om, delta=d)
+    ref = ref_chi0(case, om, d)
+    for i in range(len(om)):
+        fro, mx = rel_err(chi[i], ref[i])
+        assert fro <= 1e-10 and mx <= 1e-10, (i, fro, mx)
+    # delta = 0 below the gap: Hermitian
+    chi0 = g.chi0(case, omegas=[0.5 / EV], delta=0.0)[0]
+    assert np.abs(chi0 - chi0.conj().T).max() <= 1e-14 * np.abs(chi0).max()
+
+
+def test_chi0_grouped_fp64(g):
+    # C1 spectrum [5, 60] eV grouped above E_0 = 30 eV in 1 eV windows (count weights)
+    case = make_case(0, nv=16, nc=240)
+    e0, de, nwin = 30.0 / EV, 1.0 / EV, 30
+    col, e_col, n_col, n0 = g.p.gw_group_windows(case.e_c, e0, de, nwin)
+    want = oracle.group_windows(case.e_c, e0, de, nwin)
+    assert np.array_equal(col, want[0]) and np.array_equal(n_col, want[2]) and n0 == want[3]
+    case.col_band, case.e_col, case.n_col = col, e_col, n_col
+    chi = g.chi0(case)[0]
+    ref = oracle.chi0_grouped_static(case.coef_v, case.e_v, case.coef_c, case.e_c, case.gw, case.gc,
+                                     (case.nd,) * 3, e0, de, nwin)
+    fro, mx = rel_err(chi, ref)
+    assert fro <= 1e-10 and mx <= 1e-10, (fro, mx)
+
+
+@pytest.mark.parametrize("cfg,prec,tol", [(1, "fp64", 1e-10), (1, "fp32", 2e-5), (2, "fp32", 2e-5),
+                                          (4, "fp32", 2e-5)])
+def test_chi0_config_geometry_subset(g, cfg, prec, tol):
+    # the configs' grids and dielectric spheres (72^3 / NG 2000, 96^3 / 4000, 128^3 / 8000)
+    # on a few bands the oracle finishes in seconds
+    case = make_case(cfg, nv=4, nc=12)
+    chi = g.chi0(case, prec=prec)[0]
+    ref = ref_chi0(case)[0]
+    fro, mx = rel_err(chi, ref)
+    assert fro <= tol and mx <= tol, (fro, mx)
+
+
+@pytest.mark.parametrize("iq", [0, 3, 7])
+def test_chi0_batched_config_q_points(g, iq):
+    # q-points and dielectric spheres of the batched workload (NG 800 ... 3000), dynamic
+    case = make_case(3, nv=4, nc=8, iq=iq)
+    om = np.array([0.0, 10.0]) / EV
+    d = 0.1 / EV
+    chi = g.chi0(case, omegas=om, delta=d, prec="fp32")
+    ref = ref_chi0(case, om, d)
+    for i in range(2):
+        fro, mx = rel_err(chi[i], ref[i])
+        assert fro <= 2e-5 and mx <= 2e-5, (iq, i, fro, mx)
+
+
+def test_chi0_deterministic(g):
+    case = make_case(0, nv=8, nc=100)
+    a = g.chi0(case)
+    b = g.chi0(case)
+    assert np.array_equal(a, b)
+
+
+def test_invalid_arguments_raise(g):
+    case = make_case(0, nv=2, nc=3)
+    p = g.p
+    prob = g.problem(case)
+    with pytest.raises(p.GwError):
+        p.gw_chi0_build(g.ctx, [prob], [len(case.gc)], [0.0], -1.0, p.GW_FP64)
+    with pytest.raises(p.GwError):
+        p.gw_pair_density(g.ctx, prob, 0, 3, 0, 1, len(case.gc), p.GW_FP64)
+    # not alias-free: 24^3 grid, wavefunction half-width 10, dielectric half-width 4 (2*10 + 4 = 24)
+    with pytest.raises(p.GwError):
+        p.gw_geom_create(g.ctx, (24, 24, 24), synth.wf_sphere(24, 10), case.gc)
+    # workspace too small
+    import torch
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(p.GwError):
+        p.gw_chi0_build(g.ctx, [prob], [len(case.gc)], [0.0], 0.0, p.GW_FP64, workspace=ws)
