@@ -174,6 +174,13 @@ gw_status gw_eps_inv(gw_ctx* ctx, int ng, int nbatch, const double* vcoul, const
 /* Synchronises the stream; GW_ESINGULAR if the last gw_eps_inv met a zero pivot. */
 gw_status gw_eps_inv_status(gw_ctx* ctx);
 
+/* Adjoint of gw_eps_inv for a real loss L: with Z = eps^-1 (the saved output) and
+ * Zbar = dL/dRe Z + i dL/dIm Z (device, complex128, same shape), writes
+ *   chi0bar = diag(v) Z^H Zbar Z^H
+ * (device complex128, may not alias the inputs).  Workspace: gw_eps_inv_workspace_size. */
+gw_status gw_eps_inv_backward(gw_ctx* ctx, int ng, int nbatch, const double* vcoul, const void* eps_inv,
+                              const void* grad_eps_inv, void* workspace, size_t ws_bytes, void* grad_chi0);
+
 /* ---------------------------------------------------------------- grouping */
 
 /* Columns of Eq. (energyintegration) from a conduction spectrum (host arrays).

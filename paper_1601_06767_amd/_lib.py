@@ -60,6 +60,7 @@ _sig("gw_pair_density", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_i
 _sig("gw_eps_inv_workspace_size", C.c_int, [vp, C.c_int, C.c_int, C.POINTER(C.c_size_t)])
 _sig("gw_eps_inv", C.c_int, [vp, C.c_int, C.c_int, vp, vp, vp, C.c_size_t, vp])
 _sig("gw_eps_inv_status", C.c_int, [vp])
+_sig("gw_eps_inv_backward", C.c_int, [vp, C.c_int, C.c_int, vp, vp, vp, vp, C.c_size_t, vp])
 _sig("gw_group_windows", C.c_int, [C.c_int, dp, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double, C.c_double,
                                    i32p, dp, dp, C.POINTER(C.c_int), C.POINTER(C.c_int)])
 
@@ -71,7 +72,8 @@ STAGES = ["band", "planes", "finish", "weights", "contract", "finalize", "eps_in
 EXPORTED = ["gw_ctx_set_timing", "gw_ctx_stage_times",
             "gw_version", "gw_ctx_create", "gw_ctx_destroy", "gw_last_error", "gw_geom_create", "gw_geom_destroy",
             "gw_chi0_workspace_size", "gw_chi0_build", "gw_pair_density_workspace_size", "gw_pair_density",
-            "gw_eps_inv_workspace_size", "gw_eps_inv", "gw_eps_inv_status", "gw_group_windows"]
+            "gw_eps_inv_workspace_size", "gw_eps_inv", "gw_eps_inv_status", "gw_eps_inv_backward",
+            "gw_group_windows"]
 
 
 class GwError(RuntimeError):
@@ -227,6 +229,23 @@ def gw_eps_inv(ctx, vcoul, chi0, workspace=None, out=None):
 
 def gw_eps_inv_status(ctx) -> None:
     _check(lib.gw_eps_inv_status(ctx), ctx)
+
+
+def gw_eps_inv_backward(ctx, vcoul, eps_inv, grad_eps_inv, workspace=None, out=None):
+    """chi0bar = diag(v) Z^H Zbar Z^H for Z = eps^-1 (shapes as in gw_eps_inv)."""
+    import torch
+    squeeze = eps_inv.dim() == 2
+    z = eps_inv.reshape(-1, eps_inv.shape[-1], eps_inv.shape[-1]).contiguous()
+    zb = grad_eps_inv.reshape(z.shape).contiguous()
+    nb, ng = z.shape[0], z.shape[-1]
+    v = vcoul.reshape(-1, ng).expand(nb, ng).contiguous()
+    if workspace is None:
+        workspace = torch.empty(gw_eps_inv_workspace_size(ctx, ng, nb), dtype=torch.uint8, device=z.device)
+    if out is None:
+        out = torch.empty_like(z)
+    _check(lib.gw_eps_inv_backward(ctx, ng, nb, _ptr(v), _ptr(z), _ptr(zb), _ptr(workspace), workspace.numel(),
+                                   _ptr(out)), ctx)
+    return out[0] if squeeze else out
 
 
 # ---------------------------------------------------------------- grouping (host)

@@ -365,9 +365,11 @@ gw_status gw_chi0_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, in
         if (s != GW_OK) return s;
         for (int iw = 0; iw < nomega; ++iw) {
           double* w = (double*)(ws + pl.off_w);
-          gw::StageScope scw(ctx, gw::kStageWeights);
-          GW_HIP(ctx, gw::launch_weights(p.e_v, 0, p.nv, pl.nvs, p.e_col, p.n_col, c0, p.ncol, pl.cc, omega, iw,
-                                         delta, w, ctx->stream));
+          {
+            gw::StageScope scw(ctx, gw::kStageWeights);
+            GW_HIP(ctx, gw::launch_weights(p.e_v, 0, p.nv, pl.nvs, p.e_col, p.n_col, c0, p.ncol, pl.cc, omega, iw,
+                                           delta, w, ctx->stream));
+          }
           for (int part = 0; part < pl.nparts; ++part) {
             double2* acc = (double2*)(ws + pl.off_acc + acc_one * ((size_t)iw * pl.nparts + part));
             gw::StageScope sc(ctx, gw::kStageContract);
@@ -520,28 +522,65 @@ gw_status gw_ctx_stage_times(gw_ctx* ctx, double* ms, long long* counts, int res
 
 gw_status gw_eps_inv_workspace_size(gw_ctx* ctx, int ng, int nbatch, size_t* bytes) {
   if (!ctx) return GW_EINVAL;
-  (void)ng;
-  (void)nbatch;
-  (void)bytes;
-  return fail(ctx, GW_EUNSUPPORTED, "eps_inv not built yet");
+  if (ng < 1 || nbatch < 1 || !bytes) return fail(ctx, GW_EINVAL, "bad arguments");
+  *bytes = std::max(gw::eps_inv_workspace(ng), gw::eps_inv_backward_workspace(ng));
+  return GW_OK;
 }
 
 gw_status gw_eps_inv(gw_ctx* ctx, int ng, int nbatch, const double* vcoul, const void* chi0, void* workspace,
                      size_t ws_bytes, void* eps_inv) {
   if (!ctx) return GW_EINVAL;
-  (void)ng;
-  (void)nbatch;
-  (void)vcoul;
-  (void)chi0;
-  (void)workspace;
-  (void)ws_bytes;
-  (void)eps_inv;
-  return fail(ctx, GW_EUNSUPPORTED, "eps_inv not built yet");
+  if (ng < 1 || nbatch < 1 || !vcoul || !chi0 || !workspace || !eps_inv) return fail(ctx, GW_EINVAL, "bad arguments");
+  if (chi0 == eps_inv) return fail(ctx, GW_EINVAL, "eps_inv may not alias chi0");
+  if (ws_bytes < gw::eps_inv_workspace(ng))
+    return fail(ctx, GW_EINVAL, "workspace too small: need " + std::to_string(gw::eps_inv_workspace(ng)));
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(ctx->device);
+  auto run = [&]() -> gw_status {
+    GW_HIP(ctx, gw::launch_flag_clear(ctx->d_pivot_flag, ctx->stream));
+    gw::StageScope sc(ctx, gw::kStageEpsInv);
+    const size_t nn = (size_t)ng * ng;
+    for (int b = 0; b < nbatch; ++b)
+      GW_HIP(ctx, gw::launch_eps_inv(ng, vcoul + (size_t)b * ng, (const double2*)chi0 + b * nn,
+                                     (double2*)eps_inv + b * nn, workspace, ctx->d_pivot_flag, ctx->stream));
+    return GW_OK;
+  };
+  gw_status s = run();
+  (void)hipSetDevice(prev);
+  return s;
 }
 
 gw_status gw_eps_inv_status(gw_ctx* ctx) {
   if (!ctx) return GW_EINVAL;
+  int flag = 0;
+  GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  GW_HIP(ctx, hipMemcpy(&flag, ctx->d_pivot_flag, sizeof(int), hipMemcpyDeviceToHost));
+  if (flag) return fail(ctx, GW_ESINGULAR, "zero or non-finite pivot in eps = I - v chi0");
   return GW_OK;
+}
+
+gw_status gw_eps_inv_backward(gw_ctx* ctx, int ng, int nbatch, const double* vcoul, const void* eps_inv,
+                              const void* grad_eps_inv, void* workspace, size_t ws_bytes, void* grad_chi0) {
+  if (!ctx) return GW_EINVAL;
+  if (ng < 1 || nbatch < 1 || !vcoul || !eps_inv || !grad_eps_inv || !workspace || !grad_chi0)
+    return fail(ctx, GW_EINVAL, "bad arguments");
+  if (ws_bytes < gw::eps_inv_backward_workspace(ng)) return fail(ctx, GW_EINVAL, "workspace too small");
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(ctx->device);
+  auto run = [&]() -> gw_status {
+    gw::StageScope sc(ctx, gw::kStageBackward);
+    const size_t nn = (size_t)ng * ng;
+    for (int b = 0; b < nbatch; ++b)
+      GW_HIP(ctx, gw::launch_eps_inv_backward(ng, vcoul + (size_t)b * ng, (const double2*)eps_inv + b * nn,
+                                              (const double2*)grad_eps_inv + b * nn, (double2*)grad_chi0 + b * nn,
+                                              workspace, ctx->stream));
+    return GW_OK;
+  };
+  gw_status s = run();
+  (void)hipSetDevice(prev);
+  return s;
 }
 
 }  // extern "C"

@@ -113,4 +113,16 @@ hipError_t launch_copy_m(const void* m, int nvs, int ncs, int ncs_pad, int ng, i
 
 constexpr int kTile = 64;   // contraction tile (G x G')
 
+// ---------------------------------------------------------------- dielectric
+constexpr int kNb = 64;     // Gauss-Jordan panel width
+hipError_t launch_zgemm(int m, int n, int k, double2 alpha, const double2* A, int lda, bool cta, const double2* B,
+                        int ldb, bool ctb, double2 beta, double2* C, int ldc, hipStream_t st);
+size_t eps_inv_workspace(int n);
+hipError_t launch_eps_inv(int n, const double* v, const double2* chi, double2* out, void* ws, int* flag,
+                          hipStream_t st);
+size_t eps_inv_backward_workspace(int n);
+hipError_t launch_eps_inv_backward(int n, const double* v, const double2* z, const double2* zbar, double2* out,
+                                   void* ws, hipStream_t st);
+hipError_t launch_flag_clear(int* flag, hipStream_t st);
+
 }  // namespace gw

@@ -27,7 +27,7 @@ constexpr int kLdsMax = 163840;
 
 template <typename T, int ND, int K, bool STAGE>
 struct PlaneLds {
-  static constexpr int rowp = ND;
+  static constexpr int rowp = ND + 1;   // padded row: the 8 rows read together fall on distinct banks
   static constexpr size_t psic = STAGE ? (size_t)kTC * kRows * rowp * sizeof(cx<T>) : 0;
   static constexpr size_t z = (size_t)kTV * kTC * kRows * K * sizeof(cx<T>);
   static constexpr size_t total = psic + z;
@@ -84,7 +84,8 @@ __global__ __launch_bounds__(256) void k_pair_planes(const cx<T>* __restrict__ p
       constexpr int per_col = kRows * ND;
       for (int i = tid; i < kTC * per_col; i += 256) {
         const int c = i / per_col, o = i % per_col;
-        s_psic[c * per_col + o] = psi_c[((size_t)(c0 + c) * ND + x1) * NPL + (size_t)b2 * per_col + o];
+        s_psic[(c * kRows + o / ND) * L::rowp + o % ND] =
+            psi_c[((size_t)(c0 + c) * ND + x1) * NPL + (size_t)b2 * per_col + o];
       }
       __syncthreads();
     } else {
@@ -93,7 +94,7 @@ __global__ __launch_bounds__(256) void k_pair_planes(const cx<T>* __restrict__ p
     // ---------------- stage 1: one row per lane
     {
       const V* rv = pv_plane + (size_t)(b2 * kRows + a2) * ND;
-      const V* rc = STAGE ? s_psic + (cl * kRows + a2) * ND : pc_plane + (size_t)(b2 * kRows + a2) * ND;
+      const V* rc = STAGE ? s_psic + (cl * kRows + a2) * L::rowp : pc_plane + (size_t)(b2 * kRows + a2) * ND;
       V acc[K];
 #pragma unroll
       for (int j = 0; j < K; ++j) acc[j] = V{T(0), T(0)};
