@@ -330,7 +330,6 @@ gw_status gw_chi0_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, in
     return fail(ctx, GW_EINVAL, "bad arguments");
   if (!(delta >= 0.0)) return fail(ctx, GW_EINVAL, "delta must be >= 0");
   if (prec != GW_FP64 && prec != GW_FP32 && prec != GW_BF16X3) return fail(ctx, GW_EINVAL, "bad precision");
-  if (prec == GW_BF16X3) return fail(ctx, GW_EUNSUPPORTED, "bf16x3 contraction not built yet");
   for (int i = 0; i < nprob; ++i) {
     gw_status s = check_problem(ctx, probs[i]);
     if (s != GW_OK) return s;
@@ -373,10 +372,12 @@ gw_status gw_chi0_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, in
           for (int part = 0; part < pl.nparts; ++part) {
             double2* acc = (double2*)(ws + pl.off_acc + acc_one * ((size_t)iw * pl.nparts + part));
             gw::StageScope sc(ctx, gw::kStageContract);
-            hipError_t e = pl.fp64 ? gw::launch_contract<double>(ws + pl.off_m, w + (size_t)part * pl.npair,
-                                                                 pl.npair, g.ngp, pl.ksplit, acc, ctx->stream)
-                                   : gw::launch_contract<float>(ws + pl.off_m, w + (size_t)part * pl.npair, pl.npair,
-                                                                g.ngp, pl.ksplit, acc, ctx->stream);
+            const double* wp = w + (size_t)part * pl.npair;
+            hipError_t e =
+                pl.fp64 ? gw::launch_contract<double>(ws + pl.off_m, wp, pl.npair, g.ngp, pl.ksplit, acc, ctx->stream)
+                : prec == GW_BF16X3
+                    ? gw::launch_contract_bf16x3(ws + pl.off_m, wp, pl.npair, g.ngp, pl.ksplit, acc, ctx->stream)
+                    : gw::launch_contract<float>(ws + pl.off_m, wp, pl.npair, g.ngp, pl.ksplit, acc, ctx->stream);
             GW_HIP(ctx, e);
           }
         }

@@ -156,6 +156,138 @@ __global__ __launch_bounds__(256) void k_contract(const cx<T>* __restrict__ m, c
       }
 }
 
+// ---------------------------------------------------------------- split-bf16 x3
+// Each float32 operand x = hi + lo (hi = bf16(x), lo = bf16(x - hi), round to nearest
+// even); products use hi*hi + hi*lo + lo*hi on MFMA 16x16x32 bf16 with float32
+// accumulation.  The complex Hermitian update is two real products over a doubled
+// inner index k' = [re of 16 pairs | im of 16 pairs]:
+//   Re C = [ar | ai] [br | bi]^T,   Im C = [ai | -ar] [br | bi]^T,   b = w M(G').
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_val(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+constexpr int BK = 16;          // pairs per MFMA step
+constexpr int BROW = 40;        // bf16 per LDS row (32 used, padded so 8 rows read together hit distinct banks)
+
+__global__ __launch_bounds__(256) void k_contract_bf16x3(const float2* __restrict__ m, const double* __restrict__ w,
+                                                         int nk, int ngp, int ksplit, double2* __restrict__ acc) {
+  // [A|B][hi|lo][row][k']
+  __shared__ __align__(16) unsigned short s[2][2][kTile][BROW];
+  const int t = blockIdx.x / ksplit;
+  const int ks = blockIdx.x % ksplit;
+  int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  while (ti * (ti + 1) / 2 > t) --ti;
+  const int tj = t - ti * (ti + 1) / 2;
+  const int g0 = ti * kTile, h0 = tj * kTile;
+  const int per = (nk + ksplit - 1) / ksplit;
+  const int k0 = ks * per;
+  const int k1 = min(nk, k0 + per);
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int li = lane & 15, lg = lane >> 4;
+
+  // staging role: operand (A or B), row, half of the 16 pairs
+  const int op = tid >> 7;            // 0: A rows (G), 1: B rows (G')
+  const int srow = tid & 63;
+  const int shalf = (tid >> 6) & 1;   // pairs [8 shalf, 8 shalf + 8)
+  const int gcol = (op ? h0 : g0) + srow;
+
+  f32x4 cre[2][2], cim[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cre[i][j] = f32x4{0, 0, 0, 0};
+      cim[i][j] = f32x4{0, 0, 0, 0};
+    }
+
+  for (int kk = k0; kk < k1; kk += BK) {
+    __syncthreads();
+    {
+      u16x8 rh, rl, ih, il;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = kk + 8 * shalf + e;
+        float2 x{0.f, 0.f};
+        if (k < k1) {
+          x = m[(size_t)k * ngp + gcol];
+          if (op) {
+            const float sw = (float)w[k];
+            x.x *= sw;
+            x.y *= sw;
+          }
+        }
+        const unsigned short a = bf16_rne(x.x), b = bf16_rne(x.y);
+        rh[e] = a;
+        ih[e] = b;
+        rl[e] = bf16_rne(x.x - bf16_val(a));
+        il[e] = bf16_rne(x.y - bf16_val(b));
+      }
+      *(u16x8*)&s[op][0][srow][8 * shalf] = rh;
+      *(u16x8*)&s[op][0][srow][16 + 8 * shalf] = ih;
+      *(u16x8*)&s[op][1][srow][8 * shalf] = rl;
+      *(u16x8*)&s[op][1][srow][16 + 8 * shalf] = il;
+    }
+    __syncthreads();
+    bf16x8 xh[2], xl[2], yh[2], yl[2], bh[2], bl[2];
+    const int yg = (lg + 2) & 3;
+    const unsigned short neg = lg >= 2 ? 0x8000 : 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int r = 32 * wr + 16 * i + li;
+      xh[i] = *(const bf16x8*)&s[0][0][r][8 * lg];
+      xl[i] = *(const bf16x8*)&s[0][1][r][8 * lg];
+      u16x8 uh = *(const u16x8*)&s[0][0][r][8 * yg];
+      u16x8 ul = *(const u16x8*)&s[0][1][r][8 * yg];
+      uh ^= neg;
+      ul ^= neg;
+      yh[i] = __builtin_bit_cast(bf16x8, uh);
+      yl[i] = __builtin_bit_cast(bf16x8, ul);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int r = 32 * wc + 16 * j + li;
+      bh[j] = *(const bf16x8*)&s[1][0][r][8 * lg];
+      bl[j] = *(const bf16x8*)&s[1][1][r][8 * lg];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[i], bh[j], cre[i][j], 0, 0, 0);
+        cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[i], bl[j], cre[i][j], 0, 0, 0);
+        cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl[i], bh[j], cre[i][j], 0, 0, 0);
+        cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yh[i], bh[j], cim[i][j], 0, 0, 0);
+        cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yh[i], bl[j], cim[i][j], 0, 0, 0);
+        cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yl[i], bh[j], cim[i][j], 0, 0, 0);
+      }
+  }
+  double2* out = acc + (size_t)ks * ngp * ngp;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = g0 + 32 * wr + 16 * i + 4 * lg + r;
+        const int col = h0 + 32 * wc + 16 * j + li;
+        double2* p = out + (size_t)row * ngp + col;
+        double2 o = *p;
+        o.x += (double)cre[i][j][r];
+        o.y += (double)cim[i][j][r];
+        *p = o;
+      }
+}
+
 __global__ void k_finalize(const double2* __restrict__ accA, const double2* __restrict__ accB, int ksplit, int ng,
                            int ngp, double2* __restrict__ chi) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -177,6 +309,10 @@ __global__ void k_finalize(const double2* __restrict__ accA, const double2* __re
   if (!lower) {
     a.y = -a.y;
     b.y = -b.y;
+  } else if (g == h) {
+    // H_a and H_b are Hermitian: their diagonals are real (rounding leaves a residue)
+    a.y = 0.0;
+    b.y = 0.0;
   }
   chi[e] = double2{a.x - b.y, a.y + b.x};
 }
@@ -219,6 +355,14 @@ hipError_t launch_contract(const void* m, const double* w, int nk, int ngp, int 
 }
 template hipError_t launch_contract<double>(const void*, const double*, int, int, int, double2*, hipStream_t);
 template hipError_t launch_contract<float>(const void*, const double*, int, int, int, double2*, hipStream_t);
+
+hipError_t launch_contract_bf16x3(const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
+                                  hipStream_t st) {
+  const int nt = ngp / kTile;
+  const int ntl = nt * (nt + 1) / 2;
+  k_contract_bf16x3<<<ntl * ksplit, 256, 0, st>>>((const float2*)m, w, nk, ngp, ksplit, acc);
+  return hipGetLastError();
+}
 
 hipError_t launch_finalize(const double2* accA, const double2* accB, int ksplit, int ng, int ngp, double2* chi,
                            hipStream_t st) {

@@ -6,12 +6,17 @@
 // k_pair_planes (one x1 plane, 4 x 8 pairs per workgroup):
 //   stage 1, per lane one (pair, x2 row): the product along x3 and a pruned x3
 //     transform, x3 = b + S a:  X[n] = sum_b e^{2 pi i n b/N} DFT_R(x[b + S a])[n mod R],
-//     n in [-rchi, rchi] -> Z[pair][row][n3] in LDS;
+//     n in [-rchi, rchi] -> Z[pair][row][n3] in LDS.  The conduction rows arrive one
+//     radix-R chunk (one b) at a time through a double buffer in LDS, the next chunk
+//     in flight while the current one is used; valence rows are read directly (eight
+//     lanes share each row);
 //   stage 2, per lane (pair, n3): the same split along x2 over the 8 rows of each
 //     x2 group (x2 = b2 + S2 a2), accumulated over the S2 groups in registers;
 //   output Q[pair][p1][n2][n3] for this plane (p1 = plane stored permuted).
 // k_pair_finish (one pair per workgroup): pruned x1 transform of Q, the 1/N, and the
 //   gather of the K^3 box onto the sphere order: M[pair][G] (zero padded to ngp).
+#include <stdlib.h>
+
 #include <type_traits>
 
 #include "common.h"
@@ -23,37 +28,42 @@ namespace {
 
 constexpr int kTV = 4;              // valence bands per workgroup (one per wave)
 constexpr int kTC = 64 / kRows;     // conduction columns per workgroup (8)
-constexpr int kLdsMax = 163840;
 
-template <typename T, int ND, int K, bool STAGE>
+// LDS of one workgroup: a double buffer with the radix-R chunk (one b of the x3 split)
+// of the 64 conduction rows in flight, and Z of the current x2 group.
+template <typename T, int R, int K>
 struct PlaneLds {
-  static constexpr int rowp = ND + 1;   // padded row: the 8 rows read together fall on distinct banks
-  static constexpr size_t psic = STAGE ? (size_t)kTC * kRows * rowp * sizeof(cx<T>) : 0;
-  static constexpr size_t z = (size_t)kTV * kTC * kRows * K * sizeof(cx<T>);
-  static constexpr size_t total = psic + z;
+  static constexpr int rp = R + 1;   // padded chunk row: the 8 rows read together fall on distinct banks
+  static constexpr size_t chunk = (size_t)kTC * kRows * rp;
+  static constexpr size_t bytes = (2 * chunk + (size_t)kTV * kTC * kRows * K) * sizeof(cx<T>);
 };
 
-template <typename T, int ND, int K>
-constexpr bool stage_fits() {
-  return PlaneLds<T, ND, K, true>::total <= (size_t)kLdsMax;
+// Two resident workgroups per CU when the per-lane state (Q of IPL items, the stage-1
+// accumulators and one radix-R chunk) fits half the register file; one otherwise.
+template <typename T, int R, int K>
+constexpr int planes_min_blocks() {
+  constexpr int ipl = (kTV * kTC * K + 255) / 256;
+  constexpr int words = (ipl * K + K + R) * (int)(2 * sizeof(T) / 4);
+  return words + 24 <= 256 ? 2 : 1;
 }
 
-template <typename T, int ND, int R, int K, bool STAGE>
-__global__ __launch_bounds__(256) void k_pair_planes(const cx<T>* __restrict__ psi_v, const cx<T>* __restrict__ psi_c,
-                                                     int nvs, int ncs, const cx<T>* __restrict__ tw,
-                                                     cx<T>* __restrict__ q) {
+template <typename T, int ND, int R, int K, int MINB>
+__global__ __launch_bounds__(256, MINB) void k_pair_planes(const cx<T>* __restrict__ psi_v,
+                                                        const cx<T>* __restrict__ psi_c, int nvs, int ncs,
+                                                        const cx<T>* __restrict__ tw, cx<T>* __restrict__ q) {
   using V = cx<T>;
+  using L = PlaneLds<T, R, K>;
   constexpr int S = ND / R;
   constexpr int S2 = ND / kRows;
+  constexpr int NSTEP = S2 * S;
   constexpr int RCH = (K - 1) / 2;
   constexpr int NPAIR = kTV * kTC;
   constexpr int NITEM = NPAIR * K;
   constexpr int IPL = (NITEM + 255) / 256;
+  constexpr int PER = kTC * kRows * R / 256;   // chunk elements per thread
   constexpr size_t NPL = (size_t)ND * ND;
-  using L = PlaneLds<T, ND, K, STAGE>;
-  extern __shared__ __align__(16) unsigned char smem[];
-  V* s_psic = reinterpret_cast<V*>(smem);
-  V* s_z = reinterpret_cast<V*>(smem + L::psic);
+  __shared__ V s_c[2 * L::chunk];
+  __shared__ V s_z[NPAIR * kRows * K];
 
   const int nbc = ncs / kTC;
   const int nbv = nvs / kTV;
@@ -68,6 +78,27 @@ __global__ __launch_bounds__(256) void k_pair_planes(const cx<T>* __restrict__ p
   const int cl = lane / kRows;        // conduction column of this lane
   const int a2 = lane % kRows;        // row within the x2 group
 
+  // chunk staging: element e = row * R + a of step s (x2 group s / S, x3 group b = s % S)
+  const V* pc_base = psi_c + ((size_t)c0 * ND + x1) * NPL;
+  V pf[PER];
+  auto fetch = [&](int st) {
+    const int g2 = st / S, b = st % S;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + 256 * i;
+      const int row = e / R, a = e % R;
+      const int c = row / kRows, r = row % kRows;
+      pf[i] = pc_base[(size_t)c * ND * NPL + (size_t)(g2 * kRows + r) * ND + b * R + a];
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + 256 * i;
+      s_c[buf * L::chunk + (e / R) * L::rp + e % R] = pf[i];
+    }
+  };
+
   V qacc[IPL][K];
 #pragma unroll
   for (int r = 0; r < IPL; ++r)
@@ -75,46 +106,38 @@ __global__ __launch_bounds__(256) void k_pair_planes(const cx<T>* __restrict__ p
     for (int j = 0; j < K; ++j) qacc[r][j] = V{T(0), T(0)};
 
   const V* pv_plane = psi_v + ((size_t)(v0 + wv) * ND + x1) * NPL;
-  const V* pc_plane = psi_c + ((size_t)(c0 + cl) * ND + x1) * NPL;
+  fetch(0);
+  stash(0);
+  __syncthreads();
 
   for (int b2 = 0; b2 < S2; ++b2) {
-    if constexpr (STAGE) {
-      __syncthreads();
-      // stage the 8 rows of group b2 for the 8 columns: contiguous kRows*ND per column
-      constexpr int per_col = kRows * ND;
-      for (int i = tid; i < kTC * per_col; i += 256) {
-        const int c = i / per_col, o = i % per_col;
-        s_psic[(c * kRows + o / ND) * L::rowp + o % ND] =
-            psi_c[((size_t)(c0 + c) * ND + x1) * NPL + (size_t)b2 * per_col + o];
+    // ---------------- stage 1: one (pair, x2 row) line per lane
+    const V* rv = pv_plane + (size_t)(b2 * kRows + a2) * ND;
+    V acc[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) acc[j] = V{T(0), T(0)};
+    // kept rolled: unrolled, the valence loads of all S chunks would be hoisted and spill
+#pragma unroll 1
+    for (int b = 0; b < S; ++b) {
+      const int st = b2 * S + b;
+      if (st + 1 < NSTEP) fetch(st + 1);
+      const V* rc = s_c + (st & 1) * L::chunk + (cl * kRows + a2) * L::rp;
+      V x[R];
+#pragma unroll
+      for (int a = 0; a < R; ++a) x[a] = cmulc(rv[b * R + a], rc[a]);
+      dft<R>(x);
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const int n = j - RCH;
+        const V t = tw[((n * b) % ND + ND) % ND];
+        cmac(acc[j], t, x[((n % R) + R) % R]);
       }
-      __syncthreads();
-    } else {
+      if (st + 1 < NSTEP) stash((st + 1) & 1);
       __syncthreads();
     }
-    // ---------------- stage 1: one row per lane
-    {
-      const V* rv = pv_plane + (size_t)(b2 * kRows + a2) * ND;
-      const V* rc = STAGE ? s_psic + (cl * kRows + a2) * L::rowp : pc_plane + (size_t)(b2 * kRows + a2) * ND;
-      V acc[K];
+    V* z = s_z + ((wv * kTC + cl) * kRows + a2) * K;
 #pragma unroll
-      for (int j = 0; j < K; ++j) acc[j] = V{T(0), T(0)};
-#pragma unroll
-      for (int b = 0; b < S; ++b) {
-        V x[R];
-#pragma unroll
-        for (int a = 0; a < R; ++a) x[a] = cmulc(rv[b * R + a], rc[b * R + a]);
-        dft<R>(x);
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const int n = j - RCH;
-          const V t = tw[((n * b) % ND + ND) % ND];
-          cmac(acc[j], t, x[((n % R) + R) % R]);
-        }
-      }
-      V* z = s_z + ((wv * kTC + cl) * kRows + a2) * K;
-#pragma unroll
-      for (int j = 0; j < K; ++j) z[j] = acc[j];
-    }
+    for (int j = 0; j < K; ++j) z[j] = acc[j];
     __syncthreads();
     // ---------------- stage 2: one (pair, n3) line per item, 8-point split along x2
 #pragma unroll
@@ -134,6 +157,7 @@ __global__ __launch_bounds__(256) void k_pair_planes(const cx<T>* __restrict__ p
         }
       }
     }
+    // s_z is rewritten only after the S barriers of the next group's stage 1
   }
   // ---------------- write this plane's Q[pair][p1][n2][n3]
   const int p1 = (x1 % S) * R + x1 / S;
@@ -193,18 +217,13 @@ hipError_t run_planes(const Geom& g, const void* psi_v, const void* psi_c, int n
                       hipStream_t st) {
   const cx<T>* tw = std::is_same<T, double>::value ? (const cx<T>*)g.d_tw64 : (const cx<T>*)g.d_tw32;
   const int nblk = ND * (nvs / kTV) * (ncs / kTC);
-  if constexpr (stage_fits<T, ND, K>()) {
-    using L = PlaneLds<T, ND, K, true>;
-    auto kern = k_pair_planes<T, ND, R, K, true>;
-    hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L::total);
-    kern<<<nblk, 256, L::total, st>>>((const cx<T>*)psi_v, (const cx<T>*)psi_c, nvs, ncs, tw, (cx<T>*)q);
-  } else {
-    using L = PlaneLds<T, ND, K, false>;
-    static_assert(L::total <= (size_t)kLdsMax, "pair kernel LDS");
-    auto kern = k_pair_planes<T, ND, R, K, false>;
-    hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L::total);
-    kern<<<nblk, 256, L::total, st>>>((const cx<T>*)psi_v, (const cx<T>*)psi_c, nvs, ncs, tw, (cx<T>*)q);
-  }
+  static const int force = getenv("GWCHI0_PLANES_MINB") ? atoi(getenv("GWCHI0_PLANES_MINB")) : 0;
+  if (force == 2 || (force == 0 && planes_min_blocks<T, R, K>() == 2))
+    k_pair_planes<T, ND, R, K, 2><<<nblk, 256, 0, st>>>((const cx<T>*)psi_v, (const cx<T>*)psi_c, nvs, ncs, tw,
+                                                       (cx<T>*)q);
+  else
+    k_pair_planes<T, ND, R, K, 1><<<nblk, 256, 0, st>>>((const cx<T>*)psi_v, (const cx<T>*)psi_c, nvs, ncs, tw,
+                                                       (cx<T>*)q);
   return hipGetLastError();
 }
 

@@ -2,7 +2,8 @@
 
 Tolerances: FP64 mode 1e-10 relative (Frobenius and max-abs over max |chi0|);
 pair densities 1e-12 relative; FP32 mode 2e-5 relative (float32 pair transform,
-float32 MFMA accumulation within a chunk of pairs)."""
+float32 MFMA accumulation within a chunk of pairs); split-bf16 x3 mode 1e-4
+(each product keeps about 16 bits of mantissa)."""
 import numpy as np
 import pytest
 
@@ -87,6 +88,27 @@ def test_chi0_c1_fp32(g):
     assert fro <= 2e-5 and mx <= 2e-5, (fro, mx)
 
 
+def test_chi0_c1_bf16x3(g):
+    # split-bf16 x3 products carry ~2^-16 relative error each; float32 accumulation
+    case = make_case(0)
+    chi = g.chi0(case, prec="bf16x3")[0]
+    ref = ref_chi0(case)[0]
+    fro, mx = rel_err(chi, ref)
+    assert fro <= 1e-4 and mx <= 1e-4, (fro, mx)
+    assert np.abs(chi - chi.conj().T).max() <= 1e-14 * np.abs(chi).max()
+
+
+def test_chi0_dynamic_bf16x3(g):
+    case = make_case(0, nv=8, nc=60)
+    om = np.array([0.0, 7.0]) / EV
+    d = 0.1 / EV
+    chi = g.chi0(case, omegas=om, delta=d, prec="bf16x3")
+    ref = ref_chi0(case, om, d)
+    for i in range(len(om)):
+        fro, mx = rel_err(chi[i], ref[i])
+        assert fro <= 1e-4 and mx <= 1e-4, (i, fro, mx)
+
+
 @pytest.mark.parametrize("nv,nc", [(1, 1), (5, 13), (7, 65)])
 def test_chi0_ragged_fp64(g, nv, nc):
     case = make_case(0, nv=nv, nc=nc)
@@ -126,7 +148,8 @@ def test_chi0_grouped_fp64(g):
 
 
 @pytest.mark.parametrize("cfg,prec,tol", [(1, "fp64", 1e-10), (1, "fp32", 2e-5), (2, "fp32", 2e-5),
-                                          (4, "fp32", 2e-5)])
+                                          (4, "fp32", 2e-5), (1, "bf16x3", 1e-4), (2, "bf16x3", 1e-4),
+                                          (4, "bf16x3", 1e-4)])
 def test_chi0_config_geometry_subset(g, cfg, prec, tol):
     # the configs' grids and dielectric spheres (72^3 / NG 2000, 96^3 / 4000, 128^3 / 8000)
     # on a few bands the oracle finishes in seconds
