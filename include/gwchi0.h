@@ -146,6 +146,25 @@ gw_status gw_chi0_workspace_size(gw_ctx* ctx, const gw_chi0_problem* probs, int 
 gw_status gw_chi0_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, const double* omega,
                         double delta, gw_precision prec, void* workspace, size_t ws_bytes, void* chi0);
 
+/* Adjoint of gw_chi0_build for a real loss L (same problems, frequencies, precision and
+ * workspace size as the forward call).
+ *   grad_chi0   device complex128, the layout of gw_chi0_build's output, holding
+ *               chibar = dL/dRe chi0 + i dL/dIm chi0.
+ *   grad_e_v    device, sum over problems of nv doubles: dL/dE_v (nullable = skip).
+ *   grad_e_col  device, sum over problems of ncol doubles: dL/dE_col, which for a window
+ *               column is the derivative with respect to its energy E_i (nullable).
+ *   grad_n_col  device, same length: dL/dn_col, the derivative with respect to the
+ *               weight g(E_i) dE_i of Eq. (energyintegration) (nullable).
+ *   grad_coef_v, grad_coef_c   must be NULL (coefficient gradients: GW_EUNSUPPORTED).
+ * With s_p = m_p^H chibar m_p (pair densities recomputed, never stored for all pairs):
+ * dL/dE_v = sum_c Re(conj(s) dw/dx), dL/dE_c = -sum_v Re(conj(s) dw/dx),
+ * dL/dn_c = sum_v Re(conj(s) dw/dn), summed over frequencies, x = E_v - E_c and w the
+ * energy factor of Eq. (chi0).  Reductions are float64 in a fixed order. */
+gw_status gw_chi0_backward(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, const double* omega,
+                           double delta, gw_precision prec, void* workspace, size_t ws_bytes, const void* grad_chi0,
+                           double* grad_e_v, double* grad_e_col, double* grad_n_col, void* grad_coef_v,
+                           void* grad_coef_c);
+
 /* Workspace bytes for gw_pair_density with an nvs x ncs block. */
 gw_status gw_pair_density_workspace_size(gw_ctx* ctx, const gw_chi0_problem* prob, int nvs, int ncs,
                                          gw_precision prec, size_t* bytes);

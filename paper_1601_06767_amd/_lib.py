@@ -53,6 +53,8 @@ _sig("gw_chi0_workspace_size", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int
                                          C.POINTER(C.c_size_t)])
 _sig("gw_chi0_build", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, dp, C.c_double, C.c_int, vp,
                                 C.c_size_t, vp])
+_sig("gw_chi0_backward", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, dp, C.c_double, C.c_int,
+                                   vp, C.c_size_t, vp, vp, vp, vp, vp, vp])
 _sig("gw_pair_density_workspace_size", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, C.c_int,
                                                  C.POINTER(C.c_size_t)])
 _sig("gw_pair_density", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
@@ -71,7 +73,7 @@ STAGES = ["band", "planes", "finish", "weights", "contract", "finalize", "eps_in
 
 EXPORTED = ["gw_ctx_set_timing", "gw_ctx_stage_times",
             "gw_version", "gw_ctx_create", "gw_ctx_destroy", "gw_last_error", "gw_geom_create", "gw_geom_destroy",
-            "gw_chi0_workspace_size", "gw_chi0_build", "gw_pair_density_workspace_size", "gw_pair_density",
+            "gw_chi0_workspace_size", "gw_chi0_build", "gw_chi0_backward", "gw_pair_density_workspace_size", "gw_pair_density",
             "gw_eps_inv_workspace_size", "gw_eps_inv", "gw_eps_inv_status", "gw_eps_inv_backward",
             "gw_group_windows"]
 
@@ -183,6 +185,26 @@ def gw_chi0_build(ctx, problems, ngs: Sequence[int], omegas: Sequence[float], de
         res.append(out[o: o + len(om) * g * g].view(len(om), g, g))
         o += len(om) * g * g
     return res
+
+
+def gw_chi0_backward(ctx, problems, omegas: Sequence[float], delta: float, prec: int, grad_chi0, workspace=None,
+                     want=(True, True, True)):
+    """(dL/dE_v, dL/dE_col, dL/dn_col) over all problems (concatenated float64 tensors, None where
+    not wanted) from grad_chi0 in gw_chi0_build's output layout."""
+    import torch
+    arr = _probs(problems)
+    om = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64))
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if workspace is None:
+        workspace = torch.empty(gw_chi0_workspace_size(ctx, arr, len(om), prec), dtype=torch.uint8, device=dev)
+    nv = sum(p.nv for p in arr)
+    nc = sum(p.ncol for p in arr)
+    g = [torch.zeros(n, dtype=torch.float64, device=dev) if w else None for n, w in zip((nv, nc, nc), want)]
+    gc = grad_chi0.contiguous()
+    _check(lib.gw_chi0_backward(ctx, arr, len(arr), len(om), om.ctypes.data_as(dp), float(delta), prec,
+                                _ptr(workspace), workspace.numel(), _ptr(gc), _ptr(g[0]), _ptr(g[1]), _ptr(g[2]),
+                                None, None), ctx)
+    return tuple(g)
 
 
 def gw_pair_density_workspace_size(ctx, problem, nvs: int, ncs: int, prec: int) -> int:

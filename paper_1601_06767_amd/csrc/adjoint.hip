@@ -1,0 +1,240 @@
+// Adjoint of the band sum of Eq. (chi0) with respect to the band energies, the
+// column (window) energies and the column multiplicities.
+//
+// For a real loss L with chibar(w) = dL/dRe chi0(w) + i dL/dIm chi0(w):
+//   s_p(w)  = m_p^H chibar(w) m_p                  (wbar of pair p, complex)
+//   dL/dx_p = sum_w Re(conj(s_p) dw_p/dx),  dL/dn_p = sum_w Re(conj(s_p) dw_p/dn),  x = E_v - E_c
+//   dL/dE_v = sum_c dL/dx_vc,  dL/dE_c = -sum_v dL/dx_vc,  dL/dn_c = sum_v dL/dn_vc.
+// The pair densities m_p are recomputed chunk by chunk (never stored for all pairs).
+// k_adjoint: Y = M chibar^T on MFMA (64 pairs x 64 G per workgroup, inner G'), fused
+// with the row dot sum_G conj(M[p][G]) Y[p][G] over the tile's 64 G; the per-tile
+// partial sums are reduced in float64 in fixed order by k_adjoint_pairs.
+#include <algorithm>
+#include <type_traits>
+
+#include "common.h"
+#include "internal.h"
+
+namespace gw {
+
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct AMfma;
+template <> struct AMfma<double> {
+  using acc = f64x4;
+  static __device__ __forceinline__ acc run(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
+};
+template <> struct AMfma<float> {
+  using acc = f32x4;
+  static __device__ __forceinline__ acc run(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
+};
+
+constexpr int AT = 64, AK = 16;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_adjoint(const cx<T>* __restrict__ m, int npair, int ng, int ngp,
+                                                 const double2* __restrict__ gbar, double2* __restrict__ part) {
+  using V = cx<T>;
+  using A4 = typename AMfma<T>::acc;
+  __shared__ V sA[AK][AT + 1];   // M[p0 + i][G' = k]
+  __shared__ V sB[AK][AT + 1];   // chibar[G0 + j][G' = k]
+  __shared__ double2 sred[2][AT];
+  const int ntg = ngp / AT;
+  const int p0 = (blockIdx.x / ntg) * AT;
+  const int tg = blockIdx.x % ntg;
+  const int q0 = tg * AT;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
+  A4 cre[2][2], cim[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cre[i][j] = A4{0, 0, 0, 0};
+      cim[i][j] = A4{0, 0, 0, 0};
+    }
+  for (int k0 = 0; k0 < ng; k0 += AK) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < (AK * AT) / 256; ++r) {
+      const int e = tid + 256 * r;
+      const int row = e / AK, kk = e % AK;   // consecutive threads: consecutive G' of one row
+      V a{T(0), T(0)}, b{T(0), T(0)};
+      if (k0 + kk < ng) {
+        if (p0 + row < npair) a = m[(size_t)(p0 + row) * ngp + k0 + kk];
+        if (q0 + row < ng) {
+          const double2 x = gbar[(size_t)(q0 + row) * ng + k0 + kk];
+          b = V{T(x.x), T(x.y)};
+        }
+      }
+      sA[kk][row] = a;
+      sB[kk][row] = b;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < AK / 4; ++s) {
+      const int k = 4 * s + lk;
+      V a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = sA[k][32 * wr + 16 * i + li];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = sB[k][32 * wc + 16 * j + li];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          cre[i][j] = AMfma<T>::run(a[i].x, b[j].x, cre[i][j]);
+          cre[i][j] = AMfma<T>::run(-a[i].y, b[j].y, cre[i][j]);
+          cim[i][j] = AMfma<T>::run(a[i].x, b[j].y, cim[i][j]);
+          cim[i][j] = AMfma<T>::run(a[i].y, b[j].x, cim[i][j]);
+        }
+    }
+  }
+  // epilogue: per pair row, sum over this tile's G of conj(M[p][G]) Y[p][G]
+  double2 rs[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) rs[i][r] = double2{0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int pr = 32 * wr + 16 * i + AMfma<T>::row(lk, r);
+        const int gc = q0 + 32 * wc + 16 * j + li;
+        if (p0 + pr < npair && gc < ng) {
+          const V mv = m[(size_t)(p0 + pr) * ngp + gc];
+          const double yr = (double)cre[i][j][r], yi = (double)cim[i][j][r];
+          rs[i][r].x += (double)mv.x * yr + (double)mv.y * yi;
+          rs[i][r].y += (double)mv.x * yi - (double)mv.y * yr;
+        }
+      }
+  // reduce over the 16 lanes li that share a row (xor shuffles within the 16-lane group)
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int o = 8; o >= 1; o >>= 1) {
+        rs[i][r].x += __shfl_xor(rs[i][r].x, o, 64);
+        rs[i][r].y += __shfl_xor(rs[i][r].y, o, 64);
+      }
+  if (li == 0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sred[wc][32 * wr + 16 * i + AMfma<T>::row(lk, r)] = rs[i][r];
+  }
+  __syncthreads();
+  if (tid < AT && p0 + tid < npair) {
+    const double2 a = sred[0][tid], b = sred[1][tid];
+    part[(size_t)(p0 + tid) * ntg + tg] = double2{a.x + b.x, a.y + b.y};
+  }
+}
+
+// Per pair: s = sum over G tiles (fixed order), then dL/dx and dL/dn accumulated over w.
+__global__ void k_adjoint_pairs(const double2* __restrict__ part, int ntg, const double* __restrict__ e_v, int nv,
+                                int nvs, const double* __restrict__ e_col, const double* __restrict__ n_col, int c0,
+                                int ncol, int cc, double omega, double delta, double* __restrict__ dx,
+                                double* __restrict__ dn) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nvs * cc) return;
+  const int v = p / cc, c = c0 + p % cc;
+  double2 s{0.0, 0.0};
+  for (int t = 0; t < ntg; ++t) {
+    const double2 x = part[(size_t)p * ntg + t];
+    s.x += x.x;
+    s.y += x.y;
+  }
+  if (v >= nv || c >= ncol) return;
+  const double n = n_col ? n_col[c] : 1.0;
+  const double x = e_v[v] - e_col[c];
+  const double a = x - omega, b = x + omega;
+  const double da = a * a + delta * delta, db = b * b + delta * delta;
+  // 1/(a + i d) = (a - i d)/da;  (a + i d)^-2 = (a^2 - d^2 - 2 i a d)/da^2
+  const double2 ia{a / da, -delta / da}, ib{b / db, -delta / db};
+  const double2 ia2{(a * a - delta * delta) / (da * da), -2.0 * a * delta / (da * da)};
+  const double2 ib2{(b * b - delta * delta) / (db * db), -2.0 * b * delta / (db * db)};
+  const double2 dwdx{-0.5 * n * (ia2.x + ib2.x), -0.5 * n * (ia2.y + ib2.y)};
+  const double2 dwdn{0.5 * (ia.x + ib.x), 0.5 * (ia.y + ib.y)};
+  // Re(conj(s) z) = s.x z.x + s.y z.y
+  dx[p] += s.x * dwdx.x + s.y * dwdx.y;
+  dn[p] += s.x * dwdn.x + s.y * dwdn.y;
+}
+
+// Deterministic reductions of one chunk: each valence band adds the sum over the chunk's
+// columns; each column (present in exactly one chunk) gets the sum over valence bands.
+__global__ void k_adjoint_reduce(const double* __restrict__ dx, const double* __restrict__ dn, int nv, int cc,
+                                 int c0, int ncol, double* __restrict__ g_ev, double* __restrict__ g_ec,
+                                 double* __restrict__ g_n) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nv && g_ev) {
+    double acc = 0.0;
+    for (int c = 0; c < cc && c0 + c < ncol; ++c) acc += dx[(size_t)t * cc + c];
+    g_ev[t] += acc;
+  }
+  if (t < cc && c0 + t < ncol) {
+    double ax = 0.0, an = 0.0;
+    for (int v = 0; v < nv; ++v) {
+      ax += dx[(size_t)v * cc + t];
+      an += dn[(size_t)v * cc + t];
+    }
+    if (g_ec) g_ec[c0 + t] = -ax;
+    if (g_n) g_n[c0 + t] = an;
+  }
+}
+
+__global__ void k_fill_f64(double* __restrict__ p, size_t n, double v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+}  // namespace
+
+hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const unsigned nb = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+  k_fill_f64<<<nb, 256, 0, st>>>(p, n, v);
+  return hipGetLastError();
+}
+
+size_t adjoint_partial_bytes(int npair, int ngp) { return (size_t)npair * (ngp / AT) * sizeof(double2); }
+
+template <typename T>
+hipError_t launch_adjoint(const void* m, int npair, int ng, int ngp, const double2* gbar, double2* part,
+                          hipStream_t st) {
+  const int ntg = ngp / AT;
+  const int nb = ((npair + AT - 1) / AT) * ntg;
+  k_adjoint<T><<<nb, 256, 0, st>>>((const cx<T>*)m, npair, ng, ngp, gbar, part);
+  return hipGetLastError();
+}
+template hipError_t launch_adjoint<double>(const void*, int, int, int, const double2*, double2*, hipStream_t);
+template hipError_t launch_adjoint<float>(const void*, int, int, int, const double2*, double2*, hipStream_t);
+
+hipError_t launch_adjoint_pairs(const double2* part, int ngp, const double* e_v, int nv, int nvs, const double* e_col,
+                                const double* n_col, int c0, int ncol, int cc, double omega, double delta, double* dx,
+                                double* dn, hipStream_t st) {
+  const int np = nvs * cc;
+  k_adjoint_pairs<<<(np + 255) / 256, 256, 0, st>>>(part, ngp / AT, e_v, nv, nvs, e_col, n_col, c0, ncol, cc, omega,
+                                                     delta, dx, dn);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_reduce(const double* dx, const double* dn, int nv, int cc, int c0, int ncol, double* g_ev,
+                                 double* g_ec, double* g_n, hipStream_t st) {
+  const int n = nv > cc ? nv : cc;
+  k_adjoint_reduce<<<(n + 255) / 256, 256, 0, st>>>(dx, dn, nv, cc, c0, ncol, g_ev, g_ec, g_n);
+  return hipGetLastError();
+}
+
+}  // namespace gw

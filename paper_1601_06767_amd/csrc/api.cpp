@@ -49,6 +49,7 @@ struct ChiPlan {
   int nomega = 1;
   int band_batch = 32;
   size_t off_psiv = 0, off_psic = 0, off_scr = 0, off_q = 0, off_m = 0, off_w = 0, off_acc = 0, total = 0;
+  size_t off_part = 0, off_dx = 0, off_dn = 0;   // backward only
 };
 
 constexpr int kPairTarget = 32768;
@@ -82,6 +83,9 @@ ChiPlan make_plan(const Geom& g, int nv, int ncol, int nomega, bool complex_w, g
   p.off_m = take((size_t)p.npair * g.ngp * p.csz);
   p.off_w = take((size_t)2 * p.npair * sizeof(double));
   p.off_acc = take((size_t)nomega * p.nparts * p.ksplit * g.ngp * g.ngp * sizeof(double2));
+  p.off_part = take(gw::adjoint_partial_bytes(p.npair, g.ngp));
+  p.off_dx = take((size_t)p.npair * sizeof(double));
+  p.off_dn = take((size_t)p.npair * sizeof(double));
   p.total = o;
   return p;
 }
@@ -392,6 +396,79 @@ gw_status gw_chi0_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, in
       return GW_OK;
     };
     st = run();
+  }
+  (void)hipSetDevice(prev);
+  return st;
+}
+
+gw_status gw_chi0_backward(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, const double* omega,
+                           double delta, gw_precision prec, void* workspace, size_t ws_bytes, const void* grad_chi0,
+                           double* grad_e_v, double* grad_e_col, double* grad_n_col, void* grad_coef_v,
+                           void* grad_coef_c) {
+  if (!ctx) return GW_EINVAL;
+  if (!probs || nprob < 1 || nomega < 1 || !omega || !grad_chi0 || !workspace)
+    return fail(ctx, GW_EINVAL, "bad arguments");
+  if (!(delta >= 0.0)) return fail(ctx, GW_EINVAL, "delta must be >= 0");
+  if (prec != GW_FP64 && prec != GW_FP32 && prec != GW_BF16X3) return fail(ctx, GW_EINVAL, "bad precision");
+  if (grad_coef_v || grad_coef_c)
+    return fail(ctx, GW_EUNSUPPORTED, "gradients with respect to the coefficients are not built");
+  for (int i = 0; i < nprob; ++i) {
+    gw_status s = check_problem(ctx, probs[i]);
+    if (s != GW_OK) return s;
+  }
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(ctx->device);
+  char* ws = (char*)workspace;
+  const char* gin = (const char*)grad_chi0;
+  size_t off_ev = 0, off_ec = 0;
+  gw_status st = GW_OK;
+  for (int ip = 0; ip < nprob && st == GW_OK; ++ip) {
+    const gw_chi0_problem& p = probs[ip];
+    const Geom& g = p.geom->g;
+    const ChiPlan pl = make_plan(g, p.nv, p.ncol, nomega, delta > 0.0, prec);
+    if (pl.total > ws_bytes) {
+      st = fail(ctx, GW_EINVAL, "workspace too small: need " + std::to_string(pl.total) + " bytes");
+      break;
+    }
+    double* gev = grad_e_v ? grad_e_v + off_ev : nullptr;
+    double* gec = grad_e_col ? grad_e_col + off_ec : nullptr;
+    double* gn = grad_n_col ? grad_n_col + off_ec : nullptr;
+    auto run = [&]() -> gw_status {
+      gw::StageScope sc(ctx, gw::kStageBackward);
+      if (gev) GW_HIP(ctx, gw::launch_fill_f64(gev, p.nv, 0.0, ctx->stream));
+      gw_status s = band_to_real(ctx, pl, g, (const double2*)p.coef_v, p.nv, nullptr, 0, p.nv, pl.nvs, ws,
+                                 ws + pl.off_psiv);
+      if (s != GW_OK) return s;
+      double* dx = (double*)(ws + pl.off_dx);
+      double* dn = (double*)(ws + pl.off_dn);
+      double2* part = (double2*)(ws + pl.off_part);
+      for (int c0 = 0; c0 < p.ncol; c0 += pl.cc) {
+        s = band_to_real(ctx, pl, g, (const double2*)p.coef_c, p.nband, p.col_band, c0, p.ncol, pl.cc, ws,
+                         ws + pl.off_psic);
+        if (s != GW_OK) return s;
+        s = pair_block(ctx, pl, g, ws, pl.nvs, pl.cc);
+        if (s != GW_OK) return s;
+        GW_HIP(ctx, gw::launch_fill_f64(dx, pl.npair, 0.0, ctx->stream));
+        GW_HIP(ctx, gw::launch_fill_f64(dn, pl.npair, 0.0, ctx->stream));
+        for (int iw = 0; iw < nomega; ++iw) {
+          const double2* gb = (const double2*)gin + (size_t)iw * g.ng * g.ng;
+          hipError_t e = pl.fp64 ? gw::launch_adjoint<double>(ws + pl.off_m, pl.npair, g.ng, g.ngp, gb, part,
+                                                              ctx->stream)
+                                 : gw::launch_adjoint<float>(ws + pl.off_m, pl.npair, g.ng, g.ngp, gb, part,
+                                                             ctx->stream);
+          GW_HIP(ctx, e);
+          GW_HIP(ctx, gw::launch_adjoint_pairs(part, g.ngp, p.e_v, p.nv, pl.nvs, p.e_col, p.n_col, c0, p.ncol, pl.cc,
+                                               omega[iw], delta, dx, dn, ctx->stream));
+        }
+        GW_HIP(ctx, gw::launch_adjoint_reduce(dx, dn, p.nv, pl.cc, c0, p.ncol, gev, gec, gn, ctx->stream));
+      }
+      return GW_OK;
+    };
+    st = run();
+    gin += (size_t)nomega * g.ng * g.ng * sizeof(double2);
+    off_ev += p.nv;
+    off_ec += p.ncol;
   }
   (void)hipSetDevice(prev);
   return st;

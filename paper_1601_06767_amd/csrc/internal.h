@@ -125,4 +125,16 @@ hipError_t launch_eps_inv_backward(int n, const double* v, const double2* z, con
                                    void* ws, hipStream_t st);
 hipError_t launch_flag_clear(int* flag, hipStream_t st);
 
+// ---------------------------------------------------------------- adjoint
+size_t adjoint_partial_bytes(int npair, int ngp);
+template <typename T>
+hipError_t launch_adjoint(const void* m, int npair, int ng, int ngp, const double2* gbar, double2* part,
+                          hipStream_t st);
+hipError_t launch_adjoint_pairs(const double2* part, int ngp, const double* e_v, int nv, int nvs, const double* e_col,
+                                const double* n_col, int c0, int ncol, int cc, double omega, double delta, double* dx,
+                                double* dn, hipStream_t st);
+hipError_t launch_adjoint_reduce(const double* dx, const double* dn, int nv, int cc, int c0, int ncol, double* g_ev,
+                                 double* g_ec, double* g_n, hipStream_t st);
+hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t st);
+
 }  // namespace gw

@@ -76,3 +76,14 @@ def test_context_create_without_gpu_reports_error():
     st = p._lib.lib.gw_ctx_create(0, None, ctypes.byref(out))
     assert st != 0 and not out.value
     assert p.gw_last_error(None)
+
+
+def test_torch_complex_gradient_convention():
+    # the binding hands torch's complex gradients straight to the C ABI, whose convention is
+    # dL/dRe + i dL/dIm; check torch's on a linear real loss
+    import torch
+    z = torch.tensor([1.0 + 2.0j, -0.5 + 0.25j], dtype=torch.complex128, requires_grad=True)
+    a = torch.tensor([3.0, -1.0], dtype=torch.float64)
+    b = torch.tensor([0.5, 2.0], dtype=torch.float64)
+    (z.real * a + z.imag * b).sum().backward()
+    assert torch.allclose(z.grad, torch.complex(a, b))
