@@ -133,7 +133,10 @@ typedef struct {
 gw_status gw_chi0_workspace_size(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega,
                                  gw_precision prec, size_t* bytes);
 
-/* chi0 of Eq. (chi0) for nprob q-points and nomega real frequencies.
+/* chi0 of Eq. (chi0) for nprob q-points (each with its own geometry and dielectric
+ * sphere size) and nomega real frequencies.  Up to 16 q-points run together: after the
+ * pair densities of one conduction chunk exist for all of them, a single persistent
+ * launch contracts every (q-point, frequency, tile) item, largest spheres first.
  *   omega   host, nomega doubles (read before the call returns).  omega[i] == 0 with
  *           delta == 0 is the static case of Eq. (chi02): a Hermitian, negative
  *           semidefinite matrix.  With delta == 0 every chi0(omega) is Hermitian.
@@ -164,6 +167,22 @@ gw_status gw_chi0_backward(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob,
                            double delta, gw_precision prec, void* workspace, size_t ws_bytes, const void* grad_chi0,
                            double* grad_e_v, double* grad_e_col, double* grad_n_col, void* grad_coef_v,
                            void* grad_coef_c);
+
+/* Graph mode (enable != 0): gw_chi0_build captures its launch sequence into a HIP
+ * graph the first time it sees a given argument signature (problem records, frequency
+ * values, delta, precision, workspace and output pointers) and replays the graph on
+ * later identical calls; the data behind the pointers may change between calls.
+ * Needs a context on a non-null stream.  Disabling drops the cached graphs. */
+gw_status gw_ctx_set_graph(gw_ctx* ctx, int enable);
+
+/* Launch-shape tuner: on the first conduction chunk of each problem, times the pair
+ * kernel compiled for one or two resident workgroups per CU and the contraction with
+ * 1..32 pair-range splits, and keeps the fastest per problem shape in the context.
+ * Later gw_chi0_workspace_size / gw_chi0_build calls use the tuned shapes (query the
+ * workspace size again after tuning).  Synchronises the stream; workspace as for
+ * gw_chi0_build. */
+gw_status gw_tune(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, gw_precision prec,
+                  void* workspace, size_t ws_bytes);
 
 /* Workspace bytes for gw_pair_density with an nvs x ncs block. */
 gw_status gw_pair_density_workspace_size(gw_ctx* ctx, const gw_chi0_problem* prob, int nvs, int ncs,

@@ -1,0 +1,573 @@
+// Host driver of the band sum of Eq. (chi0): workspace layout, the launch sequence
+// of gw_chi0_build / gw_chi0_backward / gw_pair_density, the launch-shape tuner and
+// the graph cache.
+//
+// A build processes up to kMaxBatch q-points together.  Each q-point keeps its
+// real-space valence bands, its pair densities of the current conduction chunk, its
+// weights for every frequency and its float64 partial sums resident; the conduction
+// chunks, the band-transform scratch and the pair-transform intermediate are shared
+// and reused q-point after q-point.  After the pair densities of chunk j exist for
+// every q-point, one persistent contraction launch covers all (q, frequency, part,
+// tile, pair range) items of that chunk.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using gw::Geom;
+
+namespace {
+
+size_t round_up(size_t x, size_t m) { return (x + m - 1) / m * m; }
+
+constexpr int kPairTarget = 32768;   // band pairs per conduction chunk
+constexpr int kBandBatch = 32;       // bands per band-transform launch group
+
+int mode_of(gw_precision p) { return p == GW_FP64 ? 0 : (p == GW_FP32 ? 1 : 2); }
+
+std::string shape_key(const Geom& g, int nv, int ncol, gw_precision prec) {
+  char b[160];
+  snprintf(b, sizeof b, "nd%d_K%d_ngp%d_nv%d_nc%d_p%d", g.nd, g.K, g.ngp, nv, ncol, (int)prec);
+  return b;
+}
+
+struct ProbPlan {
+  const gw_chi0_problem* p = nullptr;
+  int nvs = 0, cc = 0, npair = 0, ksplit = 1, ntl = 0, minb = 0;
+  size_t off_psiv = 0, off_m = 0, off_w = 0, off_acc = 0, acc_one = 0;
+};
+
+struct Layout {
+  bool fp64 = true;
+  size_t csz = 16;
+  int nparts = 1, nomega = 1, mode = 0;
+  std::vector<ProbPlan> pp;
+  size_t off_psic = 0, off_scr = 0, off_q = 0, off_part = 0, off_dx = 0, off_dn = 0, off_counter = 0, total = 0;
+  size_t scr_a = 0;
+  int max_cc = 0;
+};
+
+// Contraction work items of one problem per job (frequency, part).
+int items_per_job(const ProbPlan& q) { return q.ntl * q.ksplit; }
+
+Layout make_layout(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, bool complex_w, gw_precision prec,
+                   bool backward, int force_ksplit = 0) {
+  Layout L;
+  L.fp64 = prec == GW_FP64;
+  L.csz = L.fp64 ? 16 : 8;
+  L.nparts = complex_w ? 2 : 1;
+  L.nomega = nomega;
+  L.mode = mode_of(prec);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = round_up(o + bytes, 256);
+    return at;
+  };
+  long long items = 0;
+  for (int i = 0; i < nprob; ++i) {
+    const Geom& g = probs[i].geom->g;
+    ProbPlan q;
+    q.p = &probs[i];
+    q.nvs = (int)round_up(probs[i].nv, 4);
+    int cc = std::max(8, (kPairTarget / q.nvs) / 8 * 8);
+    q.cc = std::min<int>(cc, (int)round_up(probs[i].ncol, 8));
+    q.npair = q.nvs * q.cc;
+    const int nt = g.ngp / gw::kTile;
+    q.ntl = nt * (nt + 1) / 2;
+    items += (long long)q.ntl * nomega * L.nparts;
+    L.pp.push_back(q);
+  }
+  // split the pair ranges until the batch has about 8 items per CU (or a tuned choice)
+  const long long want = 8LL * 256;
+  int ks = items >= want ? 1 : (int)std::min<long long>(32, (want + items - 1) / items);
+  for (auto& q : L.pp) {
+    int k = ks;
+    auto it = ctx->tune.find(shape_key(q.p->geom->g, q.p->nv, q.p->ncol, prec));
+    if (it != ctx->tune.end()) {
+      q.minb = it->second.first;
+      k = it->second.second;
+    }
+    if (force_ksplit) k = force_ksplit;
+    q.ksplit = std::max(1, std::min(k, std::max(1, q.npair / 64)));
+  }
+  size_t max_psic = 0, max_scr = 0, max_q = 0, max_part = 0, max_np = 0;
+  for (auto& q : L.pp) {
+    const Geom& g = q.p->geom->g;
+    const size_t npts = (size_t)g.nd * g.nd * g.nd;
+    q.off_psiv = take((size_t)q.nvs * npts * L.csz);
+    q.off_m = take((size_t)q.npair * g.ngp * L.csz);
+    q.off_w = take((size_t)nomega * L.nparts * q.npair * sizeof(double));
+    q.acc_one = (size_t)q.ksplit * g.ngp * g.ngp * sizeof(double2);
+    q.off_acc = backward ? 0 : take(q.acc_one * nomega * L.nparts);
+    max_psic = std::max(max_psic, (size_t)q.cc * npts * L.csz);
+    max_scr = std::max(max_scr, gw::band_scratch_bytes(g, kBandBatch, L.fp64));
+    L.scr_a = std::max(L.scr_a, (size_t)kBandBatch * g.W * g.W * g.nd * L.csz);
+    max_q = std::max(max_q, (size_t)q.npair * g.nd * g.K * g.K * L.csz);
+    max_part = std::max(max_part, gw::adjoint_partial_bytes(q.npair, g.ngp));
+    max_np = std::max(max_np, (size_t)q.npair);
+    L.max_cc = std::max(L.max_cc, q.cc);
+  }
+  L.off_psic = take(max_psic);
+  L.off_scr = take(max_scr);
+  L.off_q = take(max_q);
+  if (backward) {
+    L.off_part = take(max_part);
+    L.off_dx = take(max_np * sizeof(double));
+    L.off_dn = take(max_np * sizeof(double));
+  }
+  L.off_counter = take(256);
+  L.total = o;
+  return L;
+}
+
+gw_status band_to_real(gw_ctx* ctx, const Layout& L, const Geom& g, const double2* coef, int nrows,
+                       const int32_t* band_idx, int band0, int nvalid, int nslot, char* ws, char* psi) {
+  const size_t npts = (size_t)g.nd * g.nd * g.nd;
+  for (int s0 = 0; s0 < nslot; s0 += kBandBatch) {
+    const int ns = std::min(kBandBatch, nslot - s0);
+    void* tA = ws + L.off_scr;
+    void* tB = ws + L.off_scr + L.scr_a;
+    void* out = psi + (size_t)s0 * npts * L.csz;
+    gw::StageScope sc(ctx, gw::kStageBand);
+    hipError_t e = L.fp64 ? gw::launch_band_to_real<double>(g, coef, nrows, band_idx, band0 + s0, nvalid, ns, tA, tB,
+                                                            out, ctx->stream)
+                          : gw::launch_band_to_real<float>(g, coef, nrows, band_idx, band0 + s0, nvalid, ns, tA, tB,
+                                                           out, ctx->stream);
+    GW_HIP(ctx, e);
+  }
+  return GW_OK;
+}
+
+// pair densities of problem q for the conduction chunk already in the shared psi_c
+gw_status pair_block(gw_ctx* ctx, const Layout& L, const ProbPlan& q, char* ws) {
+  const Geom& g = q.p->geom->g;
+  hipError_t e;
+  {
+    gw::StageScope sc(ctx, gw::kStagePlanes);
+    e = L.fp64 ? gw::launch_pair_planes<double>(g, ws + q.off_psiv, ws + L.off_psic, q.nvs, q.cc, ws + L.off_q, q.minb,
+                                                ctx->stream)
+               : gw::launch_pair_planes<float>(g, ws + q.off_psiv, ws + L.off_psic, q.nvs, q.cc, ws + L.off_q, q.minb,
+                                               ctx->stream);
+  }
+  GW_HIP(ctx, e);
+  {
+    gw::StageScope sc(ctx, gw::kStageFinish);
+    e = L.fp64 ? gw::launch_pair_finish<double>(g, ws + L.off_q, q.npair, ws + q.off_m, ctx->stream)
+               : gw::launch_pair_finish<float>(g, ws + L.off_q, q.npair, ws + q.off_m, ctx->stream);
+  }
+  GW_HIP(ctx, e);
+  return GW_OK;
+}
+
+gw_status check_problem(gw_ctx* ctx, const gw_chi0_problem& p) {
+  if (!p.geom) return gw::fail(ctx, GW_EINVAL, "problem without geometry");
+  if (p.nv < 1 || p.ncol < 1 || p.nband < 1) return gw::fail(ctx, GW_EINVAL, "nv, nband and ncol must be >= 1");
+  if (!p.coef_v || !p.e_v || !p.coef_c || !p.e_col) return gw::fail(ctx, GW_EINVAL, "NULL band data pointer");
+  if (!p.col_band && p.ncol > p.nband) return gw::fail(ctx, GW_EINVAL, "ncol > nband without col_band");
+  return GW_OK;
+}
+
+gw_status check_common(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, const double* omega,
+                       double delta, gw_precision prec) {
+  if (!probs || nprob < 1 || nomega < 1 || !omega) return gw::fail(ctx, GW_EINVAL, "bad arguments");
+  if (!(delta >= 0.0) || !std::isfinite(delta)) return gw::fail(ctx, GW_EINVAL, "delta must be finite and >= 0");
+  if (prec != GW_FP64 && prec != GW_FP32 && prec != GW_BF16X3) return gw::fail(ctx, GW_EINVAL, "bad precision");
+  for (int w = 0; w < nomega; ++w)
+    if (!std::isfinite(omega[w])) return gw::fail(ctx, GW_EINVAL, "non-finite frequency");
+  for (int i = 0; i < nprob; ++i) {
+    gw_status s = check_problem(ctx, probs[i]);
+    if (s != GW_OK) return s;
+  }
+  return GW_OK;
+}
+
+struct DeviceScope {
+  int prev = 0;
+  explicit DeviceScope(int dev) {
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(dev);
+  }
+  ~DeviceScope() { (void)hipSetDevice(prev); }
+};
+
+// Enqueue one batch (<= kMaxBatch problems) of the forward band sum.
+gw_status enqueue_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, const double* omega,
+                        double delta, gw_precision prec, char* ws, size_t ws_bytes, char* out) {
+  const Layout L = make_layout(ctx, probs, nprob, nomega, delta > 0.0, prec, false);
+  if (L.total > ws_bytes)
+    return gw::fail(ctx, GW_EINVAL, "workspace too small: need " + std::to_string(L.total) + " bytes");
+  for (const ProbPlan& q : L.pp) {
+    GW_HIP(ctx, gw::launch_zero(ws + q.off_acc, q.acc_one * nomega * L.nparts, ctx->stream));
+    gw_status s = band_to_real(ctx, L, q.p->geom->g, (const double2*)q.p->coef_v, q.p->nv, nullptr, 0, q.p->nv, q.nvs,
+                               ws, ws + q.off_psiv);
+    if (s != GW_OK) return s;
+  }
+  int nchunk = 0;
+  for (const ProbPlan& q : L.pp) nchunk = std::max(nchunk, (q.p->ncol + q.cc - 1) / q.cc);
+  for (int j = 0; j < nchunk; ++j) {
+    gw::ContractBatch bt{};
+    std::vector<int> active;
+    for (int i = 0; i < (int)L.pp.size(); ++i) {
+      const ProbPlan& q = L.pp[i];
+      const int c0 = j * q.cc;
+      if (c0 >= q.p->ncol) continue;
+      gw_status s = band_to_real(ctx, L, q.p->geom->g, (const double2*)q.p->coef_c, q.p->nband, q.p->col_band, c0,
+                                 q.p->ncol, q.cc, ws, ws + L.off_psic);
+      if (s != GW_OK) return s;
+      s = pair_block(ctx, L, q, ws);
+      if (s != GW_OK) return s;
+      {
+        gw::StageScope sc(ctx, gw::kStageWeights);
+        for (int iw = 0; iw < nomega; ++iw)
+          GW_HIP(ctx, gw::launch_weights(q.p->e_v, 0, q.p->nv, q.nvs, q.p->e_col, q.p->n_col, c0, q.p->ncol, q.cc,
+                                         omega[iw], delta, L.nparts,
+                                         (double*)(ws + q.off_w) + (size_t)iw * L.nparts * q.npair, ctx->stream));
+      }
+      active.push_back(i);
+    }
+    // largest dielectric spheres first
+    std::stable_sort(active.begin(), active.end(), [&](int a, int b) {
+      return L.pp[a].p->geom->g.ngp > L.pp[b].p->geom->g.ngp;
+    });
+    bt.nprob = (int)active.size();
+    long long item = 0;
+    for (int k = 0; k < bt.nprob; ++k) {
+      const ProbPlan& q = L.pp[active[k]];
+      bt.item0[k] = item;
+      bt.p[k] = gw::ContractProb{ws + q.off_m, (const double*)(ws + q.off_w), (double2*)(ws + q.off_acc), q.npair,
+                                 q.p->geom->g.ngp, q.ksplit, q.ntl};
+      item += (long long)items_per_job(q) * nomega * L.nparts;
+    }
+    bt.item0[bt.nprob] = item;
+    int* counter = (int*)(ws + L.off_counter);
+    GW_HIP(ctx, gw::launch_zero(counter, 256, ctx->stream));
+    const int grid = (int)std::min<long long>(item, 256LL * 8);
+    gw::StageScope sc(ctx, gw::kStageContract);
+    GW_HIP(ctx, gw::launch_contract_batch(L.mode, bt, counter, grid, ctx->stream));
+  }
+  for (const ProbPlan& q : L.pp) {
+    const Geom& g = q.p->geom->g;
+    for (int iw = 0; iw < nomega; ++iw) {
+      const double2* accA = (const double2*)(ws + q.off_acc + q.acc_one * ((size_t)iw * L.nparts));
+      const double2* accB = L.nparts == 2 ? accA + q.acc_one / sizeof(double2) : nullptr;
+      gw::StageScope sc(ctx, gw::kStageFinalize);
+      GW_HIP(ctx, gw::launch_finalize(accA, accB, q.ksplit, g.ng, g.ngp, (double2*)out, ctx->stream));
+      out += (size_t)g.ng * g.ng * sizeof(double2);
+    }
+  }
+  return GW_OK;
+}
+
+gw_status enqueue_build_all(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, const double* omega,
+                            double delta, gw_precision prec, char* ws, size_t ws_bytes, char* out) {
+  for (int b0 = 0; b0 < nprob; b0 += gw::kMaxBatch) {
+    const int nb = std::min(gw::kMaxBatch, nprob - b0);
+    gw_status s = enqueue_build(ctx, probs + b0, nb, nomega, omega, delta, prec, ws, ws_bytes, out);
+    if (s != GW_OK) return s;
+    for (int i = b0; i < b0 + nb; ++i) out += (size_t)nomega * probs[i].geom->g.ng * probs[i].geom->g.ng * 16;
+  }
+  return GW_OK;
+}
+
+std::string graph_key(const gw_chi0_problem* probs, int nprob, int nomega, const double* omega, double delta,
+                      gw_precision prec, const void* ws, size_t ws_bytes, const void* out) {
+  std::string k;
+  auto add = [&](const void* p, size_t n) { k.append((const char*)p, n); };
+  add(&nprob, sizeof nprob);
+  add(probs, sizeof(gw_chi0_problem) * nprob);
+  add(&nomega, sizeof nomega);
+  add(omega, sizeof(double) * nomega);
+  add(&delta, sizeof delta);
+  add(&prec, sizeof prec);
+  add(&ws, sizeof ws);
+  add(&ws_bytes, sizeof ws_bytes);
+  add(&out, sizeof out);
+  return k;
+}
+
+}  // namespace
+
+extern "C" {
+
+gw_status gw_chi0_workspace_size(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega,
+                                 gw_precision prec, size_t* bytes) {
+  if (!ctx) return GW_EINVAL;
+  if (!probs || nprob < 1 || nomega < 1 || !bytes) return gw::fail(ctx, GW_EINVAL, "bad arguments");
+  if (prec != GW_FP64 && prec != GW_FP32 && prec != GW_BF16X3) return gw::fail(ctx, GW_EINVAL, "bad precision");
+  size_t mx = 0;
+  for (int i = 0; i < nprob; ++i) {
+    gw_status s = check_problem(ctx, probs[i]);
+    if (s != GW_OK) return s;
+  }
+  for (int b0 = 0; b0 < nprob; b0 += gw::kMaxBatch) {
+    const int nb = std::min(gw::kMaxBatch, nprob - b0);
+    const Layout f = make_layout(ctx, probs + b0, nb, nomega, true, prec, false);
+    const Layout b = make_layout(ctx, probs + b0, nb, nomega, true, prec, true);
+    mx = std::max({mx, f.total, b.total});
+  }
+  *bytes = mx;
+  return GW_OK;
+}
+
+gw_status gw_chi0_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, const double* omega,
+                        double delta, gw_precision prec, void* workspace, size_t ws_bytes, void* chi0) {
+  if (!ctx) return GW_EINVAL;
+  gw_status s = check_common(ctx, probs, nprob, nomega, omega, delta, prec);
+  if (s != GW_OK) return s;
+  if (!chi0 || !workspace) return gw::fail(ctx, GW_EINVAL, "NULL workspace or output");
+  DeviceScope dev(ctx->device);
+  if (!ctx->graph)
+    return enqueue_build_all(ctx, probs, nprob, nomega, omega, delta, prec, (char*)workspace, ws_bytes, (char*)chi0);
+  // graph mode: replay the captured launch sequence of an identical call
+  if (!ctx->stream) return gw::fail(ctx, GW_EINVAL, "graph mode needs a context on a non-null stream");
+  const std::string key = graph_key(probs, nprob, nomega, omega, delta, prec, workspace, ws_bytes, chi0);
+  for (auto& ge : ctx->graphs)
+    if (ge.key == key) {
+      GW_HIP(ctx, hipGraphLaunch(ge.exec, ctx->stream));
+      return GW_OK;
+    }
+  const bool timing = ctx->timing;
+  ctx->timing = false;   // no event nodes in a captured graph
+  GW_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+  s = enqueue_build_all(ctx, probs, nprob, nomega, omega, delta, prec, (char*)workspace, ws_bytes, (char*)chi0);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
+  ctx->timing = timing;
+  if (s != GW_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess) return gw::fail(ctx, GW_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return gw::fail(ctx, GW_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  }
+  ctx->graphs.push_back(gw_ctx::GraphEntry{key, graph, exec});
+  GW_HIP(ctx, hipGraphLaunch(exec, ctx->stream));
+  return GW_OK;
+}
+
+gw_status gw_ctx_set_graph(gw_ctx* ctx, int enable) {
+  if (!ctx) return GW_EINVAL;
+  ctx->graph = enable != 0;
+  if (!ctx->graph) {
+    for (auto& ge : ctx->graphs) {
+      (void)hipGraphExecDestroy(ge.exec);
+      (void)hipGraphDestroy(ge.graph);
+    }
+    ctx->graphs.clear();
+  }
+  return GW_OK;
+}
+
+gw_status gw_chi0_backward(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, const double* omega,
+                           double delta, gw_precision prec, void* workspace, size_t ws_bytes, const void* grad_chi0,
+                           double* grad_e_v, double* grad_e_col, double* grad_n_col, void* grad_coef_v,
+                           void* grad_coef_c) {
+  if (!ctx) return GW_EINVAL;
+  gw_status st = check_common(ctx, probs, nprob, nomega, omega, delta, prec);
+  if (st != GW_OK) return st;
+  if (!grad_chi0 || !workspace) return gw::fail(ctx, GW_EINVAL, "NULL workspace or gradient");
+  if (grad_coef_v || grad_coef_c)
+    return gw::fail(ctx, GW_EUNSUPPORTED, "gradients with respect to the coefficients are not built");
+  DeviceScope dev(ctx->device);
+  char* ws = (char*)workspace;
+  const char* gin = (const char*)grad_chi0;
+  size_t off_ev = 0, off_ec = 0;
+  for (int ip = 0; ip < nprob; ++ip) {
+    const gw_chi0_problem& p = probs[ip];
+    const Geom& g = p.geom->g;
+    const Layout L = make_layout(ctx, &p, 1, nomega, delta > 0.0, prec, true);
+    if (L.total > ws_bytes) return gw::fail(ctx, GW_EINVAL, "workspace too small: need " + std::to_string(L.total));
+    const ProbPlan& q = L.pp[0];
+    double* gev = grad_e_v ? grad_e_v + off_ev : nullptr;
+    double* gec = grad_e_col ? grad_e_col + off_ec : nullptr;
+    double* gn = grad_n_col ? grad_n_col + off_ec : nullptr;
+    gw::StageScope sc(ctx, gw::kStageBackward);
+    if (gev) GW_HIP(ctx, gw::launch_fill_f64(gev, p.nv, 0.0, ctx->stream));
+    gw_status s = band_to_real(ctx, L, g, (const double2*)p.coef_v, p.nv, nullptr, 0, p.nv, q.nvs, ws, ws + q.off_psiv);
+    if (s != GW_OK) return s;
+    double* dx = (double*)(ws + L.off_dx);
+    double* dn = (double*)(ws + L.off_dn);
+    double2* part = (double2*)(ws + L.off_part);
+    for (int c0 = 0; c0 < p.ncol; c0 += q.cc) {
+      s = band_to_real(ctx, L, g, (const double2*)p.coef_c, p.nband, p.col_band, c0, p.ncol, q.cc, ws, ws + L.off_psic);
+      if (s != GW_OK) return s;
+      s = pair_block(ctx, L, q, ws);
+      if (s != GW_OK) return s;
+      GW_HIP(ctx, gw::launch_fill_f64(dx, q.npair, 0.0, ctx->stream));
+      GW_HIP(ctx, gw::launch_fill_f64(dn, q.npair, 0.0, ctx->stream));
+      for (int iw = 0; iw < nomega; ++iw) {
+        const double2* gb = (const double2*)gin + (size_t)iw * g.ng * g.ng;
+        hipError_t e = L.fp64 ? gw::launch_adjoint<double>(ws + q.off_m, q.npair, g.ng, g.ngp, gb, part, ctx->stream)
+                              : gw::launch_adjoint<float>(ws + q.off_m, q.npair, g.ng, g.ngp, gb, part, ctx->stream);
+        GW_HIP(ctx, e);
+        GW_HIP(ctx, gw::launch_adjoint_pairs(part, g.ngp, p.e_v, p.nv, q.nvs, p.e_col, p.n_col, c0, p.ncol, q.cc,
+                                             omega[iw], delta, dx, dn, ctx->stream));
+      }
+      GW_HIP(ctx, gw::launch_adjoint_reduce(dx, dn, p.nv, q.cc, c0, p.ncol, gev, gec, gn, ctx->stream));
+    }
+    gin += (size_t)nomega * g.ng * g.ng * sizeof(double2);
+    off_ev += p.nv;
+    off_ec += p.ncol;
+  }
+  return GW_OK;
+}
+
+gw_status gw_pair_density_workspace_size(gw_ctx* ctx, const gw_chi0_problem* prob, int nvs, int ncs,
+                                         gw_precision prec, size_t* bytes) {
+  if (!ctx) return GW_EINVAL;
+  if (!prob || !bytes || nvs < 1 || ncs < 1) return gw::fail(ctx, GW_EINVAL, "bad arguments");
+  gw_status s = check_problem(ctx, *prob);
+  if (s != GW_OK) return s;
+  gw_chi0_problem sub = *prob;
+  sub.nv = nvs;
+  sub.ncol = ncs;
+  *bytes = make_layout(ctx, &sub, 1, 1, false, prec, false).total;
+  return GW_OK;
+}
+
+gw_status gw_pair_density(gw_ctx* ctx, const gw_chi0_problem* prob, int v0, int nvs, int c0, int ncs,
+                          gw_precision prec, void* workspace, size_t ws_bytes, void* m_out) {
+  if (!ctx) return GW_EINVAL;
+  if (!prob || !workspace || !m_out) return gw::fail(ctx, GW_EINVAL, "NULL argument");
+  gw_status s = check_problem(ctx, *prob);
+  if (s != GW_OK) return s;
+  if (prec != GW_FP64 && prec != GW_FP32 && prec != GW_BF16X3) return gw::fail(ctx, GW_EINVAL, "bad precision");
+  if (nvs < 1 || ncs < 1 || v0 < 0 || c0 < 0 || v0 + nvs > prob->nv || c0 + ncs > prob->ncol)
+    return gw::fail(ctx, GW_EINVAL, "pair block out of range");
+  const Geom& g = prob->geom->g;
+  gw_chi0_problem sub = *prob;
+  sub.nv = nvs;
+  sub.ncol = ncs;
+  const Layout L = make_layout(ctx, &sub, 1, 1, false, prec, false);
+  const ProbPlan& q = L.pp[0];
+  if (q.cc < (int)round_up(ncs, 8)) return gw::fail(ctx, GW_EINVAL, "pair block too large for one pass");
+  if (L.total > ws_bytes) return gw::fail(ctx, GW_EINVAL, "workspace too small: need " + std::to_string(L.total));
+  DeviceScope dev(ctx->device);
+  char* ws = (char*)workspace;
+  s = band_to_real(ctx, L, g, (const double2*)prob->coef_v, prob->nv, nullptr, v0, v0 + nvs, q.nvs, ws, ws + q.off_psiv);
+  if (s != GW_OK) return s;
+  s = band_to_real(ctx, L, g, (const double2*)prob->coef_c, prob->nband, prob->col_band, c0, c0 + ncs, q.cc, ws,
+                   ws + L.off_psic);
+  if (s != GW_OK) return s;
+  s = pair_block(ctx, L, q, ws);
+  if (s != GW_OK) return s;
+  GW_HIP(ctx, gw::launch_copy_m(ws + q.off_m, nvs, ncs, q.cc, g.ng, g.ngp, L.fp64, (double2*)m_out, ctx->stream));
+  return GW_OK;
+}
+
+// Launch-shape tuner: times the candidates of the tunable launches on the first chunk
+// of each problem shape and keeps the fastest in the context.
+gw_status gw_tune(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, gw_precision prec,
+                  void* workspace, size_t ws_bytes) {
+  if (!ctx) return GW_EINVAL;
+  std::vector<double> om(std::max(1, nomega), 0.0);
+  gw_status s = check_common(ctx, probs, nprob, std::max(1, nomega), om.data(), 0.0, prec);
+  if (s != GW_OK) return s;
+  if (!workspace) return gw::fail(ctx, GW_EINVAL, "NULL workspace");
+  if (ctx->graph) return gw::fail(ctx, GW_EINVAL, "disable graph mode while tuning");
+  DeviceScope dev(ctx->device);
+  char* ws = (char*)workspace;
+  hipEvent_t a, b;
+  GW_HIP(ctx, hipEventCreate(&a));
+  GW_HIP(ctx, hipEventCreate(&b));
+  auto timed = [&](auto&& fn, float* ms) -> gw_status {
+    GW_HIP(ctx, hipEventRecord(a, ctx->stream));
+    gw_status r = fn();
+    if (r != GW_OK) return r;
+    GW_HIP(ctx, hipEventRecord(b, ctx->stream));
+    GW_HIP(ctx, hipEventSynchronize(b));
+    GW_HIP(ctx, hipEventElapsedTime(ms, a, b));
+    return GW_OK;
+  };
+  const bool timing = ctx->timing;
+  ctx->timing = false;
+  gw_status result = GW_OK;
+  for (int ip = 0; ip < nprob && result == GW_OK; ++ip) {
+    const gw_chi0_problem& p = probs[ip];
+    const std::string key = shape_key(p.geom->g, p.nv, p.ncol, prec);
+    int best_minb = 0, best_ks = 0;
+    float best = 1e30f;
+    // pair kernel: one or two resident workgroups per CU
+    Layout L = make_layout(ctx, &p, 1, std::max(1, nomega), false, prec, false);
+    if (L.total > ws_bytes) {
+      result = gw::fail(ctx, GW_EINVAL, "workspace too small for tuning");
+      break;
+    }
+    ProbPlan q = L.pp[0];
+    result = band_to_real(ctx, L, p.geom->g, (const double2*)p.coef_v, p.nv, nullptr, 0, p.nv, q.nvs, ws, ws + q.off_psiv);
+    if (result == GW_OK)
+      result = band_to_real(ctx, L, p.geom->g, (const double2*)p.coef_c, p.nband, p.col_band, 0, p.ncol, q.cc, ws,
+                            ws + L.off_psic);
+    for (int minb = 1; minb <= 2 && result == GW_OK; ++minb) {
+      q.minb = minb;
+      float t0 = 0, t1 = 0;
+      result = timed([&] { return pair_block(ctx, L, q, ws); }, &t0);   // warm-up
+      if (result == GW_OK) result = timed([&] { return pair_block(ctx, L, q, ws); }, &t1);
+      if (result == GW_OK && t1 < best) {
+        best = t1;
+        best_minb = minb;
+      }
+    }
+    // contraction: pair-range splits
+    best = 1e30f;
+    for (int ks : {1, 2, 4, 8, 16, 32}) {
+      if (result != GW_OK) break;
+      Layout Lk = make_layout(ctx, &p, 1, std::max(1, nomega), false, prec, false, ks);
+      if (Lk.total > ws_bytes) continue;
+      const ProbPlan& qk = Lk.pp[0];
+      if (qk.ksplit != ks) continue;
+      result = band_to_real(ctx, Lk, p.geom->g, (const double2*)p.coef_v, p.nv, nullptr, 0, p.nv, qk.nvs, ws,
+                            ws + qk.off_psiv);
+      if (result != GW_OK) break;
+      result = band_to_real(ctx, Lk, p.geom->g, (const double2*)p.coef_c, p.nband, p.col_band, 0, p.ncol, qk.cc, ws,
+                            ws + Lk.off_psic);
+      if (result != GW_OK) break;
+      result = pair_block(ctx, Lk, qk, ws);
+      if (result != GW_OK) break;
+      GW_HIP(ctx, gw::launch_weights(p.e_v, 0, p.nv, qk.nvs, p.e_col, p.n_col, 0, p.ncol, qk.cc, 0.0, 0.0, 1,
+                                     (double*)(ws + qk.off_w), ctx->stream));
+      gw::ContractBatch bt{};
+      bt.nprob = 1;
+      bt.item0[0] = 0;
+      bt.item0[1] = items_per_job(qk);
+      bt.p[0] = gw::ContractProb{ws + qk.off_m, (const double*)(ws + qk.off_w), (double2*)(ws + qk.off_acc), qk.npair,
+                                 p.geom->g.ngp, qk.ksplit, qk.ntl};
+      int* counter = (int*)(ws + Lk.off_counter);
+      const int grid = (int)std::min<long long>(bt.item0[1], 256LL * 8);
+      float t = 0;
+      for (int rep = 0; rep < 2 && result == GW_OK; ++rep) {
+        result = timed(
+            [&]() -> gw_status {
+              GW_HIP(ctx, gw::launch_zero(ws + qk.off_acc, qk.acc_one, ctx->stream));
+              GW_HIP(ctx, gw::launch_zero(counter, 256, ctx->stream));
+              GW_HIP(ctx, gw::launch_contract_batch(Lk.mode, bt, counter, grid, ctx->stream));
+              return GW_OK;
+            },
+            &t);
+      }
+      if (result == GW_OK && t < best) {
+        best = t;
+        best_ks = ks;
+      }
+    }
+    if (result == GW_OK && best_minb && best_ks) ctx->tune[key] = std::make_pair(best_minb, best_ks);
+  }
+  ctx->timing = timing;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return result;
+}
+
+}  // extern "C"

@@ -2,13 +2,19 @@
 //   chi0_GG' += sum_p w_p M_p(G) conj(M_p(G')),
 //   w_p = n_c * 1/2 [1/(E_v - E_c - w + i delta) + 1/(E_v - E_c + w + i delta)]   (float64).
 // A complex weight splits into two real ones, chi0 = H_a + i H_b with
-// H_x = sum_p x_p M_p M_p^H Hermitian, so every launch is a Hermitian rank-k update
-// with real per-pair weights, computed for the lower tiles only and mirrored at the end.
+// H_x = sum_p x_p M_p M_p^H Hermitian, so every job is a Hermitian rank-k update with
+// real per-pair weights, computed for the lower tiles only and mirrored at the end.
 //
-// k_contract: one 64 x 64 tile (G, G') per workgroup, k (pairs) split over ksplit
-// workgroups that own separate float64 partial sums (no atomics, fixed summation
-// order).  Complex products on real MFMA 16x16x4 (f64 or f32):
-//   Re += a.re b.re + a.im b.im,  Im += a.im b.re - a.re b.im   with b = w M(G').
+// One work item = one 64 x 64 lower tile (G, G') of one job (q-point, frequency, part)
+// over one of ksplit ranges of pairs; each item owns a float64 partial sum (no
+// atomics, fixed summation order).  The next stage of pairs is fetched into registers
+// while the current one runs on MFMA.  Items are run either as a plain grid (one
+// job) or by a persistent grid that pulls items from a counter, ordered so that the
+// problems with the largest dielectric spheres come first.
+//
+// MFMA forms: f64 / f32 16x16x4 with Re += a.re b.re + a.im b.im and
+// Im += a.im b.re - a.re b.im (b = w M(G')), and split-bf16 x3 (see below).
+#include <algorithm>
 #include <type_traits>
 
 #include "common.h"
@@ -21,9 +27,9 @@ namespace {
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-template <typename T> struct Mfma;
 // Output row of accumulator register r in lane group lk = lane / 16 (column = lane % 16);
 // the f64 and f32 16x16x4 instructions differ here.
+template <typename T> struct Mfma;
 template <> struct Mfma<double> {
   using acc = f64x4;
   static __device__ __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
@@ -41,7 +47,7 @@ template <> struct Mfma<float> {
 
 __global__ void k_weights(const double* __restrict__ e_v, int v0, int nv_valid, int nvs,
                           const double* __restrict__ e_col, const double* __restrict__ n_col, int c0, int nc_valid,
-                          int ncs, double omega, double delta, double* __restrict__ w) {
+                          int ncs, double omega, double delta, int nparts, double* __restrict__ w) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int np = nvs * ncs;
   if (p >= np) return;
@@ -62,35 +68,58 @@ __global__ void k_weights(const double* __restrict__ e_v, int v0, int nv_valid, 
     }
   }
   w[p] = wr;
-  w[np + p] = wi;
+  if (nparts == 2) w[np + p] = wi;
+}
+
+__device__ __forceinline__ void tile_coords(int t, int* ti, int* tj) {
+  int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  *ti = i;
+  *tj = t - i * (i + 1) / 2;
+}
+
+// float64 partial sum of one item
+template <typename A4>
+__device__ __forceinline__ void store_tile(double2* out, int ngp, int g0, int h0, const A4 (&cre)[2][2],
+                                           const A4 (&cim)[2][2], int wr, int wc, int li, int lk, bool f64_rows) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = g0 + 32 * wr + 16 * i + (f64_rows ? lk + 4 * r : 4 * lk + r);
+        const int col = h0 + 32 * wc + 16 * j + li;
+        double2* p = out + (size_t)row * ngp + col;
+        double2 o = *p;
+        o.x += (double)cre[i][j][r];
+        o.y += (double)cim[i][j][r];
+        *p = o;
+      }
 }
 
 constexpr int KC = 16;   // pairs per LDS stage
 
+// ---------------------------------------------------------------- f64 / f32 MFMA tile
 template <typename T>
-__global__ __launch_bounds__(256) void k_contract(const cx<T>* __restrict__ m, const double* __restrict__ w, int nk,
-                                                  int ngp, int ksplit, double2* __restrict__ acc) {
+__device__ void tile_mfma(const cx<T>* __restrict__ m, const double* __restrict__ w, int nk, int ngp, int ksplit,
+                          double2* __restrict__ acc, int t, int ks) {
   using V = cx<T>;
   using A4 = typename Mfma<T>::acc;
   __shared__ V sA[KC][kTile];
   __shared__ V sB[KC][kTile];
-
-  const int t = blockIdx.x / ksplit;
-  const int ks = blockIdx.x % ksplit;
-  int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-  while (ti * (ti + 1) / 2 > t) --ti;
-  const int tj = t - ti * (ti + 1) / 2;
+  int ti, tj;
+  tile_coords(t, &ti, &tj);
   const int g0 = ti * kTile, h0 = tj * kTile;
-
   const int per = (nk + ksplit - 1) / ksplit;
   const int k0 = ks * per;
   const int k1 = min(nk, k0 + per);
-
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int wr = wave >> 1, wc = wave & 1;
   const int li = lane & 15, lk = lane >> 4;
+  constexpr int NR = (KC * kTile) / 256;
 
   A4 cre[2][2], cim[2][2];
 #pragma unroll
@@ -100,11 +129,10 @@ __global__ __launch_bounds__(256) void k_contract(const cx<T>* __restrict__ m, c
       cre[i][j] = A4{0, 0, 0, 0};
       cim[i][j] = A4{0, 0, 0, 0};
     }
-
-  for (int kk = k0; kk < k1; kk += KC) {
-    __syncthreads();
+  V pa[NR], pb[NR];
+  auto fetch = [&](int kk) {
 #pragma unroll
-    for (int r = 0; r < (KC * kTile) / 256; ++r) {
+    for (int r = 0; r < NR; ++r) {
       const int e = tid + 256 * r;
       const int k = e / kTile, g = e % kTile;
       V a{T(0), T(0)}, b{T(0), T(0)};
@@ -115,10 +143,21 @@ __global__ __launch_bounds__(256) void k_contract(const cx<T>* __restrict__ m, c
         const T s = T(w[kk + k]);
         b = V{bb.x * s, bb.y * s};
       }
-      sA[k][g] = a;
-      sB[k][g] = b;
+      pa[r] = a;
+      pb[r] = b;
+    }
+  };
+  if (k0 < k1) fetch(k0);
+  for (int kk = k0; kk < k1; kk += KC) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int e = tid + 256 * r;
+      sA[e / kTile][e % kTile] = pa[r];
+      sB[e / kTile][e % kTile] = pb[r];
     }
     __syncthreads();
+    if (kk + KC < k1) fetch(kk + KC);
 #pragma unroll
     for (int s = 0; s < KC / 4; ++s) {
       const int k = 4 * s + lk;
@@ -138,30 +177,17 @@ __global__ __launch_bounds__(256) void k_contract(const cx<T>* __restrict__ m, c
         }
     }
   }
-  // accumulate into this split's float64 partial sum
-  double2* out = acc + (size_t)ks * ngp * ngp;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = g0 + 32 * wr + 16 * i + Mfma<T>::row(lk, r);
-        const int col = h0 + 32 * wc + 16 * j + li;
-        double2* p = out + (size_t)row * ngp + col;
-        double2 o = *p;
-        o.x += (double)cre[i][j][r];
-        o.y += (double)cim[i][j][r];
-        *p = o;
-      }
+  store_tile(acc + (size_t)ks * ngp * ngp, ngp, g0, h0, cre, cim, wr, wc, li, lk, std::is_same<T, double>::value);
 }
 
-// ---------------------------------------------------------------- split-bf16 x3
+// ---------------------------------------------------------------- split-bf16 x3 tile
 // Each float32 operand x = hi + lo (hi = bf16(x), lo = bf16(x - hi), round to nearest
 // even); products use hi*hi + hi*lo + lo*hi on MFMA 16x16x32 bf16 with float32
 // accumulation.  The complex Hermitian update is two real products over a doubled
 // inner index k' = [re of 16 pairs | im of 16 pairs]:
 //   Re C = [ar | ai] [br | bi]^T,   Im C = [ai | -ar] [br | bi]^T,   b = w M(G').
+// MFMA 16x16x32 bf16 operands: lane l holds row l % 16, inner indices 8 (l / 16) + 0..7;
+// result rows 4 (l / 16) + r, column l % 16.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
@@ -175,26 +201,20 @@ __device__ __forceinline__ float bf16_val(unsigned short h) { return __uint_as_f
 constexpr int BK = 16;          // pairs per MFMA step
 constexpr int BROW = 40;        // bf16 per LDS row (32 used, padded so 8 rows read together hit distinct banks)
 
-__global__ __launch_bounds__(256) void k_contract_bf16x3(const float2* __restrict__ m, const double* __restrict__ w,
-                                                         int nk, int ngp, int ksplit, double2* __restrict__ acc) {
+__device__ void tile_bf16x3(const float2* __restrict__ m, const double* __restrict__ w, int nk, int ngp, int ksplit,
+                            double2* __restrict__ acc, int t, int ks) {
   // [A|B][hi|lo][row][k']
   __shared__ __align__(16) unsigned short s[2][2][kTile][BROW];
-  const int t = blockIdx.x / ksplit;
-  const int ks = blockIdx.x % ksplit;
-  int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-  while (ti * (ti + 1) / 2 > t) --ti;
-  const int tj = t - ti * (ti + 1) / 2;
+  int ti, tj;
+  tile_coords(t, &ti, &tj);
   const int g0 = ti * kTile, h0 = tj * kTile;
   const int per = (nk + ksplit - 1) / ksplit;
   const int k0 = ks * per;
   const int k1 = min(nk, k0 + per);
-
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int wr = wave >> 1, wc = wave & 1;
   const int li = lane & 15, lg = lane >> 4;
-
   // staging role: operand (A or B), row, half of the 16 pairs
   const int op = tid >> 7;            // 0: A rows (G), 1: B rows (G')
   const int srow = tid & 63;
@@ -209,28 +229,37 @@ __global__ __launch_bounds__(256) void k_contract_bf16x3(const float2* __restric
       cre[i][j] = f32x4{0, 0, 0, 0};
       cim[i][j] = f32x4{0, 0, 0, 0};
     }
-
+  float2 pf[8];
+  auto fetch = [&](int kk) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = kk + 8 * shalf + e;
+      float2 x{0.f, 0.f};
+      if (k < k1) {
+        x = m[(size_t)k * ngp + gcol];
+        if (op) {
+          const float sw = (float)w[k];
+          x.x *= sw;
+          x.y *= sw;
+        }
+      }
+      pf[e] = x;
+    }
+  };
+  if (k0 < k1) fetch(k0);
+  const int yg = (lg + 2) & 3;
+  const unsigned short neg = lg >= 2 ? 0x8000 : 0;
   for (int kk = k0; kk < k1; kk += BK) {
     __syncthreads();
     {
       u16x8 rh, rl, ih, il;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const int k = kk + 8 * shalf + e;
-        float2 x{0.f, 0.f};
-        if (k < k1) {
-          x = m[(size_t)k * ngp + gcol];
-          if (op) {
-            const float sw = (float)w[k];
-            x.x *= sw;
-            x.y *= sw;
-          }
-        }
-        const unsigned short a = bf16_rne(x.x), b = bf16_rne(x.y);
+        const unsigned short a = bf16_rne(pf[e].x), b = bf16_rne(pf[e].y);
         rh[e] = a;
         ih[e] = b;
-        rl[e] = bf16_rne(x.x - bf16_val(a));
-        il[e] = bf16_rne(x.y - bf16_val(b));
+        rl[e] = bf16_rne(pf[e].x - bf16_val(a));
+        il[e] = bf16_rne(pf[e].y - bf16_val(b));
       }
       *(u16x8*)&s[op][0][srow][8 * shalf] = rh;
       *(u16x8*)&s[op][0][srow][16 + 8 * shalf] = ih;
@@ -238,9 +267,8 @@ __global__ __launch_bounds__(256) void k_contract_bf16x3(const float2* __restric
       *(u16x8*)&s[op][1][srow][16 + 8 * shalf] = il;
     }
     __syncthreads();
+    if (kk + BK < k1) fetch(kk + BK);
     bf16x8 xh[2], xl[2], yh[2], yl[2], bh[2], bl[2];
-    const int yg = (lg + 2) & 3;
-    const unsigned short neg = lg >= 2 ? 0x8000 : 0;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int r = 32 * wr + 16 * i + li;
@@ -271,21 +299,49 @@ __global__ __launch_bounds__(256) void k_contract_bf16x3(const float2* __restric
         cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yl[i], bh[j], cim[i][j], 0, 0, 0);
       }
   }
-  double2* out = acc + (size_t)ks * ngp * ngp;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = g0 + 32 * wr + 16 * i + 4 * lg + r;
-        const int col = h0 + 32 * wc + 16 * j + li;
-        double2* p = out + (size_t)row * ngp + col;
-        double2 o = *p;
-        o.x += (double)cre[i][j][r];
-        o.y += (double)cim[i][j][r];
-        *p = o;
-      }
+  store_tile(acc + (size_t)ks * ngp * ngp, ngp, g0, h0, cre, cim, wr, wc, li, lg, false);
+}
+
+// ---------------------------------------------------------------- kernels
+template <int MODE>   // 0 f64, 1 f32, 2 bf16x3
+__device__ __forceinline__ void run_item(const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
+                                         int t, int ks) {
+  if constexpr (MODE == 0)
+    tile_mfma<double>((const double2*)m, w, nk, ngp, ksplit, acc, t, ks);
+  else if constexpr (MODE == 1)
+    tile_mfma<float>((const float2*)m, w, nk, ngp, ksplit, acc, t, ks);
+  else
+    tile_bf16x3((const float2*)m, w, nk, ngp, ksplit, acc, t, ks);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_contract(const void* __restrict__ m, const double* __restrict__ w, int nk,
+                                                  int ngp, int ksplit, double2* __restrict__ acc) {
+  run_item<MODE>(m, w, nk, ngp, ksplit, acc, blockIdx.x / ksplit, blockIdx.x % ksplit);
+}
+
+// Persistent grid over all items of a batch; items of problem b occupy
+// [item0[b], item0[b+1]) and decode as (job, tile, split), job = w_index * nparts + part.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_contract_batch(ContractBatch bt, int* __restrict__ counter) {
+  __shared__ int s_item;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const long long item = s_item;
+    if (item >= bt.item0[bt.nprob]) break;
+    int b = 0;
+    while (b + 1 < bt.nprob && item >= bt.item0[b + 1]) ++b;
+    const ContractProb& p = bt.p[b];
+    const long long local = item - bt.item0[b];
+    const int per_job = p.ntl * p.ksplit;
+    const int job = (int)(local / per_job);
+    const int rem = (int)(local % per_job);
+    const double* w = p.w + (size_t)job * p.nk;
+    double2* acc = p.acc + (size_t)job * p.ksplit * p.ngp * p.ngp;
+    run_item<MODE>(p.m, w, p.nk, p.ngp, p.ksplit, acc, rem / p.ksplit, rem % p.ksplit);
+  }
 }
 
 __global__ void k_finalize(const double2* __restrict__ accA, const double2* __restrict__ accB, int ksplit, int ng,
@@ -337,30 +393,34 @@ __global__ void k_copy_m(const cx<T>* __restrict__ m, int nvs, int ncs, int ncs_
 }  // namespace
 
 hipError_t launch_weights(const double* e_v, int v0, int nv_valid, int nvs, const double* e_col, const double* n_col,
-                          int c0, int nc_valid, int ncs, const double* omega, int iw, double delta, double* w,
+                          int c0, int nc_valid, int ncs, double omega, double delta, int nparts, double* w,
                           hipStream_t st) {
   const int np = nvs * ncs;
-  k_weights<<<(np + 255) / 256, 256, 0, st>>>(e_v, v0, nv_valid, nvs, e_col, n_col, c0, nc_valid, ncs,
-                                               omega ? omega[iw] : 0.0, delta, w);
+  k_weights<<<(np + 255) / 256, 256, 0, st>>>(e_v, v0, nv_valid, nvs, e_col, n_col, c0, nc_valid, ncs, omega, delta,
+                                               nparts, w);
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_contract(const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
+hipError_t launch_contract(int mode, const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
                            hipStream_t st) {
   const int nt = ngp / kTile;
-  const int ntl = nt * (nt + 1) / 2;
-  k_contract<T><<<ntl * ksplit, 256, 0, st>>>((const cx<T>*)m, w, nk, ngp, ksplit, acc);
+  const int nb = nt * (nt + 1) / 2 * ksplit;
+  if (mode == 0)
+    k_contract<0><<<nb, 256, 0, st>>>(m, w, nk, ngp, ksplit, acc);
+  else if (mode == 1)
+    k_contract<1><<<nb, 256, 0, st>>>(m, w, nk, ngp, ksplit, acc);
+  else
+    k_contract<2><<<nb, 256, 0, st>>>(m, w, nk, ngp, ksplit, acc);
   return hipGetLastError();
 }
-template hipError_t launch_contract<double>(const void*, const double*, int, int, int, double2*, hipStream_t);
-template hipError_t launch_contract<float>(const void*, const double*, int, int, int, double2*, hipStream_t);
 
-hipError_t launch_contract_bf16x3(const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
-                                  hipStream_t st) {
-  const int nt = ngp / kTile;
-  const int ntl = nt * (nt + 1) / 2;
-  k_contract_bf16x3<<<ntl * ksplit, 256, 0, st>>>((const float2*)m, w, nk, ngp, ksplit, acc);
+hipError_t launch_contract_batch(int mode, const ContractBatch& bt, int* counter, int grid, hipStream_t st) {
+  if (mode == 0)
+    k_contract_batch<0><<<grid, 256, 0, st>>>(bt, counter);
+  else if (mode == 1)
+    k_contract_batch<1><<<grid, 256, 0, st>>>(bt, counter);
+  else
+    k_contract_batch<2><<<grid, 256, 0, st>>>(bt, counter);
   return hipGetLastError();
 }
 

@@ -5,7 +5,9 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/gwchi0.h"
@@ -29,7 +31,31 @@ struct gw_ctx {
   std::vector<Mark> marks;
   double stage_ms[gw::kNumStages] = {};
   long long stage_n[gw::kNumStages] = {};
+  // launch shapes chosen by gw_tune, by problem shape: (pair-kernel residency, pair-range splits)
+  std::map<std::string, std::pair<int, int>> tune;
+  // graph mode: captured launch sequences of gw_chi0_build, by argument signature
+  bool graph = false;
+  struct GraphEntry {
+    std::string key;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
 };
+
+namespace gw {
+inline gw_status fail(gw_ctx* ctx, gw_status s, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return s;
+}
+}  // namespace gw
+
+#define GW_HIP(ctx, expr)                                                                          \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    if (e_ != hipSuccess)                                                                          \
+      return gw::fail((ctx), GW_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));       \
+  } while (0)
 
 namespace gw {
 // Records an event pair around the launches in its scope when the context times stages.
@@ -73,6 +99,15 @@ struct Geom {
   float2* d_tw32 = nullptr;
 };
 
+}  // namespace gw
+
+struct gw_geom {
+  gw_ctx* ctx = nullptr;
+  gw::Geom g;
+};
+
+namespace gw {
+
 // ---------------------------------------------------------------- launches
 // Band -> real space: psi[slot][x1][p2][p3] for nslot bands.  Band of slot s:
 // idx = band0 + s; if idx >= nvalid it is clamped to nvalid - 1; then
@@ -84,9 +119,10 @@ size_t band_scratch_bytes(const Geom& g, int nslot, bool fp64);
 
 // Pair planes: Q[pair][p1][j2][j3] for pairs (v, c), v < nvs (multiple of 4), c < ncs (multiple of 8);
 // pair = v * ncs + c.
+// minb: 0 = choose by register demand, 1 or 2 = resident workgroups per CU to compile for.
 template <typename T>
 hipError_t launch_pair_planes(const Geom& g, const void* psi_v, const void* psi_c, int nvs, int ncs, void* q,
-                              hipStream_t st);
+                              int minb, hipStream_t st);
 // Pair finish: x1 transforms, 1/N, gather to the chi sphere: m[pair][ngp] (zero padded).
 template <typename T>
 hipError_t launch_pair_finish(const Geom& g, const void* q, int npair, void* m, hipStream_t st);
@@ -94,16 +130,30 @@ bool pair_supported(int nd, int K);
 
 // Weights of Eq. (chi0) per pair p = v * ncs + c (zero for padded pairs):
 // part 0 = Re w, part 1 = Im w, w[part][p].
+// w[p] = Re w_p; with nparts == 2 also w[np + p] = Im w_p.
 hipError_t launch_weights(const double* e_v, int v0, int nv_valid, int nvs, const double* e_col, const double* n_col,
-                          int c0, int nc_valid, int ncs, const double* omega, int iw, double delta, double* w,
+                          int c0, int nc_valid, int ncs, double omega, double delta, int nparts, double* w,
                           hipStream_t st);
 
-// acc[ks][G][G'] (lower tiles) += sum_k m[k][G] w[k] conj(m[k][G'])
-template <typename T>
-hipError_t launch_contract(const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
+// acc[ks][G][G'] (lower tiles) += sum_k m[k][G] w[k] conj(m[k][G']);  mode 0 f64, 1 f32, 2 bf16x3
+hipError_t launch_contract(int mode, const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
                            hipStream_t st);
-hipError_t launch_contract_bf16x3(const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
-                                  hipStream_t st);
+// Batched contraction: per problem, nomega * nparts jobs (job j uses w + j nk and
+// acc + j ksplit ngp^2), each split into ntl lower tiles x ksplit pair ranges; one
+// persistent launch pulls the items from *counter (zeroed beforehand).
+struct ContractProb {
+  const void* m;
+  const double* w;
+  double2* acc;
+  int nk, ngp, ksplit, ntl;
+};
+constexpr int kMaxBatch = 16;
+struct ContractBatch {
+  int nprob;
+  long long item0[kMaxBatch + 1];
+  ContractProb p[kMaxBatch];
+};
+hipError_t launch_contract_batch(int mode, const ContractBatch& bt, int* counter, int grid, hipStream_t st);
 // chi[G][G'] = sum_ks accA + i sum_ks accB (Hermitian parts mirrored), for G, G' < ng.
 hipError_t launch_finalize(const double2* accA, const double2* accB, int ksplit, int ng, int ngp, double2* chi,
                            hipStream_t st);

@@ -15,8 +15,6 @@
 //   output Q[pair][p1][n2][n3] for this plane (p1 = plane stored permuted).
 // k_pair_finish (one pair per workgroup): pruned x1 transform of Q, the 1/N, and the
 //   gather of the K^3 box onto the sphere order: M[pair][G] (zero padded to ngp).
-#include <stdlib.h>
-
 #include <type_traits>
 
 #include "common.h"
@@ -213,12 +211,11 @@ __global__ __launch_bounds__(256) void k_pair_finish(const cx<T>* __restrict__ q
 }
 
 template <typename T, int ND, int R, int K>
-hipError_t run_planes(const Geom& g, const void* psi_v, const void* psi_c, int nvs, int ncs, void* q,
+hipError_t run_planes(const Geom& g, const void* psi_v, const void* psi_c, int nvs, int ncs, void* q, int minb,
                       hipStream_t st) {
   const cx<T>* tw = std::is_same<T, double>::value ? (const cx<T>*)g.d_tw64 : (const cx<T>*)g.d_tw32;
   const int nblk = ND * (nvs / kTV) * (ncs / kTC);
-  static const int force = getenv("GWCHI0_PLANES_MINB") ? atoi(getenv("GWCHI0_PLANES_MINB")) : 0;
-  if (force == 2 || (force == 0 && planes_min_blocks<T, R, K>() == 2))
+  if (minb == 2 || (minb == 0 && planes_min_blocks<T, R, K>() == 2))
     k_pair_planes<T, ND, R, K, 2><<<nblk, 256, 0, st>>>((const cx<T>*)psi_v, (const cx<T>*)psi_c, nvs, ncs, tw,
                                                        (cx<T>*)q);
   else
@@ -266,10 +263,10 @@ bool pair_supported(int nd, int K) {
 }
 
 template <typename T>
-hipError_t launch_pair_planes(const Geom& g, const void* psi_v, const void* psi_c, int nvs, int ncs, void* q,
+hipError_t launch_pair_planes(const Geom& g, const void* psi_v, const void* psi_c, int nvs, int ncs, void* q, int minb,
                               hipStream_t st) {
 #define X(nd_, r_, k_) \
-  if (g.nd == nd_ && g.K == k_) return run_planes<T, nd_, r_, k_>(g, psi_v, psi_c, nvs, ncs, q, st);
+  if (g.nd == nd_ && g.K == k_) return run_planes<T, nd_, r_, k_>(g, psi_v, psi_c, nvs, ncs, q, minb, st);
   GW_PAIR_CASES(X)
 #undef X
   return hipErrorInvalidValue;
@@ -284,8 +281,10 @@ hipError_t launch_pair_finish(const Geom& g, const void* q, int npair, void* m, 
   return hipErrorInvalidValue;
 }
 
-template hipError_t launch_pair_planes<double>(const Geom&, const void*, const void*, int, int, void*, hipStream_t);
-template hipError_t launch_pair_planes<float>(const Geom&, const void*, const void*, int, int, void*, hipStream_t);
+template hipError_t launch_pair_planes<double>(const Geom&, const void*, const void*, int, int, void*, int,
+                                               hipStream_t);
+template hipError_t launch_pair_planes<float>(const Geom&, const void*, const void*, int, int, void*, int,
+                                              hipStream_t);
 template hipError_t launch_pair_finish<double>(const Geom&, const void*, int, void*, hipStream_t);
 template hipError_t launch_pair_finish<float>(const Geom&, const void*, int, void*, hipStream_t);
 

@@ -1,0 +1,99 @@
+"""Batched q-points / frequencies in one persistent contraction launch, graph capture and
+replay, and the launch-shape tuner -- all checked against the oracle and against
+separate eager calls."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from cases import Gpu, make_case, rel_err
+
+pytestmark = pytest.mark.gpu
+EV = synth.HARTREE_EV
+
+
+@pytest.fixture(scope="module")
+def g(gpu):
+    return Gpu()
+
+
+def ref_chi0(case, om, d):
+    return oracle.chi0_bands(case.coef_v, case.e_v, case.coef_c, case.e_c, case.gw, case.gc, (case.nd,) * 3, om, d)
+
+
+def test_batched_q_points_uneven_spheres_match_oracle_and_single_calls(g):
+    # the batched workload's q-points (NG 800 ... 3000), 3 frequencies with broadening
+    cases = [make_case(3, nv=4, nc=10, iq=iq) for iq in (0, 2, 5, 7)]
+    om = np.array([0.0, 12.0, 33.0]) / EV
+    d = 0.1 / EV
+    p = g.p
+    probs = [g.problem(c) for c in cases]
+    for prec, tol in (("fp64", 1e-10), ("fp32", 2e-5)):
+        got = p.gw_chi0_build(g.ctx, probs, [len(c.gc) for c in cases], om, d, p.PRECISIONS[prec])
+        g.torch.cuda.synchronize()
+        for c, x in zip(cases, got):
+            x = x.cpu().numpy()
+            ref = ref_chi0(c, om, d)
+            single = g.chi0(c, om, d, prec)
+            for i in range(len(om)):
+                fro, mx = rel_err(x[i], ref[i])
+                assert fro <= tol and mx <= tol, (prec, len(c.gc), i, fro, mx)
+                assert rel_err(x[i], single[i])[1] <= (1e-13 if prec == "fp64" else 1e-6)
+
+
+def test_more_than_sixteen_problems(g):
+    # 18 problems run as two batches of the persistent launch
+    base = make_case(0, nv=2, nc=3)
+    cases = [base] * 18
+    p = g.p
+    got = p.gw_chi0_build(g.ctx, [g.problem(c) for c in cases], [len(base.gc)] * 18, [0.0], 0.0, p.GW_FP64)
+    ref = ref_chi0(base, [0.0], 0.0)[0]
+    for x in got:
+        assert rel_err(x[0].cpu().numpy(), ref)[0] <= 1e-10
+
+
+def test_graph_capture_replays_match_eager(g):
+    torch = g.torch
+    p = g.p
+    case = make_case(0, nv=6, nc=30)
+    stream = torch.cuda.Stream()
+    ctx = p.gw_ctx_create(0, stream)
+    geom = p.gw_geom_create(ctx, (case.nd,) * 3, case.gw, case.gc)
+    cv, cc = g.t(case.coef_v), g.t(case.coef_c)
+    ev, ec = g.t(case.e_v.copy()), g.t(case.e_c.copy())
+    prob = p.make_problem(geom, cv, ev, cc, ec)
+    ng = len(case.gc)
+    om = [0.0, 5.0 / EV]
+    ws = torch.empty(p.gw_chi0_workspace_size(ctx, [prob], 2, p.GW_FP64), dtype=torch.uint8, device=g.dev)
+    out = torch.empty(2 * ng * ng, dtype=torch.complex128, device=g.dev)
+    with torch.cuda.stream(stream):
+        eager = p.gw_chi0_build(ctx, [prob], [ng], om, 0.05 / EV, p.GW_FP64, workspace=ws, out=out)[0].clone()
+        p.gw_ctx_set_graph(ctx, True)
+        for rep in range(3):
+            if rep == 2:
+                ec.add_(0.01)        # new data behind the same pointers: the replay must see it
+            got = p.gw_chi0_build(ctx, [prob], [ng], om, 0.05 / EV, p.GW_FP64, workspace=ws, out=out)[0].clone()
+            torch.cuda.synchronize()
+            # eager work between replays
+            _ = (got.abs() ** 2).sum().item()
+            if rep < 2:
+                assert torch.equal(got, eager)
+        p.gw_ctx_set_graph(ctx, False)
+        again = p.gw_chi0_build(ctx, [prob], [ng], om, 0.05 / EV, p.GW_FP64, workspace=ws, out=out)[0].clone()
+    torch.cuda.synchronize()
+    assert torch.equal(got, again)
+    assert not torch.equal(got, eager)
+    p.gw_geom_destroy(geom)
+    p.gw_ctx_destroy(ctx)
+
+
+def test_tuner_choices_keep_parity(g):
+    p = g.p
+    case = make_case(1, nv=8, nc=24)
+    prob = g.problem(case)
+    for prec, tol in (("fp64", 1e-10), ("fp32", 2e-5), ("bf16x3", 1e-4)):
+        p.gw_tune(g.ctx, [prob], 1, p.PRECISIONS[prec])
+        chi = g.chi0(case, prec=prec)[0]
+        ref = ref_chi0(case, [0.0], 0.0)[0]
+        fro, mx = rel_err(chi, ref)
+        assert fro <= tol and mx <= tol, (prec, fro, mx)
