@@ -49,6 +49,33 @@ def flops_model(nd, k, ng, npair, nband, with_inverse=True):
             "eps_inv": inverse, "total": (planes + finish + contract) * npair + band * nband + inverse}
 
 
+KERNEL_OF_STAGE = {"planes": ("pair_transform.hip", "k_pair_planes<{t}, 72, 8, 15"),
+                   "finish": ("pair_transform.hip", "k_pair_finish<{t}, 72, 8, 15"),
+                   "contract": ("contract.hip", "k_contract_batch<{m}>")}
+
+
+def measured_traffic(stage, mode):
+    """HBM bytes per launch of the stage's kernel from the committed FETCH_SIZE / WRITE_SIZE
+    summary, or None when that kernel's source changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+            tr = json.load(f)
+        src, pat = KERNEL_OF_STAGE[stage]
+        with open(os.path.join(ROOT, "paper_1601_06767_amd", "csrc", src), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != tr["sources"][src]:
+                return None
+        key = pat.format(t="double" if mode == "fp64" else "float", m={"fp64": 0, "fp32": 1, "bf16x3": 2}[mode])
+        for k, v in tr["kernels"].items():
+            if k.startswith(key):
+                return {"read_bytes": v["read_bytes_per_dispatch"], "write_bytes": v["write_bytes_per_dispatch"],
+                        "bytes": v["read_bytes_per_dispatch"] + v["write_bytes_per_dispatch"],
+                        "source": "profiles/chi0_build_72cube_512kpairs_hbm_counters.md"}
+    except (OSError, KeyError, ValueError):
+        pass
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,6 +84,10 @@ def main():
     ap.add_argument("--modes", default="fp64,fp32")
     ap.add_argument("--cpu-sample", type=int, default=16, help="valence bands in the oracle sample (0 = skip)")
     ap.add_argument("--cpu-cols", type=int, default=320)
+    ap.add_argument("--inputs-cache", default=None,
+                    help="npz file for the generated inputs: loaded if present, written otherwise")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the band sum shards over "
@@ -74,8 +105,16 @@ def main():
     gw = synth.wf_sphere(nd)
     gc = synth.chi_sphere(cfg.ng[0], cfg.qs[0], cfg.cell)
     t0 = time.time()
-    bands = synth.make_bands(cfg, gvec_wf=gw, device="cuda")
-    log(f"inputs: npw={len(gw)} ng={len(gc)} nv={cfg.nv} nc={cfg.nc} generated in {time.time() - t0:.1f}s")
+    if args.inputs_cache and os.path.exists(args.inputs_cache):
+        z = np.load(args.inputs_cache)
+        bands = synth.Bands(z["coef_v"], z["e_v"], z["coef_c"], z["e_c"], z["v_index"], z["c_index"])
+        log(f"inputs loaded from {args.inputs_cache}")
+    else:
+        bands = synth.make_bands(cfg, gvec_wf=gw, device="cuda")
+        if args.inputs_cache:
+            np.savez(args.inputs_cache, coef_v=bands.coef_v, e_v=bands.e_v, coef_c=bands.coef_c, e_c=bands.e_c,
+                     v_index=bands.v_index, c_index=bands.c_index)
+    log(f"inputs: npw={len(gw)} ng={len(gc)} nv={cfg.nv} nc={cfg.nc} ready in {time.time() - t0:.1f}s")
 
     ctx = p.gw_ctx_create(0)
     geom = p.gw_geom_create(ctx, (nd,) * 3, gw, gc)
@@ -150,8 +189,16 @@ def main():
         work = fl[dom if dom in fl else "planes"] / launches
     achieved = work / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None, "avg_launch_ms": avg_ms,
+                "frac": achieved / peak, "traffic": measured_traffic(dom, head), "avg_launch_ms": avg_ms,
                 "algorithmic_work_per_launch": work}
+
+    if args.copy_calibration:
+        x = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        torch.mul(x, 2.0, out=y)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written by one elementwise kernel")
+        del x, y
 
     cpu = None
     if args.cpu_sample > 0:

@@ -85,11 +85,15 @@ Layout make_layout(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nom
     items += (long long)q.ntl * nomega * L.nparts;
     L.pp.push_back(q);
   }
-  // split the pair ranges until the batch has about 8 items per CU (or a tuned choice)
+  // Split the pair ranges so that (a) the batch has about 8 items per CU and (b) the rows
+  // of M that the items in flight share (one pair range) stay near 32 MB, so they are
+  // served from cache instead of HBM; a tuned choice overrides.
   const long long want = 8LL * 256;
-  int ks = items >= want ? 1 : (int)std::min<long long>(32, (want + items - 1) / items);
+  const int ks_par = items >= want ? 1 : (int)std::min<long long>(32, (want + items - 1) / items);
   for (auto& q : L.pp) {
-    int k = ks;
+    const size_t mbytes = (size_t)q.npair * q.p->geom->g.ngp * L.csz;
+    const int ks_cache = (int)std::min<size_t>(32, (mbytes + (32u << 20) - 1) / (32u << 20));
+    int k = std::max(ks_par, ks_cache);
     auto it = ctx->tune.find(shape_key(q.p->geom->g, q.p->nv, q.p->ncol, prec));
     if (it != ctx->tune.end()) {
       q.minb = it->second.first;

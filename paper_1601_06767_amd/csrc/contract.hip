@@ -314,14 +314,17 @@ __device__ __forceinline__ void run_item(const void* m, const double* w, int nk,
     tile_bf16x3((const float2*)m, w, nk, ngp, ksplit, acc, t, ks);
 }
 
+// Items are ordered pair-range major (all tiles of range 0, then range 1, ...): the
+// workgroups in flight read the same few thousand rows of M, which stay in cache.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_contract(const void* __restrict__ m, const double* __restrict__ w, int nk,
-                                                  int ngp, int ksplit, double2* __restrict__ acc) {
-  run_item<MODE>(m, w, nk, ngp, ksplit, acc, blockIdx.x / ksplit, blockIdx.x % ksplit);
+                                                  int ngp, int ksplit, int ntl, double2* __restrict__ acc) {
+  run_item<MODE>(m, w, nk, ngp, ksplit, acc, blockIdx.x % ntl, blockIdx.x / ntl);
 }
 
 // Persistent grid over all items of a batch; items of problem b occupy
-// [item0[b], item0[b+1]) and decode as (job, tile, split), job = w_index * nparts + part.
+// [item0[b], item0[b+1]) and decode as (job, split, tile), job = w_index * nparts + part,
+// tile fastest (pair-range major, as above).
 template <int MODE>
 __global__ __launch_bounds__(256) void k_contract_batch(ContractBatch bt, int* __restrict__ counter) {
   __shared__ int s_item;
@@ -340,7 +343,7 @@ __global__ __launch_bounds__(256) void k_contract_batch(ContractBatch bt, int* _
     const int rem = (int)(local % per_job);
     const double* w = p.w + (size_t)job * p.nk;
     double2* acc = p.acc + (size_t)job * p.ksplit * p.ngp * p.ngp;
-    run_item<MODE>(p.m, w, p.nk, p.ngp, p.ksplit, acc, rem / p.ksplit, rem % p.ksplit);
+    run_item<MODE>(p.m, w, p.nk, p.ngp, p.ksplit, acc, rem % p.ntl, rem / p.ntl);
   }
 }
 
@@ -404,13 +407,14 @@ hipError_t launch_weights(const double* e_v, int v0, int nv_valid, int nvs, cons
 hipError_t launch_contract(int mode, const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
                            hipStream_t st) {
   const int nt = ngp / kTile;
-  const int nb = nt * (nt + 1) / 2 * ksplit;
+  const int ntl = nt * (nt + 1) / 2;
+  const int nb = ntl * ksplit;
   if (mode == 0)
-    k_contract<0><<<nb, 256, 0, st>>>(m, w, nk, ngp, ksplit, acc);
+    k_contract<0><<<nb, 256, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
   else if (mode == 1)
-    k_contract<1><<<nb, 256, 0, st>>>(m, w, nk, ngp, ksplit, acc);
+    k_contract<1><<<nb, 256, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
   else
-    k_contract<2><<<nb, 256, 0, st>>>(m, w, nk, ngp, ksplit, acc);
+    k_contract<2><<<nb, 256, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
   return hipGetLastError();
 }
 
