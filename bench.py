@@ -49,7 +49,7 @@ def flops_model(nd, k, ng, npair, nband, with_inverse=True):
             "eps_inv": inverse, "total": (planes + finish + contract) * npair + band * nband + inverse}
 
 
-KERNEL_OF_STAGE = {"planes": ("pair_transform.hip", "k_pair_planes<{t}, 72, 8, 15"),
+KERNEL_OF_STAGE = {"planes": ("pair_transform.hip", ("k_pair_planes<{t}, 72, 8, 15", "k_pair_planes_split<{t}, 72, 8, 15")),
                    "finish": ("pair_transform.hip", "k_pair_finish<{t}, 72, 8, 15"),
                    "contract": ("contract.hip", "k_contract_batch<{m}>")}
 
@@ -65,9 +65,11 @@ def measured_traffic(stage, mode):
         with open(os.path.join(ROOT, "paper_1601_06767_amd", "csrc", src), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != tr["sources"][src]:
                 return None
-        key = pat.format(t="double" if mode == "fp64" else "float", m={"fp64": 0, "fp32": 1, "bf16x3": 2}[mode])
+        pats = pat if isinstance(pat, tuple) else (pat,)
+        keys = tuple(p.format(t="double" if mode == "fp64" else "float", m={"fp64": 0, "fp32": 1, "bf16x3": 2}[mode])
+                     for p in pats)
         for k, v in tr["kernels"].items():
-            if k.startswith(key):
+            if k.startswith(keys):
                 return {"read_bytes": v["read_bytes_per_dispatch"], "write_bytes": v["write_bytes_per_dispatch"],
                         "bytes": v["read_bytes_per_dispatch"] + v["write_bytes_per_dispatch"],
                         "source": "profiles/chi0_build_72cube_512kpairs_hbm_counters.md"}
@@ -84,6 +86,7 @@ def main():
     ap.add_argument("--modes", default="fp64,fp32")
     ap.add_argument("--cpu-sample", type=int, default=16, help="valence bands in the oracle sample (0 = skip)")
     ap.add_argument("--cpu-cols", type=int, default=320)
+    ap.add_argument("--tune", action="store_true", help="run the launch-shape tuner before timing each mode")
     ap.add_argument("--inputs-cache", default=None,
                     help="npz file for the generated inputs: loaded if present, written otherwise")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -137,6 +140,10 @@ def main():
     stream = torch.cuda.current_stream()
     for m in modes:
         out = torch.empty(ng * ng, dtype=torch.complex128, device=dev)
+        if args.tune:
+            p.gw_tune(ctx, [prob], 1, p.PRECISIONS[m], workspace=ws)
+            log(f"{m}: tuned (pair-kernel form, contraction splits) = {p.gw_tune_get(ctx, prob, p.PRECISIONS[m])}")
+
         def run():
             p.gw_chi0_build(ctx, [prob], [ng], [0.0], 0.0, p.PRECISIONS[m], workspace=ws, out=out)
             p.gw_eps_inv(ctx, vcoul, out.view(ng, ng), workspace=ws_inv, out=zout)

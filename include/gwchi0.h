@@ -175,14 +175,18 @@ gw_status gw_chi0_backward(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob,
  * Needs a context on a non-null stream.  Disabling drops the cached graphs. */
 gw_status gw_ctx_set_graph(gw_ctx* ctx, int enable);
 
-/* Launch-shape tuner: on the first conduction chunk of each problem, times the pair
- * kernel compiled for one or two resident workgroups per CU and the contraction with
+/* Launch-shape tuner: on the first conduction chunk of each problem, times the three
+ * forms of the pair kernel and the contraction with
  * 1..32 pair-range splits, and keeps the fastest per problem shape in the context.
  * Later gw_chi0_workspace_size / gw_chi0_build calls use the tuned shapes (query the
  * workspace size again after tuning).  Synchronises the stream; workspace as for
  * gw_chi0_build. */
 gw_status gw_tune(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, gw_precision prec,
                   void* workspace, size_t ws_bytes);
+/* The tuned shapes for prob's problem shape: pair-kernel form (1, 2 = 256 threads with
+ * one or two resident workgroups per CU, 3 = 512-thread split-line form) and the number
+ * of pair-range splits of the contraction; both 0 if the shape was not tuned. */
+gw_status gw_tune_get(gw_ctx* ctx, const gw_chi0_problem* prob, gw_precision prec, int* pair_variant, int* ksplit);
 
 /* Workspace bytes for gw_pair_density with an nvs x ncs block. */
 gw_status gw_pair_density_workspace_size(gw_ctx* ctx, const gw_chi0_problem* prob, int nvs, int ncs,

@@ -69,11 +69,12 @@ _sig("gw_group_windows", C.c_int, [C.c_int, dp, C.c_double, C.c_double, C.c_int,
 _sig("gw_ctx_set_timing", C.c_int, [vp, C.c_int])
 _sig("gw_ctx_set_graph", C.c_int, [vp, C.c_int])
 _sig("gw_tune", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, C.c_int, vp, C.c_size_t])
+_sig("gw_tune_get", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)])
 _sig("gw_ctx_stage_times", C.c_int, [vp, dp, C.POINTER(C.c_longlong), C.c_int])
 
 STAGES = ["band", "planes", "finish", "weights", "contract", "finalize", "eps_inv", "backward"]
 
-EXPORTED = ["gw_ctx_set_timing", "gw_ctx_stage_times", "gw_ctx_set_graph", "gw_tune",
+EXPORTED = ["gw_ctx_set_timing", "gw_ctx_stage_times", "gw_ctx_set_graph", "gw_tune", "gw_tune_get",
             "gw_version", "gw_ctx_create", "gw_ctx_destroy", "gw_last_error", "gw_geom_create", "gw_geom_destroy",
             "gw_chi0_workspace_size", "gw_chi0_build", "gw_chi0_backward", "gw_pair_density_workspace_size", "gw_pair_density",
             "gw_eps_inv_workspace_size", "gw_eps_inv", "gw_eps_inv_status", "gw_eps_inv_backward",
@@ -134,6 +135,13 @@ def gw_tune(ctx, problems, nomega: int, prec: int, workspace=None) -> None:
         workspace = torch.empty(gw_chi0_workspace_size(ctx, arr, nomega, prec), dtype=torch.uint8,
                                 device=torch.device("cuda", torch.cuda.current_device()))
     _check(lib.gw_tune(ctx, arr, len(arr), nomega, prec, _ptr(workspace), workspace.numel()), ctx)
+
+
+def gw_tune_get(ctx, problem, prec: int):
+    """(pair-kernel form, contraction splits) tuned for this problem's shape, (0, 0) if untuned."""
+    a, b = C.c_int(), C.c_int()
+    _check(lib.gw_tune_get(ctx, C.byref(problem), prec, C.byref(a), C.byref(b)), ctx)
+    return a.value, b.value
 
 
 def gw_ctx_stage_times(ctx, reset: bool = False) -> dict:

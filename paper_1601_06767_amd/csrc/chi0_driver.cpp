@@ -503,7 +503,7 @@ gw_status gw_tune(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nome
     const std::string key = shape_key(p.geom->g, p.nv, p.ncol, prec);
     int best_minb = 0, best_ks = 0;
     float best = 1e30f;
-    // pair kernel: one or two resident workgroups per CU
+    // pair kernel: 256 threads with one or two resident workgroups per CU, or the 512-thread split-line form
     Layout L = make_layout(ctx, &p, 1, std::max(1, nomega), false, prec, false);
     if (L.total > ws_bytes) {
       result = gw::fail(ctx, GW_EINVAL, "workspace too small for tuning");
@@ -514,7 +514,7 @@ gw_status gw_tune(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nome
     if (result == GW_OK)
       result = band_to_real(ctx, L, p.geom->g, (const double2*)p.coef_c, p.nband, p.col_band, 0, p.ncol, q.cc, ws,
                             ws + L.off_psic);
-    for (int minb = 1; minb <= 2 && result == GW_OK; ++minb) {
+    for (int minb = 1; minb <= 3 && result == GW_OK; ++minb) {
       q.minb = minb;
       float t0 = 0, t1 = 0;
       result = timed([&] { return pair_block(ctx, L, q, ws); }, &t0);   // warm-up
@@ -572,6 +572,15 @@ gw_status gw_tune(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nome
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   return result;
+}
+
+gw_status gw_tune_get(gw_ctx* ctx, const gw_chi0_problem* prob, gw_precision prec, int* pair_variant, int* ksplit) {
+  if (!ctx) return GW_EINVAL;
+  if (!prob || !prob->geom || !pair_variant || !ksplit) return gw::fail(ctx, GW_EINVAL, "bad arguments");
+  auto it = ctx->tune.find(shape_key(prob->geom->g, prob->nv, prob->ncol, prec));
+  *pair_variant = it == ctx->tune.end() ? 0 : it->second.first;
+  *ksplit = it == ctx->tune.end() ? 0 : it->second.second;
+  return GW_OK;
 }
 
 }  // extern "C"

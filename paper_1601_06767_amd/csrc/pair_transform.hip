@@ -6,10 +6,9 @@
 // k_pair_planes (one x1 plane, 4 x 8 pairs per workgroup):
 //   stage 1, per lane one (pair, x2 row): the product along x3 and a pruned x3
 //     transform, x3 = b + S a:  X[n] = sum_b e^{2 pi i n b/N} DFT_R(x[b + S a])[n mod R],
-//     n in [-rchi, rchi] -> Z[pair][row][n3] in LDS.  The conduction rows arrive one
-//     radix-R chunk (one b) at a time through a double buffer in LDS, the next chunk
-//     in flight while the current one is used; valence rows are read directly (eight
-//     lanes share each row);
+//     n in [-rchi, rchi] -> Z[pair][row][n3] in LDS.  The conduction and valence rows
+//     arrive one radix-R chunk (one b) at a time through a double buffer in LDS, the
+//     next chunk in flight while the current one is used;
 //   stage 2, per lane (pair, n3): the same split along x2 over the 8 rows of each
 //     x2 group (x2 = b2 + S2 a2), accumulated over the S2 groups in registers;
 //   output Q[pair][p1][n2][n3] for this plane (p1 = plane stored permuted).
@@ -27,13 +26,14 @@ namespace {
 constexpr int kTV = 4;              // valence bands per workgroup (one per wave)
 constexpr int kTC = 64 / kRows;     // conduction columns per workgroup (8)
 
-// LDS of one workgroup: a double buffer with the radix-R chunk (one b of the x3 split)
-// of the 64 conduction rows in flight, and Z of the current x2 group.
+// LDS of one workgroup: double buffers with the radix-R chunk (one b of the x3 split) of
+// the 64 conduction rows and the 32 valence rows in flight, and Z of the current x2 group.
 template <typename T, int R, int K>
 struct PlaneLds {
   static constexpr int rp = R + 1;   // padded chunk row: the 8 rows read together fall on distinct banks
   static constexpr size_t chunk = (size_t)kTC * kRows * rp;
-  static constexpr size_t bytes = (2 * chunk + (size_t)kTV * kTC * kRows * K) * sizeof(cx<T>);
+  static constexpr size_t vchunk = (size_t)kTV * kRows * rp;
+  static constexpr size_t bytes = (2 * chunk + 2 * vchunk + (size_t)kTV * kTC * kRows * K) * sizeof(cx<T>);
 };
 
 // Two resident workgroups per CU when the per-lane state (Q of IPL items, the stage-1
@@ -58,9 +58,12 @@ __global__ __launch_bounds__(256, MINB) void k_pair_planes(const cx<T>* __restri
   constexpr int NPAIR = kTV * kTC;
   constexpr int NITEM = NPAIR * K;
   constexpr int IPL = (NITEM + 255) / 256;
-  constexpr int PER = kTC * kRows * R / 256;   // chunk elements per thread
+  constexpr int CH = kTC * kRows * R;          // conduction chunk elements
+  constexpr int CV = kTV * kRows * R;          // valence chunk elements
+  constexpr int PER = (CH + CV) / 256;         // chunk elements per thread
   constexpr size_t NPL = (size_t)ND * ND;
   __shared__ V s_c[2 * L::chunk];
+  __shared__ V s_v[2 * L::vchunk];
   __shared__ V s_z[NPAIR * kRows * K];
 
   const int nbc = ncs / kTC;
@@ -76,24 +79,30 @@ __global__ __launch_bounds__(256, MINB) void k_pair_planes(const cx<T>* __restri
   const int cl = lane / kRows;        // conduction column of this lane
   const int a2 = lane % kRows;        // row within the x2 group
 
-  // chunk staging: element e = row * R + a of step s (x2 group s / S, x3 group b = s % S)
+  // chunk staging: element e of step s (x2 group s / S, x3 group b = s % S); conduction
+  // rows first, then valence rows
   const V* pc_base = psi_c + ((size_t)c0 * ND + x1) * NPL;
+  const V* pv_base = psi_v + ((size_t)v0 * ND + x1) * NPL;
   V pf[PER];
   auto fetch = [&](int st) {
     const int g2 = st / S, b = st % S;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int e = tid + 256 * i;
-      const int row = e / R, a = e % R;
-      const int c = row / kRows, r = row % kRows;
-      pf[i] = pc_base[(size_t)c * ND * NPL + (size_t)(g2 * kRows + r) * ND + b * R + a];
+      const int e2 = e < CH ? e : e - CH;
+      const int row = e2 / R, a = e2 % R;
+      const V* base = e < CH ? pc_base : pv_base;
+      pf[i] = base[(size_t)(row / kRows) * ND * NPL + (size_t)(g2 * kRows + row % kRows) * ND + b * R + a];
     }
   };
   auto stash = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int e = tid + 256 * i;
-      s_c[buf * L::chunk + (e / R) * L::rp + e % R] = pf[i];
+      if (e < CH)
+        s_c[buf * L::chunk + (e / R) * L::rp + e % R] = pf[i];
+      else
+        s_v[buf * L::vchunk + ((e - CH) / R) * L::rp + (e - CH) % R] = pf[i];
     }
   };
 
@@ -103,26 +112,24 @@ __global__ __launch_bounds__(256, MINB) void k_pair_planes(const cx<T>* __restri
 #pragma unroll
     for (int j = 0; j < K; ++j) qacc[r][j] = V{T(0), T(0)};
 
-  const V* pv_plane = psi_v + ((size_t)(v0 + wv) * ND + x1) * NPL;
   fetch(0);
   stash(0);
   __syncthreads();
 
   for (int b2 = 0; b2 < S2; ++b2) {
     // ---------------- stage 1: one (pair, x2 row) line per lane
-    const V* rv = pv_plane + (size_t)(b2 * kRows + a2) * ND;
     V acc[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) acc[j] = V{T(0), T(0)};
-    // kept rolled: unrolled, the valence loads of all S chunks would be hoisted and spill
 #pragma unroll 1
     for (int b = 0; b < S; ++b) {
       const int st = b2 * S + b;
       if (st + 1 < NSTEP) fetch(st + 1);
       const V* rc = s_c + (st & 1) * L::chunk + (cl * kRows + a2) * L::rp;
+      const V* rv = s_v + (st & 1) * L::vchunk + (wv * kRows + a2) * L::rp;
       V x[R];
 #pragma unroll
-      for (int a = 0; a < R; ++a) x[a] = cmulc(rv[b * R + a], rc[a]);
+      for (int a = 0; a < R; ++a) x[a] = cmulc(rv[a], rc[a]);
       dft<R>(x);
 #pragma unroll
       for (int j = 0; j < K; ++j) {
@@ -162,6 +169,181 @@ __global__ __launch_bounds__(256, MINB) void k_pair_planes(const cx<T>* __restri
 #pragma unroll
   for (int r = 0; r < IPL; ++r) {
     const int it = tid + 256 * r;
+    if (it < NITEM) {
+      const int pair = it / K, j3 = it % K;
+      const int pv = pair / kTC, pc = pair % kTC;
+      const size_t pg = (size_t)(v0 + pv) * ncs + (c0 + pc);
+      V* dst = q + (pg * ND + p1) * (K * K) + j3;
+#pragma unroll
+      for (int j = 0; j < K; ++j) dst[j * K] = qacc[r][j];
+    }
+  }
+}
+
+// Split-line variant, 512 threads: waves 0-3 and 4-7 take the first and second half of
+// each line's x3 chunks (b < SL and b >= SL), so every lane carries half the stage-1
+// work and one stage-2 item; the two partial Z halves are added in LDS.  It halves the
+// per-lane register state of the 256-thread kernel (no spills in float64).
+template <typename T, int R, int K>
+struct SplitLds {
+  static constexpr int rp = R + 1;
+  static constexpr size_t chunk = (size_t)kTC * kRows * rp;    // one radix-R chunk of the 64 conduction rows
+  static constexpr size_t vchunk = (size_t)kTV * kRows * rp;   // and of the 32 valence rows
+  static constexpr size_t bytes = (2 * 2 * (chunk + vchunk) + (size_t)kTV * kTC * kRows * K) * sizeof(cx<T>);
+};
+
+template <typename T, int R, int K>
+constexpr bool split_fits() {
+  return SplitLds<T, R, K>::bytes <= 160 * 1024;
+}
+
+// float64 shapes whose split-line kernel holds its state in registers: there it runs
+// ahead of the 256-thread kernel, which needs one resident workgroup per CU
+template <typename T, int R, int K>
+constexpr bool split_preferred() {
+  return std::is_same<T, double>::value && R == 8 && K <= 15 && split_fits<T, R, K>();
+}
+
+template <typename T, int ND, int R, int K>
+__global__ __launch_bounds__(512, 1) void k_pair_planes_split(const cx<T>* __restrict__ psi_v,
+                                                              const cx<T>* __restrict__ psi_c, int nvs, int ncs,
+                                                              const cx<T>* __restrict__ tw, cx<T>* __restrict__ q) {
+  using V = cx<T>;
+  using L = SplitLds<T, R, K>;
+  constexpr int S = ND / R;
+  constexpr int SL = (S + 1) / 2;        // chunks of the first half
+  constexpr int SH = S - SL;             // chunks of the second half
+  constexpr int S2 = ND / kRows;
+  constexpr int NSTEP = S2 * SL;
+  constexpr int RCH = (K - 1) / 2;
+  constexpr int NPAIR = kTV * kTC;
+  constexpr int NITEM = NPAIR * K;
+  constexpr int IPL = (NITEM + 511) / 512;
+  constexpr int CH = kTC * kRows * R;    // conduction elements of one chunk
+  constexpr int CV = kTV * kRows * R;    // valence elements of one chunk
+  constexpr int PER = 2 * (CH + CV) / 512;
+  constexpr size_t NPL = (size_t)ND * ND;
+  __shared__ V s_c[2 * 2 * L::chunk];   // [buffer][half][row][rp]
+  __shared__ V s_v[2 * 2 * L::vchunk];
+  __shared__ V s_z[NPAIR * kRows * K];
+
+  const int nbc = ncs / kTC;
+  const int nbv = nvs / kTV;
+  const int pb = blockIdx.x % (nbc * nbv);
+  const int x1 = blockIdx.x / (nbc * nbv);
+  const int c0 = (pb % nbc) * kTC;
+  const int v0 = (pb / nbc) * kTV;
+
+  const int tid = threadIdx.x;
+  // wave-uniform: the chunk index b and its twiddles then live in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wv = wave & 3;            // valence band of this wave
+  const int hf = wave >> 2;           // half of the x3 chunks
+  const int lane = tid & 63;
+  const int cl = lane / kRows;
+  const int a2 = lane % kRows;
+
+  // element e of a step: half h = e / (CH + CV), then conduction rows, then valence rows
+  const V* pc_base = psi_c + ((size_t)c0 * ND + x1) * NPL;
+  const V* pv_base = psi_v + ((size_t)v0 * ND + x1) * NPL;
+  V pf[PER];
+  auto fetch = [&](int st) {
+    const int g2 = st / SL, t = st % SL;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + 512 * i;
+      const int h = e / (CH + CV), e1 = e % (CH + CV);
+      const int e2 = e1 < CH ? e1 : e1 - CH;
+      const int row = e2 / R, a = e2 % R;
+      const int b = h ? SL + t : t;
+      const V* base = e1 < CH ? pc_base : pv_base;
+      V x{T(0), T(0)};
+      if (b < S) x = base[(size_t)(row / kRows) * ND * NPL + (size_t)(g2 * kRows + row % kRows) * ND + b * R + a];
+      pf[i] = x;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + 512 * i;
+      const int h = e / (CH + CV), e1 = e % (CH + CV);
+      if (e1 < CH)
+        s_c[(buf * 2 + h) * L::chunk + (e1 / R) * L::rp + e1 % R] = pf[i];
+      else
+        s_v[(buf * 2 + h) * L::vchunk + ((e1 - CH) / R) * L::rp + (e1 - CH) % R] = pf[i];
+    }
+  };
+
+  V qacc[IPL][K];
+#pragma unroll
+  for (int r = 0; r < IPL; ++r)
+#pragma unroll
+    for (int j = 0; j < K; ++j) qacc[r][j] = V{T(0), T(0)};
+
+  fetch(0);
+  stash(0);
+  __syncthreads();
+
+  for (int b2 = 0; b2 < S2; ++b2) {
+    V acc[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) acc[j] = V{T(0), T(0)};
+#pragma unroll 1
+    for (int t = 0; t < SL; ++t) {
+      const int st = b2 * SL + t;
+      if (st + 1 < NSTEP) fetch(st + 1);
+      const int b = hf ? SL + t : t;
+      if (hf == 0 || t < SH) {
+        const V* rc = s_c + ((st & 1) * 2 + hf) * L::chunk + (cl * kRows + a2) * L::rp;
+        const V* rv = s_v + ((st & 1) * 2 + hf) * L::vchunk + (wv * kRows + a2) * L::rp;
+        V x[R];
+#pragma unroll
+        for (int a = 0; a < R; ++a) x[a] = cmulc(rv[a], rc[a]);
+        dft<R>(x);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const int n = j - RCH;
+          const V tv = tw[((n * b) % ND + ND) % ND];
+          cmac(acc[j], tv, x[((n % R) + R) % R]);
+        }
+      }
+      if (st + 1 < NSTEP) stash((st + 1) & 1);
+      __syncthreads();
+    }
+    V* z = s_z + ((wv * kTC + cl) * kRows + a2) * K;
+    if (hf == 1) {
+#pragma unroll
+      for (int j = 0; j < K; ++j) z[j] = acc[j];
+    }
+    __syncthreads();
+    if (hf == 0) {
+#pragma unroll
+      for (int j = 0; j < K; ++j) z[j] = cadd(z[j], acc[j]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < IPL; ++r) {
+      const int it = tid + 512 * r;
+      if (it < NITEM) {
+        const int pair = it / K, j3 = it % K;
+        V y[kRows];
+#pragma unroll
+        for (int a = 0; a < kRows; ++a) y[a] = s_z[(pair * kRows + a) * K + j3];
+        dft<kRows>(y);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const int n = j - RCH;
+          const V tv = tw[((n * b2) % ND + ND) % ND];
+          cmac(qacc[r][j], tv, y[((n % kRows) + kRows) % kRows]);
+        }
+      }
+    }
+    // s_z is rewritten only after the SL barriers of the next group's stage 1
+  }
+  const int p1 = (x1 % S) * R + x1 / S;
+#pragma unroll
+  for (int r = 0; r < IPL; ++r) {
+    const int it = tid + 512 * r;
     if (it < NITEM) {
       const int pair = it / K, j3 = it % K;
       const int pv = pair / kTC, pc = pair % kTC;
@@ -215,7 +397,18 @@ hipError_t run_planes(const Geom& g, const void* psi_v, const void* psi_c, int n
                       hipStream_t st) {
   const cx<T>* tw = std::is_same<T, double>::value ? (const cx<T>*)g.d_tw64 : (const cx<T>*)g.d_tw32;
   const int nblk = ND * (nvs / kTV) * (ncs / kTC);
-  if (minb == 2 || (minb == 0 && planes_min_blocks<T, R, K>() == 2))
+  // variant: 1 / 2 = 256-thread kernel with one / two resident workgroups per CU,
+  // 3 = 512-thread split-line kernel, 0 = split-line where preferred, else by register demand
+  int variant = minb;
+  if (variant == 0) variant = split_preferred<T, R, K>() ? 3 : planes_min_blocks<T, R, K>();
+  if constexpr (split_fits<T, R, K>()) {
+    if (variant == 3) {
+      k_pair_planes_split<T, ND, R, K><<<nblk, 512, 0, st>>>((const cx<T>*)psi_v, (const cx<T>*)psi_c, nvs, ncs, tw,
+                                                            (cx<T>*)q);
+      return hipGetLastError();
+    }
+  }
+  if (variant == 2)
     k_pair_planes<T, ND, R, K, 2><<<nblk, 256, 0, st>>>((const cx<T>*)psi_v, (const cx<T>*)psi_c, nvs, ncs, tw,
                                                        (cx<T>*)q);
   else
