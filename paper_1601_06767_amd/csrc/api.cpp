@@ -168,6 +168,16 @@ gw_status gw_geom_create(gw_ctx* ctx, const int n_fft[3], int npw, const int32_t
     tw64[j] = double2{(double)cosl(a), (double)sinl(a)};
     tw32[j] = float2{(float)cosl(a), (float)sinl(a)};
   }
+  // the twiddles of the pruned outputs per chunk index b: kernels index them by (b, j) alone
+  const size_t ntwk = (size_t)nd * g.K;
+  std::vector<double2> twk64(ntwk);
+  std::vector<float2> twk32(ntwk);
+  for (int b = 0; b < nd; ++b)
+    for (int j = 0; j < g.K; ++j) {
+      const int k = (((j - rc) * b) % nd + nd) % nd;
+      twk64[(size_t)b * g.K + j] = tw64[k];
+      twk32[(size_t)b * g.K + j] = tw32[k];
+    }
   gw_geom* gg = new (std::nothrow) gw_geom();
   if (!gg) return gw::fail(ctx, GW_ENOMEM, "out of host memory");
   gg->ctx = ctx;
@@ -179,10 +189,14 @@ gw_status gw_geom_create(gw_ctx* ctx, const int n_fft[3], int npw, const int32_t
   e = e == hipSuccess ? hipMalloc(&g.d_chi_map, chi_map.size() * 4) : e;
   e = e == hipSuccess ? hipMalloc(&g.d_tw64, nd * sizeof(double2)) : e;
   e = e == hipSuccess ? hipMalloc(&g.d_tw32, nd * sizeof(float2)) : e;
+  e = e == hipSuccess ? hipMalloc(&g.d_twk64, ntwk * sizeof(double2)) : e;
+  e = e == hipSuccess ? hipMalloc(&g.d_twk32, ntwk * sizeof(float2)) : e;
   if (e == hipSuccess) e = hipMemcpy(g.d_wf_map, wf_map.data(), wf_map.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(g.d_chi_map, chi_map.data(), chi_map.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(g.d_tw64, tw64.data(), nd * sizeof(double2), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(g.d_tw32, tw32.data(), nd * sizeof(float2), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(g.d_twk64, twk64.data(), ntwk * sizeof(double2), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(g.d_twk32, twk32.data(), ntwk * sizeof(float2), hipMemcpyHostToDevice);
   (void)hipSetDevice(prev);
   gg->g = g;
   if (e != hipSuccess) {
@@ -200,6 +214,8 @@ gw_status gw_geom_destroy(gw_geom* geom) {
   if (g.d_chi_map) (void)hipFree(g.d_chi_map);
   if (g.d_tw64) (void)hipFree(g.d_tw64);
   if (g.d_tw32) (void)hipFree(g.d_tw32);
+  if (g.d_twk64) (void)hipFree(g.d_twk64);
+  if (g.d_twk32) (void)hipFree(g.d_twk32);
   delete geom;
   return GW_OK;
 }

@@ -97,6 +97,8 @@ struct Geom {
   int32_t* d_chi_map = nullptr;  // K^3 box -> chi index or -1
   double2* d_tw64 = nullptr;     // exp(+2 pi i j / nd), j < nd
   float2* d_tw32 = nullptr;
+  double2* d_twk64 = nullptr;    // [b][j] = exp(+2 pi i (j - rchi) b / nd), b < nd, j < K
+  float2* d_twk32 = nullptr;
 };
 
 }  // namespace gw

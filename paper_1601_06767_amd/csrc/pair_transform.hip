@@ -48,7 +48,7 @@ constexpr int planes_min_blocks() {
 template <typename T, int ND, int R, int K, int MINB>
 __global__ __launch_bounds__(256, MINB) void k_pair_planes(const cx<T>* __restrict__ psi_v,
                                                         const cx<T>* __restrict__ psi_c, int nvs, int ncs,
-                                                        const cx<T>* __restrict__ tw, cx<T>* __restrict__ q) {
+                                                        const cx<T>* __restrict__ twk, cx<T>* __restrict__ q) {
   using V = cx<T>;
   using L = PlaneLds<T, R, K>;
   constexpr int S = ND / R;
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256, MINB) void k_pair_planes(const cx<T>* __restri
 #pragma unroll
       for (int j = 0; j < K; ++j) {
         const int n = j - RCH;
-        const V t = tw[((n * b) % ND + ND) % ND];
+        const V t = twk[b * K + j];
         cmac(acc[j], t, x[((n % R) + R) % R]);
       }
       if (st + 1 < NSTEP) stash((st + 1) & 1);
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(256, MINB) void k_pair_planes(const cx<T>* __restri
 #pragma unroll
         for (int j = 0; j < K; ++j) {
           const int n = j - RCH;
-          const V t = tw[((n * b2) % ND + ND) % ND];
+          const V t = twk[b2 * K + j];
           cmac(qacc[r][j], t, y[((n % kRows) + kRows) % kRows]);
         }
       }
@@ -207,7 +207,7 @@ constexpr bool split_preferred() {
 template <typename T, int ND, int R, int K>
 __global__ __launch_bounds__(512, 1) void k_pair_planes_split(const cx<T>* __restrict__ psi_v,
                                                               const cx<T>* __restrict__ psi_c, int nvs, int ncs,
-                                                              const cx<T>* __restrict__ tw, cx<T>* __restrict__ q) {
+                                                              const cx<T>* __restrict__ twk, cx<T>* __restrict__ q) {
   using V = cx<T>;
   using L = SplitLds<T, R, K>;
   constexpr int S = ND / R;
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(512, 1) void k_pair_planes_split(const cx<T>* __res
 #pragma unroll
         for (int j = 0; j < K; ++j) {
           const int n = j - RCH;
-          const V tv = tw[((n * b) % ND + ND) % ND];
+          const V tv = twk[b * K + j];
           cmac(acc[j], tv, x[((n % R) + R) % R]);
         }
       }
@@ -333,7 +333,7 @@ __global__ __launch_bounds__(512, 1) void k_pair_planes_split(const cx<T>* __res
 #pragma unroll
         for (int j = 0; j < K; ++j) {
           const int n = j - RCH;
-          const V tv = tw[((n * b2) % ND + ND) % ND];
+          const V tv = twk[b2 * K + j];
           cmac(qacc[r][j], tv, y[((n % kRows) + kRows) % kRows]);
         }
       }
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(512, 1) void k_pair_planes_split(const cx<T>* __res
 
 template <typename T, int ND, int R, int K>
 __global__ __launch_bounds__(256) void k_pair_finish(const cx<T>* __restrict__ q, const int32_t* __restrict__ chi_map,
-                                                     int ng, int ngp, T scale, const cx<T>* __restrict__ tw,
+                                                     int ng, int ngp, T scale, const cx<T>* __restrict__ twk,
                                                      cx<T>* __restrict__ m) {
   using V = cx<T>;
   constexpr int S = ND / R;
@@ -379,7 +379,7 @@ __global__ __launch_bounds__(256) void k_pair_finish(const cx<T>* __restrict__ q
 #pragma unroll
       for (int j = 0; j < K; ++j) {
         const int n = j - RCH;
-        const V t = tw[((n * b) % ND + ND) % ND];
+        const V t = twk[b * K + j];
         cmac(acc[j], t, x[((n % R) + R) % R]);
       }
     }
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(256) void k_pair_finish(const cx<T>* __restrict__ q
 template <typename T, int ND, int R, int K>
 hipError_t run_planes(const Geom& g, const void* psi_v, const void* psi_c, int nvs, int ncs, void* q, int minb,
                       hipStream_t st) {
-  const cx<T>* tw = std::is_same<T, double>::value ? (const cx<T>*)g.d_tw64 : (const cx<T>*)g.d_tw32;
+  const cx<T>* tw = std::is_same<T, double>::value ? (const cx<T>*)g.d_twk64 : (const cx<T>*)g.d_twk32;
   const int nblk = ND * (nvs / kTV) * (ncs / kTC);
   // variant: 1 / 2 = 256-thread kernel with one / two resident workgroups per CU,
   // 3 = 512-thread split-line kernel, 0 = split-line where preferred, else by register demand
@@ -419,7 +419,7 @@ hipError_t run_planes(const Geom& g, const void* psi_v, const void* psi_c, int n
 
 template <typename T, int ND, int R, int K>
 hipError_t run_finish(const Geom& g, const void* q, int npair, void* m, hipStream_t st) {
-  const cx<T>* tw = std::is_same<T, double>::value ? (const cx<T>*)g.d_tw64 : (const cx<T>*)g.d_tw32;
+  const cx<T>* tw = std::is_same<T, double>::value ? (const cx<T>*)g.d_twk64 : (const cx<T>*)g.d_twk32;
   const T scale = T(1.0 / ((double)ND * ND * ND));
   k_pair_finish<T, ND, R, K><<<npair, 256, 0, st>>>((const cx<T>*)q, g.d_chi_map, g.ng, g.ngp, scale, tw,
                                                     (cx<T>*)m);
