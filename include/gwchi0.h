@@ -184,8 +184,9 @@ gw_status gw_ctx_set_graph(gw_ctx* ctx, int enable);
 gw_status gw_tune(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, gw_precision prec,
                   void* workspace, size_t ws_bytes);
 /* The tuned shapes for prob's problem shape: pair-kernel form (1, 2 = 256 threads with
- * one or two resident workgroups per CU, 3 = 512-thread split-line form) and the number
- * of pair-range splits of the contraction; both 0 if the shape was not tuned. */
+ * one or two resident workgroups per CU, 3 / 4 = split-line form with 4 / 2 valence bands
+ * per workgroup) and the number of pair-range splits of the contraction; both 0 if the
+ * shape was not tuned. */
 gw_status gw_tune_get(gw_ctx* ctx, const gw_chi0_problem* prob, gw_precision prec, int* pair_variant, int* ksplit);
 
 /* Workspace bytes for gw_pair_density with an nvs x ncs block. */

@@ -122,7 +122,8 @@ size_t band_scratch_bytes(const Geom& g, int nslot, bool fp64);
 // Pair planes: Q[pair][p1][j2][j3] for pairs (v, c), v < nvs (multiple of 4), c < ncs (multiple of 8);
 // pair = v * ncs + c.
 // minb: 0 = automatic, 1 or 2 = 256-thread kernel with that many resident workgroups per CU,
-// 3 = 512-thread split-line kernel (falls back to 2 where its LDS does not fit).
+// 3 / 4 = split-line kernel with 4 / 2 valence bands per workgroup (falls back to the
+// 256-thread kernel where its LDS does not fit).
 template <typename T>
 hipError_t launch_pair_planes(const Geom& g, const void* psi_v, const void* psi_c, int nvs, int ncs, void* q,
                               int minb, hipStream_t st);

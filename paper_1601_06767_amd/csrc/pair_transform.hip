@@ -180,65 +180,69 @@ __global__ __launch_bounds__(256, MINB) void k_pair_planes(const cx<T>* __restri
   }
 }
 
-// Split-line variant, 512 threads: waves 0-3 and 4-7 take the first and second half of
-// each line's x3 chunks (b < SL and b >= SL), so every lane carries half the stage-1
-// work and one stage-2 item; the two partial Z halves are added in LDS.  It halves the
-// per-lane register state of the 256-thread kernel (no spills in float64).
-template <typename T, int R, int K>
+// Split-line variant, TV valence bands x 8 conduction columns per workgroup, 128 TV
+// threads: waves [0, TV) and [TV, 2 TV) take the first and second half of each line's
+// x3 chunks (b < SL and b >= SL), so every lane carries half the stage-1 work and at most
+// one stage-2 item; the two partial Z halves are added in LDS.  It halves the per-lane
+// register state of the 256-thread kernel (no spills in float64); TV = 2 also halves the
+// LDS, so that two workgroups share a CU.
+template <typename T, int R, int K, int TV>
 struct SplitLds {
   static constexpr int rp = R + 1;
-  static constexpr size_t chunk = (size_t)kTC * kRows * rp;    // one radix-R chunk of the 64 conduction rows
-  static constexpr size_t vchunk = (size_t)kTV * kRows * rp;   // and of the 32 valence rows
-  static constexpr size_t bytes = (2 * 2 * (chunk + vchunk) + (size_t)kTV * kTC * kRows * K) * sizeof(cx<T>);
+  static constexpr size_t chunk = (size_t)kTC * kRows * rp;   // one radix-R chunk of the 64 conduction rows
+  static constexpr size_t vchunk = (size_t)TV * kRows * rp;   // and of the 8 TV valence rows
+  static constexpr size_t bytes = (2 * 2 * (chunk + vchunk) + (size_t)TV * kTC * kRows * K) * sizeof(cx<T>);
 };
 
-template <typename T, int R, int K>
+template <typename T, int R, int K, int TV = kTV>
 constexpr bool split_fits() {
-  return SplitLds<T, R, K>::bytes <= 160 * 1024;
+  return SplitLds<T, R, K, TV>::bytes <= 160 * 1024;
 }
 
-// float64 shapes whose split-line kernel holds its state in registers: there it runs
-// ahead of the 256-thread kernel, which needs one resident workgroup per CU
+// float64 shapes whose two-valence split-line kernel holds its state in registers: there
+// it runs ahead of the 256-thread kernel, which needs one resident workgroup per CU
 template <typename T, int R, int K>
 constexpr bool split_preferred() {
-  return std::is_same<T, double>::value && R == 8 && K <= 15 && split_fits<T, R, K>();
+  return std::is_same<T, double>::value && R == 8 && K <= 15 && split_fits<T, R, K, 2>();
 }
 
-template <typename T, int ND, int R, int K>
-__global__ __launch_bounds__(512, 1) void k_pair_planes_split(const cx<T>* __restrict__ psi_v,
+template <typename T, int ND, int R, int K, int TV>
+__global__ __launch_bounds__(128 * TV, 1) void k_pair_planes_split(const cx<T>* __restrict__ psi_v,
                                                               const cx<T>* __restrict__ psi_c, int nvs, int ncs,
                                                               const cx<T>* __restrict__ twk, cx<T>* __restrict__ q) {
   using V = cx<T>;
-  using L = SplitLds<T, R, K>;
+  using L = SplitLds<T, R, K, TV>;
+  constexpr int NT = 128 * TV;           // threads
   constexpr int S = ND / R;
   constexpr int SL = (S + 1) / 2;        // chunks of the first half
   constexpr int SH = S - SL;             // chunks of the second half
   constexpr int S2 = ND / kRows;
   constexpr int NSTEP = S2 * SL;
   constexpr int RCH = (K - 1) / 2;
-  constexpr int NPAIR = kTV * kTC;
+  constexpr int NPAIR = TV * kTC;
   constexpr int NITEM = NPAIR * K;
-  constexpr int IPL = (NITEM + 511) / 512;
+  constexpr int IPL = (NITEM + NT - 1) / NT;
   constexpr int CH = kTC * kRows * R;    // conduction elements of one chunk
-  constexpr int CV = kTV * kRows * R;    // valence elements of one chunk
-  constexpr int PER = 2 * (CH + CV) / 512;
+  constexpr int CV = TV * kRows * R;     // valence elements of one chunk
+  constexpr int PER = 2 * (CH + CV) / NT;
+  static_assert(PER * NT == 2 * (CH + CV), "chunk elements must divide evenly");
   constexpr size_t NPL = (size_t)ND * ND;
   __shared__ V s_c[2 * 2 * L::chunk];   // [buffer][half][row][rp]
   __shared__ V s_v[2 * 2 * L::vchunk];
   __shared__ V s_z[NPAIR * kRows * K];
 
   const int nbc = ncs / kTC;
-  const int nbv = nvs / kTV;
+  const int nbv = nvs / TV;
   const int pb = blockIdx.x % (nbc * nbv);
   const int x1 = blockIdx.x / (nbc * nbv);
   const int c0 = (pb % nbc) * kTC;
-  const int v0 = (pb / nbc) * kTV;
+  const int v0 = (pb / nbc) * TV;
 
   const int tid = threadIdx.x;
   // wave-uniform: the chunk index b and its twiddles then live in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wv = wave & 3;            // valence band of this wave
-  const int hf = wave >> 2;           // half of the x3 chunks
+  const int wv = wave % TV;           // valence band of this wave
+  const int hf = wave / TV;           // half of the x3 chunks
   const int lane = tid & 63;
   const int cl = lane / kRows;
   const int a2 = lane % kRows;
@@ -251,7 +255,7 @@ __global__ __launch_bounds__(512, 1) void k_pair_planes_split(const cx<T>* __res
     const int g2 = st / SL, t = st % SL;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int e = tid + 512 * i;
+      const int e = tid + NT * i;
       const int h = e / (CH + CV), e1 = e % (CH + CV);
       const int e2 = e1 < CH ? e1 : e1 - CH;
       const int row = e2 / R, a = e2 % R;
@@ -265,7 +269,7 @@ __global__ __launch_bounds__(512, 1) void k_pair_planes_split(const cx<T>* __res
   auto stash = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int e = tid + 512 * i;
+      const int e = tid + NT * i;
       const int h = e / (CH + CV), e1 = e % (CH + CV);
       if (e1 < CH)
         s_c[(buf * 2 + h) * L::chunk + (e1 / R) * L::rp + e1 % R] = pf[i];
@@ -323,7 +327,7 @@ __global__ __launch_bounds__(512, 1) void k_pair_planes_split(const cx<T>* __res
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < IPL; ++r) {
-      const int it = tid + 512 * r;
+      const int it = tid + NT * r;
       if (it < NITEM) {
         const int pair = it / K, j3 = it % K;
         V y[kRows];
@@ -343,7 +347,7 @@ __global__ __launch_bounds__(512, 1) void k_pair_planes_split(const cx<T>* __res
   const int p1 = (x1 % S) * R + x1 / S;
 #pragma unroll
   for (int r = 0; r < IPL; ++r) {
-    const int it = tid + 512 * r;
+    const int it = tid + NT * r;
     if (it < NITEM) {
       const int pair = it / K, j3 = it % K;
       const int pv = pair / kTC, pc = pair % kTC;
@@ -396,24 +400,32 @@ template <typename T, int ND, int R, int K>
 hipError_t run_planes(const Geom& g, const void* psi_v, const void* psi_c, int nvs, int ncs, void* q, int minb,
                       hipStream_t st) {
   const cx<T>* tw = std::is_same<T, double>::value ? (const cx<T>*)g.d_twk64 : (const cx<T>*)g.d_twk32;
-  const int nblk = ND * (nvs / kTV) * (ncs / kTC);
+  const cx<T>* pv = (const cx<T>*)psi_v;
+  const cx<T>* pc = (const cx<T>*)psi_c;
   // variant: 1 / 2 = 256-thread kernel with one / two resident workgroups per CU,
-  // 3 = 512-thread split-line kernel, 0 = split-line where preferred, else by register demand
+  // 3 / 4 = split-line kernel with 4 / 2 valence bands per workgroup,
+  // 0 = split-line where preferred, else by register demand
   int variant = minb;
-  if (variant == 0) variant = split_preferred<T, R, K>() ? 3 : planes_min_blocks<T, R, K>();
-  if constexpr (split_fits<T, R, K>()) {
+  if (variant == 0) variant = split_preferred<T, R, K>() ? 4 : planes_min_blocks<T, R, K>();
+  if constexpr (split_fits<T, R, K, 4>()) {
     if (variant == 3) {
-      k_pair_planes_split<T, ND, R, K><<<nblk, 512, 0, st>>>((const cx<T>*)psi_v, (const cx<T>*)psi_c, nvs, ncs, tw,
-                                                            (cx<T>*)q);
+      const int nblk = ND * (nvs / 4) * (ncs / kTC);
+      k_pair_planes_split<T, ND, R, K, 4><<<nblk, 512, 0, st>>>(pv, pc, nvs, ncs, tw, (cx<T>*)q);
       return hipGetLastError();
     }
   }
+  if constexpr (split_fits<T, R, K, 2>()) {
+    if (variant == 4) {
+      const int nblk = ND * (nvs / 2) * (ncs / kTC);
+      k_pair_planes_split<T, ND, R, K, 2><<<nblk, 256, 0, st>>>(pv, pc, nvs, ncs, tw, (cx<T>*)q);
+      return hipGetLastError();
+    }
+  }
+  const int nblk = ND * (nvs / kTV) * (ncs / kTC);
   if (variant == 2)
-    k_pair_planes<T, ND, R, K, 2><<<nblk, 256, 0, st>>>((const cx<T>*)psi_v, (const cx<T>*)psi_c, nvs, ncs, tw,
-                                                       (cx<T>*)q);
+    k_pair_planes<T, ND, R, K, 2><<<nblk, 256, 0, st>>>(pv, pc, nvs, ncs, tw, (cx<T>*)q);
   else
-    k_pair_planes<T, ND, R, K, 1><<<nblk, 256, 0, st>>>((const cx<T>*)psi_v, (const cx<T>*)psi_c, nvs, ncs, tw,
-                                                       (cx<T>*)q);
+    k_pair_planes<T, ND, R, K, 1><<<nblk, 256, 0, st>>>(pv, pc, nvs, ncs, tw, (cx<T>*)q);
   return hipGetLastError();
 }
 
