@@ -24,6 +24,9 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # packed-FP32 VALU ops stay off: float math is issued as scalar-per-lane ops
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs: otherwise the float64 tiles shuttle them
+    # between VGPRs and AGPRs around every MFMA
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-Wno-unused-command-line-argument",
 ]
 
