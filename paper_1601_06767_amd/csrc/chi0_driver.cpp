@@ -50,7 +50,6 @@ struct Layout {
   int nparts = 1, nomega = 1, mode = 0;
   std::vector<ProbPlan> pp;
   size_t off_psic = 0, off_scr = 0, off_q = 0, off_part = 0, off_dx = 0, off_dn = 0, off_counter = 0, total = 0;
-  size_t scr_a = 0;
   int max_cc = 0;
 };
 
@@ -113,7 +112,6 @@ Layout make_layout(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nom
     q.off_acc = backward ? 0 : take(q.acc_one * nomega * L.nparts);
     max_psic = std::max(max_psic, (size_t)q.cc * npts * L.csz);
     max_scr = std::max(max_scr, gw::band_scratch_bytes(g, kBandBatch, L.fp64));
-    L.scr_a = std::max(L.scr_a, (size_t)kBandBatch * g.W * g.W * g.nd * L.csz);
     max_q = std::max(max_q, (size_t)q.npair * g.nd * g.K * g.K * L.csz);
     max_part = std::max(max_part, gw::adjoint_partial_bytes(q.npair, g.ngp));
     max_np = std::max(max_np, (size_t)q.npair);
@@ -137,13 +135,12 @@ gw_status band_to_real(gw_ctx* ctx, const Layout& L, const Geom& g, const double
   const size_t npts = (size_t)g.nd * g.nd * g.nd;
   for (int s0 = 0; s0 < nslot; s0 += kBandBatch) {
     const int ns = std::min(kBandBatch, nslot - s0);
-    void* tA = ws + L.off_scr;
-    void* tB = ws + L.off_scr + L.scr_a;
+    void* tB = ws + L.off_scr;
     void* out = psi + (size_t)s0 * npts * L.csz;
     gw::StageScope sc(ctx, gw::kStageBand);
-    hipError_t e = L.fp64 ? gw::launch_band_to_real<double>(g, coef, nrows, band_idx, band0 + s0, nvalid, ns, tA, tB,
+    hipError_t e = L.fp64 ? gw::launch_band_to_real<double>(g, coef, nrows, band_idx, band0 + s0, nvalid, ns, tB,
                                                             out, ctx->stream)
-                          : gw::launch_band_to_real<float>(g, coef, nrows, band_idx, band0 + s0, nvalid, ns, tA, tB,
+                          : gw::launch_band_to_real<float>(g, coef, nrows, band_idx, band0 + s0, nvalid, ns, tB,
                                                            out, ctx->stream);
     GW_HIP(ctx, e);
   }

@@ -113,10 +113,10 @@ namespace gw {
 // ---------------------------------------------------------------- launches
 // Band -> real space: psi[slot][x1][p2][p3] for nslot bands.  Band of slot s:
 // idx = band0 + s; if idx >= nvalid it is clamped to nvalid - 1; then
-// band = band_idx ? band_idx[idx] : idx.
+// band = band_idx ? band_idx[idx] : idx.  tB: band_scratch_bytes of scratch.
 template <typename T>
 hipError_t launch_band_to_real(const Geom& g, const double2* coef, int nrows, const int32_t* band_idx, int band0, int nvalid,
-                               int nslot, void* tA, void* tB, void* psi, hipStream_t st);
+                               int nslot, void* tB, void* psi, hipStream_t st);
 size_t band_scratch_bytes(const Geom& g, int nslot, bool fp64);
 
 // Pair planes: Q[pair][p1][j2][j3] for pairs (v, c), v < nvs (multiple of 4), c < ncs (multiple of 8);
