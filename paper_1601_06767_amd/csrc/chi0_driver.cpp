@@ -48,6 +48,8 @@ struct Layout {
   bool fp64 = true;
   size_t csz = 16;
   int nparts = 1, nomega = 1, mode = 0;
+  // bf16x3 with one real weight set: the finish stage writes sqrt|w| M pre-split (mode 3)
+  bool presplit = false;
   std::vector<ProbPlan> pp;
   size_t off_psic = 0, off_scr = 0, off_q = 0, off_part = 0, off_dx = 0, off_dn = 0, off_counter = 0, total = 0;
   int max_cc = 0;
@@ -64,6 +66,8 @@ Layout make_layout(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nom
   L.nparts = complex_w ? 2 : 1;
   L.nomega = nomega;
   L.mode = mode_of(prec);
+  L.presplit = prec == GW_BF16X3 && nomega == 1 && !complex_w && !backward;
+  if (L.presplit) L.mode = 3;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
@@ -79,7 +83,7 @@ Layout make_layout(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nom
     int cc = std::max(8, (kPairTarget / q.nvs) / 8 * 8);
     q.cc = std::min<int>(cc, (int)round_up(probs[i].ncol, 8));
     q.npair = q.nvs * q.cc;
-    const int nt = g.ngp / gw::kTile;
+    const int nt = g.ngp / gw::contract_tile(L.mode);
     q.ntl = nt * (nt + 1) / 2;
     items += (long long)q.ntl * nomega * L.nparts;
     L.pp.push_back(q);
@@ -161,8 +165,12 @@ gw_status pair_block(gw_ctx* ctx, const Layout& L, const ProbPlan& q, char* ws) 
   GW_HIP(ctx, e);
   {
     gw::StageScope sc(ctx, gw::kStageFinish);
-    e = L.fp64 ? gw::launch_pair_finish<double>(g, ws + L.off_q, q.npair, ws + q.off_m, ctx->stream)
-               : gw::launch_pair_finish<float>(g, ws + L.off_q, q.npair, ws + q.off_m, ctx->stream);
+    if (L.presplit)
+      e = gw::launch_pair_finish_split(g, ws + L.off_q, q.npair, (const double*)(ws + q.off_w), ws + q.off_m,
+                                       ctx->stream);
+    else
+      e = L.fp64 ? gw::launch_pair_finish<double>(g, ws + L.off_q, q.npair, ws + q.off_m, ctx->stream)
+                 : gw::launch_pair_finish<float>(g, ws + L.off_q, q.npair, ws + q.off_m, ctx->stream);
   }
   GW_HIP(ctx, e);
   return GW_OK;
@@ -223,15 +231,16 @@ gw_status enqueue_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, in
       gw_status s = band_to_real(ctx, L, q.p->geom->g, (const double2*)q.p->coef_c, q.p->nband, q.p->col_band, c0,
                                  q.p->ncol, q.cc, ws, ws + L.off_psic);
       if (s != GW_OK) return s;
-      s = pair_block(ctx, L, q, ws);
-      if (s != GW_OK) return s;
       {
+        // before the pair block: the pre-split finish stage scales by the weights
         gw::StageScope sc(ctx, gw::kStageWeights);
         for (int iw = 0; iw < nomega; ++iw)
           GW_HIP(ctx, gw::launch_weights(q.p->e_v, 0, q.p->nv, q.nvs, q.p->e_col, q.p->n_col, c0, q.p->ncol, q.cc,
                                          omega[iw], delta, L.nparts,
                                          (double*)(ws + q.off_w) + (size_t)iw * L.nparts * q.npair, ctx->stream));
       }
+      s = pair_block(ctx, L, q, ws);
+      if (s != GW_OK) return s;
       active.push_back(i);
     }
     // largest dielectric spheres first
@@ -451,7 +460,9 @@ gw_status gw_pair_density(gw_ctx* ctx, const gw_chi0_problem* prob, int v0, int 
   gw_chi0_problem sub = *prob;
   sub.nv = nvs;
   sub.ncol = ncs;
-  const Layout L = make_layout(ctx, &sub, 1, 1, false, prec, false);
+  Layout L = make_layout(ctx, &sub, 1, 1, false, prec, false);
+  L.presplit = false;   // M itself is the output here
+  L.mode = mode_of(prec);
   const ProbPlan& q = L.pp[0];
   if (q.cc < (int)round_up(ncs, 8)) return gw::fail(ctx, GW_EINVAL, "pair block too large for one pass");
   if (L.total > ws_bytes) return gw::fail(ctx, GW_EINVAL, "workspace too small: need " + std::to_string(L.total));
@@ -507,6 +518,8 @@ gw_status gw_tune(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nome
       break;
     }
     ProbPlan q = L.pp[0];
+    GW_HIP(ctx, gw::launch_weights(p.e_v, 0, p.nv, q.nvs, p.e_col, p.n_col, 0, p.ncol, q.cc, 0.0, 0.0, 1,
+                                   (double*)(ws + q.off_w), ctx->stream));
     result = band_to_real(ctx, L, p.geom->g, (const double2*)p.coef_v, p.nv, nullptr, 0, p.nv, q.nvs, ws, ws + q.off_psiv);
     if (result == GW_OK)
       result = band_to_real(ctx, L, p.geom->g, (const double2*)p.coef_c, p.nband, p.col_band, 0, p.ncol, q.cc, ws,
@@ -535,10 +548,10 @@ gw_status gw_tune(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nome
       result = band_to_real(ctx, Lk, p.geom->g, (const double2*)p.coef_c, p.nband, p.col_band, 0, p.ncol, qk.cc, ws,
                             ws + Lk.off_psic);
       if (result != GW_OK) break;
-      result = pair_block(ctx, Lk, qk, ws);
-      if (result != GW_OK) break;
       GW_HIP(ctx, gw::launch_weights(p.e_v, 0, p.nv, qk.nvs, p.e_col, p.n_col, 0, p.ncol, qk.cc, 0.0, 0.0, 1,
                                      (double*)(ws + qk.off_w), ctx->stream));
+      result = pair_block(ctx, Lk, qk, ws);
+      if (result != GW_OK) break;
       gw::ContractBatch bt{};
       bt.nprob = 1;
       bt.item0[0] = 0;

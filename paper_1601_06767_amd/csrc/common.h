@@ -32,6 +32,14 @@ template <typename V> __device__ __forceinline__ void cmac(V& acc, V a, V b) {
   acc.y = fma(a.y, b.x, acc.y);
 }
 
+// bfloat16 as the upper half of a float, rounded to nearest even (finite inputs)
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_val(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
 // ---------------------------------------------------------------- unit roots
 // cos and sin of k pi / 16 for k = 0..4 (first octant), correctly rounded decimals.
 constexpr double kOctC[5] = {1.0, 0.98078528040323044913, 0.92387953251128675613, 0.83146961230254523708,

@@ -79,18 +79,28 @@ __device__ __forceinline__ void tile_coords(int t, int* ti, int* tj) {
   *tj = t - i * (i + 1) / 2;
 }
 
-// float64 partial sum of one item
-template <typename A4>
-__device__ __forceinline__ void store_tile(double2* out, int ngp, int g0, int h0, const A4 (&cre)[2][2],
-                                           const A4 (&cim)[2][2], int wr, int wc, int li, int lk, bool f64_rows) {
+// Tile geometry: TILE x TILE outputs per workgroup of NW waves on a WR x WC grid, each
+// wave owning (16 MI) x (16 NJ) outputs as MI x NJ MFMA blocks.
+template <int TILE> struct TileGeo;
+template <> struct TileGeo<64> {
+  static constexpr int NW = 4, WR = 2, WC = 2, MI = 2, NJ = 2;
+};
+template <> struct TileGeo<128> {
+  static constexpr int NW = 8, WR = 2, WC = 4, MI = 4, NJ = 2;
+};
+
+// float64 partial sum of one item; rows of block (i, j) start at r0 + 16 i, columns at c0 + 16 j
+template <int MI, int NJ, typename A4>
+__device__ __forceinline__ void store_tile(double2* out, int ngp, int r0, int c0, const A4 (&cre)[MI][NJ],
+                                           const A4 (&cim)[MI][NJ], int li, int lk, bool f64_rows) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = g0 + 32 * wr + 16 * i + (f64_rows ? lk + 4 * r : 4 * lk + r);
-        const int col = h0 + 32 * wc + 16 * j + li;
+        const int row = r0 + 16 * i + (f64_rows ? lk + 4 * r : 4 * lk + r);
+        const int col = c0 + 16 * j + li;
         double2* p = out + (size_t)row * ngp + col;
         double2 o = *p;
         o.x += (double)cre[i][j][r];
@@ -102,30 +112,33 @@ __device__ __forceinline__ void store_tile(double2* out, int ngp, int g0, int h0
 constexpr int KC = 16;   // pairs per LDS stage
 
 // ---------------------------------------------------------------- f64 / f32 MFMA tile
-template <typename T>
+template <typename T, int TILE>
 __device__ void tile_mfma(const cx<T>* __restrict__ m, const double* __restrict__ w, int nk, int ngp, int ksplit,
                           double2* __restrict__ acc, int t, int ks) {
   using V = cx<T>;
   using A4 = typename Mfma<T>::acc;
-  __shared__ V sA[KC][kTile];
-  __shared__ V sB[KC][kTile];
+  using G = TileGeo<TILE>;
+  constexpr int NT = 64 * G::NW;
+  constexpr int MI = G::MI, NJ = G::NJ;
+  __shared__ V sA[KC][TILE];
+  __shared__ V sB[KC][TILE];
   int ti, tj;
   tile_coords(t, &ti, &tj);
-  const int g0 = ti * kTile, h0 = tj * kTile;
+  const int g0 = ti * TILE, h0 = tj * TILE;
   const int per = (nk + ksplit - 1) / ksplit;
   const int k0 = ks * per;
   const int k1 = min(nk, k0 + per);
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave / G::WC, wc = wave % G::WC;
   const int li = lane & 15, lk = lane >> 4;
-  constexpr int NR = (KC * kTile) / 256;
+  constexpr int NR = (KC * TILE) / NT;
 
-  A4 cre[2][2], cim[2][2];
+  A4 cre[MI][NJ], cim[MI][NJ];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < NJ; ++j) {
       cre[i][j] = A4{0, 0, 0, 0};
       cim[i][j] = A4{0, 0, 0, 0};
     }
@@ -133,8 +146,8 @@ __device__ void tile_mfma(const cx<T>* __restrict__ m, const double* __restrict_
   auto fetch = [&](int kk) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      const int e = tid + 256 * r;
-      const int k = e / kTile, g = e % kTile;
+      const int e = tid + NT * r;
+      const int k = e / TILE, g = e % TILE;
       V a{T(0), T(0)}, b{T(0), T(0)};
       if (kk + k < k1) {
         const size_t row = (size_t)(kk + k) * ngp;
@@ -152,24 +165,24 @@ __device__ void tile_mfma(const cx<T>* __restrict__ m, const double* __restrict_
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      const int e = tid + 256 * r;
-      sA[e / kTile][e % kTile] = pa[r];
-      sB[e / kTile][e % kTile] = pb[r];
+      const int e = tid + NT * r;
+      sA[e / TILE][e % TILE] = pa[r];
+      sB[e / TILE][e % TILE] = pb[r];
     }
     __syncthreads();
     if (kk + KC < k1) fetch(kk + KC);
 #pragma unroll
     for (int s = 0; s < KC / 4; ++s) {
       const int k = 4 * s + lk;
-      V a[2], b[2];
+      V a[MI], b[NJ];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = sA[k][32 * wr + 16 * i + li];
+      for (int i = 0; i < MI; ++i) a[i] = sA[k][16 * MI * wr + 16 * i + li];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = sB[k][32 * wc + 16 * j + li];
+      for (int j = 0; j < NJ; ++j) b[j] = sB[k][16 * NJ * wc + 16 * j + li];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < NJ; ++j) {
           cre[i][j] = Mfma<T>::run(a[i].x, b[j].x, cre[i][j]);
           cre[i][j] = Mfma<T>::run(a[i].y, b[j].y, cre[i][j]);
           cim[i][j] = Mfma<T>::run(a[i].y, b[j].x, cim[i][j]);
@@ -177,7 +190,8 @@ __device__ void tile_mfma(const cx<T>* __restrict__ m, const double* __restrict_
         }
     }
   }
-  store_tile(acc + (size_t)ks * ngp * ngp, ngp, g0, h0, cre, cim, wr, wc, li, lk, std::is_same<T, double>::value);
+  store_tile<MI, NJ>(acc + (size_t)ks * ngp * ngp, ngp, g0 + 16 * MI * wr, h0 + 16 * NJ * wc, cre, cim, li, lk,
+                     std::is_same<T, double>::value);
 }
 
 // ---------------------------------------------------------------- split-bf16 x3 tile
@@ -191,59 +205,75 @@ __device__ void tile_mfma(const cx<T>* __restrict__ m, const double* __restrict_
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ unsigned short bf16_rne(float x) {
-  unsigned u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-__device__ __forceinline__ float bf16_val(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
 constexpr int BK = 16;          // pairs per MFMA step
 constexpr int BROW = 40;        // bf16 per LDS row (32 used, padded so 8 rows read together hit distinct banks)
 
-__device__ void tile_bf16x3(const float2* __restrict__ m, const double* __restrict__ w, int nk, int ngp, int ksplit,
+// PRE: m holds sqrt|w_k| M_k(G) already split, {hi.re, hi.im, lo.re, lo.im} per element,
+// so that sum_k w_k M M^H = sum_k sign(w_k) Mt Mt^H: the B operand only takes the sign.
+template <bool PRE, int TILE>
+__device__ void tile_bf16x3(const void* __restrict__ mv, const double* __restrict__ w, int nk, int ngp, int ksplit,
                             double2* __restrict__ acc, int t, int ks) {
+  using G = TileGeo<TILE>;
+  constexpr int MI = G::MI, NJ = G::NJ;
+  const float2* m = (const float2*)mv;
+  const ushort4* ms = (const ushort4*)mv;
   // [A|B][hi|lo][row][k']
-  __shared__ __align__(16) unsigned short s[2][2][kTile][BROW];
+  __shared__ __align__(16) unsigned short s[2][2][TILE][BROW];
   int ti, tj;
   tile_coords(t, &ti, &tj);
-  const int g0 = ti * kTile, h0 = tj * kTile;
+  const int g0 = ti * TILE, h0 = tj * TILE;
   const int per = (nk + ksplit - 1) / ksplit;
   const int k0 = ks * per;
   const int k1 = min(nk, k0 + per);
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave / G::WC, wc = wave % G::WC;
   const int li = lane & 15, lg = lane >> 4;
   // staging role: operand (A or B), row, half of the 16 pairs
-  const int op = tid >> 7;            // 0: A rows (G), 1: B rows (G')
-  const int srow = tid & 63;
-  const int shalf = (tid >> 6) & 1;   // pairs [8 shalf, 8 shalf + 8)
+  const int op = tid / (2 * TILE);           // 0: A rows (G), 1: B rows (G')
+  const int srow = tid % TILE;
+  const int shalf = (tid / TILE) % 2;        // pairs [8 shalf, 8 shalf + 8)
   const int gcol = (op ? h0 : g0) + srow;
 
-  f32x4 cre[2][2], cim[2][2];
+  f32x4 cre[MI][NJ], cim[MI][NJ];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < NJ; ++j) {
       cre[i][j] = f32x4{0, 0, 0, 0};
       cim[i][j] = f32x4{0, 0, 0, 0};
     }
   float2 pf[8];
+  ushort4 ps[8];
   auto fetch = [&](int kk) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int k = kk + 8 * shalf + e;
-      float2 x{0.f, 0.f};
-      if (k < k1) {
-        x = m[(size_t)k * ngp + gcol];
-        if (op) {
-          const float sw = (float)w[k];
-          x.x *= sw;
-          x.y *= sw;
+      if constexpr (PRE) {
+        ushort4 x{0, 0, 0, 0};
+        if (k < k1) {
+          x = ms[(size_t)k * ngp + gcol];
+          if (op && w[k] < 0.0) {
+            x.x ^= 0x8000;
+            x.y ^= 0x8000;
+            x.z ^= 0x8000;
+            x.w ^= 0x8000;
+          }
         }
+        ps[e] = x;
+      } else {
+        float2 x{0.f, 0.f};
+        if (k < k1) {
+          x = m[(size_t)k * ngp + gcol];
+          if (op) {
+            const float sw = (float)w[k];
+            x.x *= sw;
+            x.y *= sw;
+          }
+        }
+        pf[e] = x;
       }
-      pf[e] = x;
     }
   };
   if (k0 < k1) fetch(k0);
@@ -255,11 +285,18 @@ __device__ void tile_bf16x3(const float2* __restrict__ m, const double* __restri
       u16x8 rh, rl, ih, il;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const unsigned short a = bf16_rne(pf[e].x), b = bf16_rne(pf[e].y);
-        rh[e] = a;
-        ih[e] = b;
-        rl[e] = bf16_rne(pf[e].x - bf16_val(a));
-        il[e] = bf16_rne(pf[e].y - bf16_val(b));
+        if constexpr (PRE) {
+          rh[e] = ps[e].x;
+          ih[e] = ps[e].y;
+          rl[e] = ps[e].z;
+          il[e] = ps[e].w;
+        } else {
+          const unsigned short a = bf16_rne(pf[e].x), b = bf16_rne(pf[e].y);
+          rh[e] = a;
+          ih[e] = b;
+          rl[e] = bf16_rne(pf[e].x - bf16_val(a));
+          il[e] = bf16_rne(pf[e].y - bf16_val(b));
+        }
       }
       *(u16x8*)&s[op][0][srow][8 * shalf] = rh;
       *(u16x8*)&s[op][0][srow][16 + 8 * shalf] = ih;
@@ -268,10 +305,10 @@ __device__ void tile_bf16x3(const float2* __restrict__ m, const double* __restri
     }
     __syncthreads();
     if (kk + BK < k1) fetch(kk + BK);
-    bf16x8 xh[2], xl[2], yh[2], yl[2], bh[2], bl[2];
+    bf16x8 xh[MI], xl[MI], yh[MI], yl[MI], bh[NJ], bl[NJ];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int r = 32 * wr + 16 * i + li;
+    for (int i = 0; i < MI; ++i) {
+      const int r = 16 * MI * wr + 16 * i + li;
       xh[i] = *(const bf16x8*)&s[0][0][r][8 * lg];
       xl[i] = *(const bf16x8*)&s[0][1][r][8 * lg];
       u16x8 uh = *(const u16x8*)&s[0][0][r][8 * yg];
@@ -282,15 +319,15 @@ __device__ void tile_bf16x3(const float2* __restrict__ m, const double* __restri
       yl[i] = __builtin_bit_cast(bf16x8, ul);
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int r = 32 * wc + 16 * j + li;
+    for (int j = 0; j < NJ; ++j) {
+      const int r = 16 * NJ * wc + 16 * j + li;
       bh[j] = *(const bf16x8*)&s[1][0][r][8 * lg];
       bl[j] = *(const bf16x8*)&s[1][1][r][8 * lg];
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < NJ; ++j) {
         cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[i], bh[j], cre[i][j], 0, 0, 0);
         cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[i], bl[j], cre[i][j], 0, 0, 0);
         cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl[i], bh[j], cre[i][j], 0, 0, 0);
@@ -299,34 +336,36 @@ __device__ void tile_bf16x3(const float2* __restrict__ m, const double* __restri
         cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yl[i], bh[j], cim[i][j], 0, 0, 0);
       }
   }
-  store_tile(acc + (size_t)ks * ngp * ngp, ngp, g0, h0, cre, cim, wr, wc, li, lg, false);
+  store_tile<MI, NJ>(acc + (size_t)ks * ngp * ngp, ngp, g0 + 16 * MI * wr, h0 + 16 * NJ * wc, cre, cim, li, lg, false);
 }
 
 // ---------------------------------------------------------------- kernels
-template <int MODE>   // 0 f64, 1 f32, 2 bf16x3
+template <int MODE, int TILE>   // MODE 0 f64, 1 f32, 2 bf16x3, 3 bf16x3 on pre-split operands
 __device__ __forceinline__ void run_item(const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
                                          int t, int ks) {
   if constexpr (MODE == 0)
-    tile_mfma<double>((const double2*)m, w, nk, ngp, ksplit, acc, t, ks);
+    tile_mfma<double, TILE>((const double2*)m, w, nk, ngp, ksplit, acc, t, ks);
   else if constexpr (MODE == 1)
-    tile_mfma<float>((const float2*)m, w, nk, ngp, ksplit, acc, t, ks);
+    tile_mfma<float, TILE>((const float2*)m, w, nk, ngp, ksplit, acc, t, ks);
   else
-    tile_bf16x3((const float2*)m, w, nk, ngp, ksplit, acc, t, ks);
+    tile_bf16x3<MODE == 3, TILE>(m, w, nk, ngp, ksplit, acc, t, ks);
 }
 
 // Items are ordered pair-range major (all tiles of range 0, then range 1, ...): the
 // workgroups in flight read the same few thousand rows of M, which stay in cache.
-template <int MODE>
-__global__ __launch_bounds__(256) void k_contract(const void* __restrict__ m, const double* __restrict__ w, int nk,
-                                                  int ngp, int ksplit, int ntl, double2* __restrict__ acc) {
-  run_item<MODE>(m, w, nk, ngp, ksplit, acc, blockIdx.x % ntl, blockIdx.x / ntl);
+template <int MODE, int TILE>
+__global__ __launch_bounds__(64 * TileGeo<TILE>::NW) void k_contract(const void* __restrict__ m,
+                                                                    const double* __restrict__ w, int nk, int ngp,
+                                                                    int ksplit, int ntl, double2* __restrict__ acc) {
+  run_item<MODE, TILE>(m, w, nk, ngp, ksplit, acc, blockIdx.x % ntl, blockIdx.x / ntl);
 }
 
 // Persistent grid over all items of a batch; items of problem b occupy
 // [item0[b], item0[b+1]) and decode as (job, split, tile), job = w_index * nparts + part,
 // tile fastest (pair-range major, as above).
-template <int MODE>
-__global__ __launch_bounds__(256) void k_contract_batch(ContractBatch bt, int* __restrict__ counter) {
+template <int MODE, int TILE>
+__global__ __launch_bounds__(64 * TileGeo<TILE>::NW) void k_contract_batch(ContractBatch bt,
+                                                                           int* __restrict__ counter) {
   __shared__ int s_item;
   for (;;) {
     __syncthreads();
@@ -343,7 +382,7 @@ __global__ __launch_bounds__(256) void k_contract_batch(ContractBatch bt, int* _
     const int rem = (int)(local % per_job);
     const double* w = p.w + (size_t)job * p.nk;
     double2* acc = p.acc + (size_t)job * p.ksplit * p.ngp * p.ngp;
-    run_item<MODE>(p.m, w, p.nk, p.ngp, p.ksplit, acc, rem % p.ntl, rem / p.ntl);
+    run_item<MODE, TILE>(p.m, w, p.nk, p.ngp, p.ksplit, acc, rem % p.ntl, rem / p.ntl);
   }
 }
 
@@ -404,28 +443,54 @@ hipError_t launch_weights(const double* e_v, int v0, int nv_valid, int nvs, cons
   return hipGetLastError();
 }
 
-hipError_t launch_contract(int mode, const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
-                           hipStream_t st) {
-  const int nt = ngp / kTile;
+int contract_tile(int mode) { return mode == 0 ? 64 : 128; }
+
+namespace {
+template <int TILE>
+hipError_t contract_grid(int mode, const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
+                         hipStream_t st) {
+  constexpr int NT = 64 * TileGeo<TILE>::NW;
+  const int nt = ngp / TILE;
   const int ntl = nt * (nt + 1) / 2;
   const int nb = ntl * ksplit;
   if (mode == 0)
-    k_contract<0><<<nb, 256, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
+    k_contract<0, TILE><<<nb, NT, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
   else if (mode == 1)
-    k_contract<1><<<nb, 256, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
+    k_contract<1, TILE><<<nb, NT, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
+  else if (mode == 2)
+    k_contract<2, TILE><<<nb, NT, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
   else
-    k_contract<2><<<nb, 256, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
+    k_contract<3, TILE><<<nb, NT, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
   return hipGetLastError();
 }
 
-hipError_t launch_contract_batch(int mode, const ContractBatch& bt, int* counter, int grid, hipStream_t st) {
+template <int TILE>
+hipError_t contract_batch(int mode, const ContractBatch& bt, int* counter, int grid, hipStream_t st) {
+  constexpr int NT = 64 * TileGeo<TILE>::NW;
   if (mode == 0)
-    k_contract_batch<0><<<grid, 256, 0, st>>>(bt, counter);
+    k_contract_batch<0, TILE><<<grid, NT, 0, st>>>(bt, counter);
   else if (mode == 1)
-    k_contract_batch<1><<<grid, 256, 0, st>>>(bt, counter);
+    k_contract_batch<1, TILE><<<grid, NT, 0, st>>>(bt, counter);
+  else if (mode == 2)
+    k_contract_batch<2, TILE><<<grid, NT, 0, st>>>(bt, counter);
   else
-    k_contract_batch<2><<<grid, 256, 0, st>>>(bt, counter);
+    k_contract_batch<3, TILE><<<grid, NT, 0, st>>>(bt, counter);
   return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_contract(int mode, const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
+                           hipStream_t st) {
+  if (ngp % contract_tile(mode) != 0) return hipErrorInvalidValue;
+  return contract_tile(mode) == 64 ? contract_grid<64>(mode, m, w, nk, ngp, ksplit, acc, st)
+                                   : contract_grid<128>(mode, m, w, nk, ngp, ksplit, acc, st);
+}
+
+hipError_t launch_contract_batch(int mode, const ContractBatch& bt, int* counter, int grid, hipStream_t st) {
+  for (int b = 0; b < bt.nprob; ++b)
+    if (bt.p[b].ngp % contract_tile(mode) != 0) return hipErrorInvalidValue;
+  return contract_tile(mode) == 64 ? contract_batch<64>(mode, bt, counter, grid, st)
+                                   : contract_batch<128>(mode, bt, counter, grid, st);
 }
 
 hipError_t launch_finalize(const double2* accA, const double2* accB, int ksplit, int ng, int ngp, double2* chi,
