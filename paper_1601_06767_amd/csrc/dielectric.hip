@@ -2,9 +2,13 @@
 // stated before Eq. (chi0); Table 3's eps_inf = 1/[eps^-1]_00).
 //
 // Inversion: in-place Gauss-Jordan elimination with partial (row) pivoting, blocked by
-// panels of kNb columns.  Within a panel every pivot step updates only the panel
-// columns (all rows); the panel then holds the panel columns T[:, J] of the
-// accumulated elimination transform, and the remaining columns are brought up to
+// panels of kNb columns.  The panel columns (all rows) are copied to a buffer and each
+// pivot step is one launch that reads the panel from one buffer and writes the updated
+// panel (rows j and p interchanged, pivot row scaled, column j eliminated) to the other;
+// the same launch leaves one pivot candidate per workgroup for the next column, so that
+// the next step finds its pivot by reducing those candidates.  After the panel, its row
+// interchanges are applied to the other columns, the panel holds the columns T[:, J] of
+// the accumulated elimination transform, and the remaining columns are brought up to
 // date with one rank-kNb update A[:, rest] += (T[:, J] - I[:, J]) A_old[J, rest] on
 // float64 MFMA.  The column interchanges implied by the row pivots are undone at the
 // end.  A zero or non-finite pivot raises a device flag read by gw_eps_inv_status.
@@ -38,99 +42,158 @@ __global__ void k_flag_clear(int* flag) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *flag = 0;
 }
 
-// Pivot of column j (rows j..n-1, largest |.|, lowest index on ties), full-row swap,
-// and a copy of the pivot row's panel part.
-__global__ __launch_bounds__(1024) void k_pivot(double2* __restrict__ a, int n, int j, int j0, int nbp,
-                                                int* __restrict__ piv, double2* __restrict__ prow,
-                                                int* __restrict__ flag) {
-  __shared__ double s_v[1024];
-  __shared__ int s_i[1024];
+constexpr int kStepRows = 4;   // rows per workgroup of the panel kernels (one kNb-wide row per wave)
+
+// candidate (|x|^2, row) of one workgroup's rows i >= i0 in panel column col (row index
+// n and -1 when none qualifies); the larger value wins, the lower row on ties
+__device__ __forceinline__ void step_candidate(const double2* __restrict__ p, int n, int i0, int col, double* cm,
+                                               int* ci) {
+  __shared__ double s_m[kStepRows];
+  __shared__ int s_i[kStepRows];
+  const int r = threadIdx.x >> 6;
+  const int i = blockIdx.x * kStepRows + r;
+  if ((threadIdx.x & 63) == 0) {
+    double m = -1.0;
+    if (i < n && i >= i0) {
+      const double2 x = p[(size_t)i * kNb + col];
+      m = x.x * x.x + x.y * x.y;
+    }
+    s_m[r] = m;
+    s_i[r] = (i < n && i >= i0) ? i : n;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double best = -1.0;
+    int bi = n;
+    for (int k = 0; k < kStepRows; ++k)
+      if (s_i[k] < n && (s_m[k] > best || (s_m[k] == best && s_i[k] < bi))) {
+        best = s_m[k];
+        bi = s_i[k];
+      }
+    cm[blockIdx.x] = best;
+    ci[blockIdx.x] = bi;
+  }
+}
+
+// Panel columns [j0, j0 + nbp) of a into p (n x kNb, zero padded) and the pivot
+// candidates of its first column.
+__global__ __launch_bounds__(256) void k_panel_load(const double2* __restrict__ a, int n, int j0, int nbp,
+                                                    double2* __restrict__ p, double* __restrict__ cm,
+                                                    int* __restrict__ ci) {
+  const int i = blockIdx.x * kStepRows + (threadIdx.x >> 6);
+  const int c = threadIdx.x & 63;
+  if (i < n) p[(size_t)i * kNb + c] = c < nbp ? a[(size_t)i * n + j0 + c] : double2{0.0, 0.0};
+  __syncthreads();
+  step_candidate(p, n, j0, 0, cm, ci);
+}
+
+// One pivot step j = j0 + jc on the panel: pivot p from the candidates, then
+// row j <- row p / d, row p <- row j (old) eliminated, every other row eliminated,
+// column jc <- the corresponding column of the transform.  Reads pin, writes pout.
+__global__ __launch_bounds__(256) void k_gj_step(const double2* __restrict__ pin, double2* __restrict__ pout, int n,
+                                                 int j0, int jc, int nbp, const double* __restrict__ cm_in,
+                                                 const int* __restrict__ ci_in, int ncand, double* __restrict__ cm_out,
+                                                 int* __restrict__ ci_out, int* __restrict__ piv,
+                                                 int* __restrict__ flag) {
+  __shared__ double s_m[256];
+  __shared__ int s_i[256];
+  __shared__ double2 s_prow[kNb], s_rowj[kNb];
   const int t = threadIdx.x;
+  const int j = j0 + jc;
   double best = -1.0;
   int bi = n;
-  for (int i = j + t; i < n; i += blockDim.x) {
-    const double2 x = a[(size_t)i * n + j];
-    const double m = x.x * x.x + x.y * x.y;
-    if (m > best || (m == best && i < bi)) {
+  for (int k = t; k < ncand; k += blockDim.x) {
+    const double m = cm_in[k];
+    const int i = ci_in[k];
+    if (i < n && (m > best || (m == best && i < bi))) {
       best = m;
       bi = i;
     }
   }
-  s_v[t] = best;
+  s_m[t] = best;
   s_i[t] = bi;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (t < s) {
-      const double m = s_v[t + s];
-      const int i = s_i[t + s];
-      if (m > s_v[t] || (m == s_v[t] && i < s_i[t])) {
-        s_v[t] = m;
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (t < h) {
+      const double m = s_m[t + h];
+      const int i = s_i[t + h];
+      if (i < n && (m > s_m[t] || (m == s_m[t] && i < s_i[t]))) {
+        s_m[t] = m;
         s_i[t] = i;
       }
     }
     __syncthreads();
   }
-  const int p = s_i[0];
-  const double pm = s_v[0];
-  if (t == 0) {
+  const double pm = s_m[0];
+  const int p = s_i[0] < n ? s_i[0] : j;   // no finite candidate: keep row j, the flag reports it
+  if (blockIdx.x == 0 && t == 0) {
     piv[j] = p;
     if (!(pm > 0.0) || !isfinite(pm)) *flag = 1;
   }
-  if (p != j && p < n) {
-    for (int c = t; c < n; c += blockDim.x) {
+  if (t < kNb) {
+    s_prow[t] = pin[(size_t)p * kNb + t];
+    s_rowj[t] = pin[(size_t)j * kNb + t];
+  }
+  __syncthreads();
+  const double2 d = s_prow[jc];
+  const double den = d.x * d.x + d.y * d.y;
+  const double2 dinv = den > 0.0 ? double2{d.x / den, -d.y / den} : double2{0.0, 0.0};
+  const int i = blockIdx.x * kStepRows + (t >> 6);
+  const int c = t & 63;
+  if (i < n) {
+    double2 out;
+    if (i == j) {
+      out = c == jc ? dinv : cmul(s_prow[c], dinv);
+    } else {
+      const double2 x = i == p ? s_rowj[c] : pin[(size_t)i * kNb + c];
+      const double2 f = i == p ? s_rowj[jc] : pin[(size_t)i * kNb + jc];
+      const double2 fp = cmul(f, dinv);
+      if (c == jc) {
+        out = double2{-fp.x, -fp.y};
+      } else {
+        const double2 r = cmul(fp, s_prow[c]);
+        out = double2{x.x - r.x, x.y - r.y};
+      }
+    }
+    pout[(size_t)i * kNb + c] = out;
+  }
+  if (jc + 1 < nbp) {
+    __syncthreads();
+    step_candidate(pout, n, j + 1, jc + 1, cm_out, ci_out);
+  }
+}
+
+// The panel's row interchanges, in order, on the columns outside the panel.
+__global__ void k_row_swaps(double2* __restrict__ a, int n, int j0, int nbp, const int* __restrict__ piv) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n || (c >= j0 && c < j0 + nbp)) return;
+  for (int j = j0; j < j0 + nbp; ++j) {
+    const int p = piv[j];
+    if (p != j && p >= 0 && p < n) {
       const double2 x = a[(size_t)j * n + c];
       a[(size_t)j * n + c] = a[(size_t)p * n + c];
       a[(size_t)p * n + c] = x;
     }
   }
-  __syncthreads();
-  for (int c = t; c < nbp; c += blockDim.x) prow[c] = a[(size_t)j * n + j0 + c];
 }
 
-// Elimination of pivot j restricted to the panel columns [j0, j0 + nbp): four rows per
-// workgroup, one panel column per thread.
-__global__ __launch_bounds__(256) void k_eliminate(double2* __restrict__ a, int n, int j, int j0, int nbp,
-                                                   const double2* __restrict__ prow) {
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int c = threadIdx.x & 63;
-  const int jc = j - j0;
-  double2 f{0.0, 0.0};
-  if (i < n) f = a[(size_t)i * n + j];
-  __syncthreads();
-  if (i >= n || c >= nbp) return;
-  const double2 p = prow[jc];
-  const double den = p.x * p.x + p.y * p.y;
-  const double2 pinv{p.x / den, -p.y / den};
-  double2* dst = a + (size_t)i * n + j0 + c;
-  if (i == j) {
-    *dst = c == jc ? pinv : cmul(prow[c], pinv);
-  } else {
-    const double2 fp = cmul(f, pinv);
-    if (c == jc) {
-      *dst = double2{-fp.x, -fp.y};
-    } else {
-      const double2 r = cmul(fp, prow[c]);
-      const double2 x = *dst;
-      *dst = double2{x.x - r.x, x.y - r.y};
-    }
-  }
-}
-
-// Operands of the panel's rank-nbp update: bp = T[:, J] - I[:, J] (n x kNb, zero padded),
-// tmp = A[J, :] with the panel columns zeroed (kNb x n).
-__global__ void k_panel_operands(const double2* __restrict__ a, int n, int j0, int nbp, int nb,
-                                 double2* __restrict__ bp, double2* __restrict__ tmp) {
+// The finished panel T[:, J] back into a, and the operands of the rank-nbp update:
+// bp = T[:, J] - I[:, J] (in place in the panel buffer, n x kNb), tmp = A[J, :] with the
+// panel columns zeroed (kNb x n).
+__global__ void k_panel_operands(double2* __restrict__ a, int n, int j0, int nbp, double2* __restrict__ bp,
+                                 double2* __restrict__ tmp) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < (size_t)n * nb) {
-    const int i = (int)(e / nb), c = (int)(e % nb);
+  if (e < (size_t)n * kNb) {
+    const int i = (int)(e / kNb), c = (int)(e % kNb);
     double2 x{0.0, 0.0};
     if (c < nbp) {
-      x = a[(size_t)i * n + j0 + c];
+      x = bp[e];
+      a[(size_t)i * n + j0 + c] = x;
       if (i == j0 + c) x.x -= 1.0;
     }
     bp[e] = x;
   }
-  if (e < (size_t)nb * n) {
+  if (e < (size_t)kNb * n) {
     const int c = (int)(e / n), col = (int)(e % n);
     double2 x{0.0, 0.0};
     if (c < nbp && (col < j0 || col >= j0 + nbp)) x = a[(size_t)(j0 + c) * n + col];
@@ -260,38 +323,52 @@ hipError_t launch_zgemm(int m, int n, int k, double2 alpha, const double2* A, in
 
 size_t eps_inv_workspace(int n) {
   const size_t nb = kNb;
-  return (size_t)n * n * sizeof(double2) + 2 * (size_t)n * nb * sizeof(double2) + nb * sizeof(double2) +
-         2 * (size_t)n * sizeof(int) + 1024;
+  const size_t ncand = (n + kStepRows - 1) / kStepRows;
+  return (size_t)n * n * sizeof(double2) + 2 * (size_t)n * nb * sizeof(double2) + 2 * (size_t)n * sizeof(int) +
+         2 * ncand * (sizeof(double) + sizeof(int)) + 1024;
 }
 
 hipError_t launch_eps_inv(int n, const double* v, const double2* chi, double2* out, void* ws, int* flag,
                           hipStream_t st) {
+  const int ncand = (n + kStepRows - 1) / kStepRows;
   char* w = (char*)ws;
   double2* a = (double2*)w;   // working matrix
   w += (size_t)n * n * sizeof(double2);
-  double2* bp = (double2*)w;
+  double2* pb[2];              // panel buffers (n x kNb); afterwards the update operands
+  pb[0] = (double2*)w;
   w += (size_t)n * kNb * sizeof(double2);
-  double2* tmp = (double2*)w;
+  pb[1] = (double2*)w;
   w += (size_t)n * kNb * sizeof(double2);
-  double2* prow = (double2*)w;
-  w += kNb * sizeof(double2);
   int* piv = (int*)w;
   w += (size_t)n * sizeof(int);
   int* idx = (int*)w;
+  w += (size_t)n * sizeof(int);
+  double* cm[2];
+  int* ci[2];
+  cm[0] = (double*)w;
+  w += ncand * sizeof(double);
+  cm[1] = (double*)w;
+  w += ncand * sizeof(double);
+  ci[0] = (int*)w;
+  w += ncand * sizeof(int);
+  ci[1] = (int*)w;
   const size_t nn = (size_t)n * n;
   const unsigned gnn = (unsigned)((nn + 255) / 256);
   k_form_eps<<<gnn, 256, 0, st>>>(v, chi, n, a);
   for (int j0 = 0; j0 < n; j0 += kNb) {
     const int nbp = n - j0 < kNb ? n - j0 : kNb;
-    for (int j = j0; j < j0 + nbp; ++j) {
-      k_pivot<<<1, 1024, 0, st>>>(a, n, j, j0, nbp, piv, prow, flag);
-      k_eliminate<<<(n + 3) / 4, 256, 0, st>>>(a, n, j, j0, nbp, prow);
-    }
-    if (nbp == n) break;   // a single panel: no other columns to update
+    k_panel_load<<<ncand, 256, 0, st>>>(a, n, j0, nbp, pb[0], cm[0], ci[0]);
+    for (int jc = 0; jc < nbp; ++jc)
+      k_gj_step<<<ncand, 256, 0, st>>>(pb[jc & 1], pb[(jc + 1) & 1], n, j0, jc, nbp, cm[jc & 1], ci[jc & 1], ncand,
+                                       cm[(jc + 1) & 1], ci[(jc + 1) & 1], piv, flag);
+    double2* fin = pb[nbp & 1];
+    double2* other = pb[(nbp + 1) & 1];
+    if (nbp < n) k_row_swaps<<<(n + 255) / 256, 256, 0, st>>>(a, n, j0, nbp, piv);
     const size_t nops = (size_t)n * kNb;
-    k_panel_operands<<<(unsigned)((nops + 255) / 256), 256, 0, st>>>(a, n, j0, nbp, kNb, bp, tmp);
-    hipError_t e = launch_zgemm(n, n, kNb, double2{1.0, 0.0}, bp, kNb, false, tmp, n, false, double2{1.0, 0.0}, a,
-                                n, st);
+    k_panel_operands<<<(unsigned)((nops + 255) / 256), 256, 0, st>>>(a, n, j0, nbp, fin, other);
+    if (nbp == n) break;   // a single panel: no other columns to update
+    hipError_t e = launch_zgemm(n, n, kNb, double2{1.0, 0.0}, fin, kNb, false, other, n, false, double2{1.0, 0.0},
+                                a, n, st);
     if (e != hipSuccess) return e;
   }
   k_col_perm<<<1, 64, 0, st>>>(piv, n, idx);
