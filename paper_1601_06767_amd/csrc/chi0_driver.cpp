@@ -48,8 +48,6 @@ struct Layout {
   bool fp64 = true;
   size_t csz = 16;
   int nparts = 1, nomega = 1, mode = 0;
-  // bf16x3 with one real weight set: the finish stage writes sqrt|w| M pre-split (mode 3)
-  bool presplit = false;
   std::vector<ProbPlan> pp;
   size_t off_psic = 0, off_scr = 0, off_q = 0, off_part = 0, off_dx = 0, off_dn = 0, off_counter = 0, total = 0;
   int max_cc = 0;
@@ -66,8 +64,6 @@ Layout make_layout(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nom
   L.nparts = complex_w ? 2 : 1;
   L.nomega = nomega;
   L.mode = mode_of(prec);
-  L.presplit = prec == GW_BF16X3 && nomega == 1 && !complex_w && !backward;
-  if (L.presplit) L.mode = 3;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
@@ -165,12 +161,8 @@ gw_status pair_block(gw_ctx* ctx, const Layout& L, const ProbPlan& q, char* ws) 
   GW_HIP(ctx, e);
   {
     gw::StageScope sc(ctx, gw::kStageFinish);
-    if (L.presplit)
-      e = gw::launch_pair_finish_split(g, ws + L.off_q, q.npair, (const double*)(ws + q.off_w), ws + q.off_m,
-                                       ctx->stream);
-    else
-      e = L.fp64 ? gw::launch_pair_finish<double>(g, ws + L.off_q, q.npair, ws + q.off_m, ctx->stream)
-                 : gw::launch_pair_finish<float>(g, ws + L.off_q, q.npair, ws + q.off_m, ctx->stream);
+    e = L.fp64 ? gw::launch_pair_finish<double>(g, ws + L.off_q, q.npair, ws + q.off_m, ctx->stream)
+               : gw::launch_pair_finish<float>(g, ws + L.off_q, q.npair, ws + q.off_m, ctx->stream);
   }
   GW_HIP(ctx, e);
   return GW_OK;
@@ -232,7 +224,6 @@ gw_status enqueue_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, in
                                  q.p->ncol, q.cc, ws, ws + L.off_psic);
       if (s != GW_OK) return s;
       {
-        // before the pair block: the pre-split finish stage scales by the weights
         gw::StageScope sc(ctx, gw::kStageWeights);
         for (int iw = 0; iw < nomega; ++iw)
           GW_HIP(ctx, gw::launch_weights(q.p->e_v, 0, q.p->nv, q.nvs, q.p->e_col, q.p->n_col, c0, q.p->ncol, q.cc,
@@ -460,9 +451,7 @@ gw_status gw_pair_density(gw_ctx* ctx, const gw_chi0_problem* prob, int v0, int 
   gw_chi0_problem sub = *prob;
   sub.nv = nvs;
   sub.ncol = ncs;
-  Layout L = make_layout(ctx, &sub, 1, 1, false, prec, false);
-  L.presplit = false;   // M itself is the output here
-  L.mode = mode_of(prec);
+  const Layout L = make_layout(ctx, &sub, 1, 1, false, prec, false);
   const ProbPlan& q = L.pp[0];
   if (q.cc < (int)round_up(ncs, 8)) return gw::fail(ctx, GW_EINVAL, "pair block too large for one pass");
   if (L.total > ws_bytes) return gw::fail(ctx, GW_EINVAL, "workspace too small: need " + std::to_string(L.total));

@@ -209,15 +209,12 @@ typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 constexpr int BK = 16;          // pairs per MFMA step
 constexpr int BROW = 40;        // bf16 per LDS row (32 used, padded so 8 rows read together hit distinct banks)
 
-// PRE: m holds sqrt|w_k| M_k(G) already split, {hi.re, hi.im, lo.re, lo.im} per element,
-// so that sum_k w_k M M^H = sum_k sign(w_k) Mt Mt^H: the B operand only takes the sign.
-template <bool PRE, int TILE>
+template <int TILE>
 __device__ void tile_bf16x3(const void* __restrict__ mv, const double* __restrict__ w, int nk, int ngp, int ksplit,
                             double2* __restrict__ acc, int t, int ks) {
   using G = TileGeo<TILE>;
   constexpr int MI = G::MI, NJ = G::NJ;
   const float2* m = (const float2*)mv;
-  const ushort4* ms = (const ushort4*)mv;
   // [A|B][hi|lo][row][k']
   __shared__ __align__(16) unsigned short s[2][2][TILE][BROW];
   int ti, tj;
@@ -245,35 +242,20 @@ __device__ void tile_bf16x3(const void* __restrict__ mv, const double* __restric
       cim[i][j] = f32x4{0, 0, 0, 0};
     }
   float2 pf[8];
-  ushort4 ps[8];
   auto fetch = [&](int kk) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int k = kk + 8 * shalf + e;
-      if constexpr (PRE) {
-        ushort4 x{0, 0, 0, 0};
-        if (k < k1) {
-          x = ms[(size_t)k * ngp + gcol];
-          if (op && w[k] < 0.0) {
-            x.x ^= 0x8000;
-            x.y ^= 0x8000;
-            x.z ^= 0x8000;
-            x.w ^= 0x8000;
-          }
+      float2 x{0.f, 0.f};
+      if (k < k1) {
+        x = m[(size_t)k * ngp + gcol];
+        if (op) {
+          const float sw = (float)w[k];
+          x.x *= sw;
+          x.y *= sw;
         }
-        ps[e] = x;
-      } else {
-        float2 x{0.f, 0.f};
-        if (k < k1) {
-          x = m[(size_t)k * ngp + gcol];
-          if (op) {
-            const float sw = (float)w[k];
-            x.x *= sw;
-            x.y *= sw;
-          }
-        }
-        pf[e] = x;
       }
+      pf[e] = x;
     }
   };
   if (k0 < k1) fetch(k0);
@@ -285,18 +267,11 @@ __device__ void tile_bf16x3(const void* __restrict__ mv, const double* __restric
       u16x8 rh, rl, ih, il;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        if constexpr (PRE) {
-          rh[e] = ps[e].x;
-          ih[e] = ps[e].y;
-          rl[e] = ps[e].z;
-          il[e] = ps[e].w;
-        } else {
-          const unsigned short a = bf16_rne(pf[e].x), b = bf16_rne(pf[e].y);
-          rh[e] = a;
-          ih[e] = b;
-          rl[e] = bf16_rne(pf[e].x - bf16_val(a));
-          il[e] = bf16_rne(pf[e].y - bf16_val(b));
-        }
+        const unsigned short a = bf16_rne(pf[e].x), b = bf16_rne(pf[e].y);
+        rh[e] = a;
+        ih[e] = b;
+        rl[e] = bf16_rne(pf[e].x - bf16_val(a));
+        il[e] = bf16_rne(pf[e].y - bf16_val(b));
       }
       *(u16x8*)&s[op][0][srow][8 * shalf] = rh;
       *(u16x8*)&s[op][0][srow][16 + 8 * shalf] = ih;
@@ -340,7 +315,7 @@ __device__ void tile_bf16x3(const void* __restrict__ mv, const double* __restric
 }
 
 // ---------------------------------------------------------------- kernels
-template <int MODE, int TILE>   // MODE 0 f64, 1 f32, 2 bf16x3, 3 bf16x3 on pre-split operands
+template <int MODE, int TILE>   // MODE 0 f64, 1 f32, 2 bf16x3
 __device__ __forceinline__ void run_item(const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
                                          int t, int ks) {
   if constexpr (MODE == 0)
@@ -348,7 +323,7 @@ __device__ __forceinline__ void run_item(const void* m, const double* w, int nk,
   else if constexpr (MODE == 1)
     tile_mfma<float, TILE>((const float2*)m, w, nk, ngp, ksplit, acc, t, ks);
   else
-    tile_bf16x3<MODE == 3, TILE>(m, w, nk, ngp, ksplit, acc, t, ks);
+    tile_bf16x3<TILE>(m, w, nk, ngp, ksplit, acc, t, ks);
 }
 
 // Items are ordered pair-range major (all tiles of range 0, then range 1, ...): the
@@ -457,10 +432,8 @@ hipError_t contract_grid(int mode, const void* m, const double* w, int nk, int n
     k_contract<0, TILE><<<nb, NT, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
   else if (mode == 1)
     k_contract<1, TILE><<<nb, NT, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
-  else if (mode == 2)
-    k_contract<2, TILE><<<nb, NT, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
   else
-    k_contract<3, TILE><<<nb, NT, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
+    k_contract<2, TILE><<<nb, NT, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
   return hipGetLastError();
 }
 
@@ -471,10 +444,8 @@ hipError_t contract_batch(int mode, const ContractBatch& bt, int* counter, int g
     k_contract_batch<0, TILE><<<grid, NT, 0, st>>>(bt, counter);
   else if (mode == 1)
     k_contract_batch<1, TILE><<<grid, NT, 0, st>>>(bt, counter);
-  else if (mode == 2)
-    k_contract_batch<2, TILE><<<grid, NT, 0, st>>>(bt, counter);
   else
-    k_contract_batch<3, TILE><<<grid, NT, 0, st>>>(bt, counter);
+    k_contract_batch<2, TILE><<<grid, NT, 0, st>>>(bt, counter);
   return hipGetLastError();
 }
 }  // namespace

@@ -130,10 +130,6 @@ hipError_t launch_pair_planes(const Geom& g, const void* psi_v, const void* psi_
 // Pair finish: x1 transforms, 1/N, gather to the chi sphere: m[pair][ngp] (zero padded).
 template <typename T>
 hipError_t launch_pair_finish(const Geom& g, const void* q, int npair, void* m, hipStream_t st);
-// The float32 finish scaled by sqrt|w[pair]| and split for the bf16x3 contraction:
-// m[pair][ngp] of {hi.re, hi.im, lo.re, lo.im} bf16 (zero padded).
-hipError_t launch_pair_finish_split(const Geom& g, const void* q, int npair, const double* w, void* m,
-                                    hipStream_t st);
 bool pair_supported(int nd, int K);
 
 // Weights of Eq. (chi0) per pair p = v * ncs + c (zero for padded pairs):
@@ -143,8 +139,7 @@ hipError_t launch_weights(const double* e_v, int v0, int nv_valid, int nvs, cons
                           int c0, int nc_valid, int ncs, double omega, double delta, int nparts, double* w,
                           hipStream_t st);
 
-// acc[ks][G][G'] (lower tiles) += sum_k m[k][G] w[k] conj(m[k][G']);  mode 0 f64, 1 f32, 2 bf16x3,
-// 3 bf16x3 on the operands of launch_pair_finish_split (w only gives the sign)
+// acc[ks][G][G'] (lower tiles) += sum_k m[k][G] w[k] conj(m[k][G']);  mode 0 f64, 1 f32, 2 bf16x3
 hipError_t launch_contract(int mode, const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
                            hipStream_t st);
 // Batched contraction: per problem, nomega * nparts jobs (job j uses w + j nk and

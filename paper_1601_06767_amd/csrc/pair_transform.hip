@@ -13,9 +13,7 @@
 //     x2 group (x2 = b2 + S2 a2), accumulated over the S2 groups in registers;
 //   output Q[pair][p1][n2][n3] for this plane (p1 = plane stored permuted).
 // k_pair_finish (one pair per workgroup): pruned x1 transform of Q, the 1/N, and the
-//   gather of the K^3 box onto the sphere order: M[pair][G] (zero padded to ngp);
-//   k_pair_finish_split writes sqrt|w_pair| M split into bf16 hi/lo for the bf16x3
-//   contraction.
+//   gather of the K^3 box onto the sphere order: M[pair][G] (zero padded to ngp).
 #include <type_traits>
 
 #include "common.h"
@@ -402,56 +400,6 @@ __global__ __launch_bounds__(256) void k_pair_finish(const cx<T>* __restrict__ q
   for (int i = ng + threadIdx.x; i < ngp; i += blockDim.x) dst[i] = V{T(0), T(0)};
 }
 
-// The same transform in float32, the result scaled by sqrt|w_pair| and stored split for
-// the bf16x3 contraction: {hi.re, hi.im, lo.re, lo.im}, hi = bf16(x), lo = bf16(x - hi).
-template <int ND, int R, int K>
-__global__ __launch_bounds__(256) void k_pair_finish_split(const float2* __restrict__ q,
-                                                           const int32_t* __restrict__ chi_map, int ng, int ngp,
-                                                           float scale, const double* __restrict__ w,
-                                                           const float2* __restrict__ twk, ushort4* __restrict__ m) {
-  using T = float;
-  using V = cx<T>;
-  constexpr int S = ND / R;
-  constexpr int RCH = (K - 1) / 2;
-  const size_t pair = blockIdx.x;
-  const V* src = q + pair * ND * (K * K);
-  ushort4* dst = m + pair * ngp;
-  const float sp = scale * (float)sqrt(fabs(w[pair]));
-  for (int l = threadIdx.x; l < K * K; l += blockDim.x) {
-    V acc[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) acc[j] = V{T(0), T(0)};
-    // the R planes of chunk b + 1 are loaded while chunk b is transformed; the loop stays
-    // rolled (unrolled, the loads of all S chunks would be hoisted and spill)
-    V nx[R];
-#pragma unroll
-    for (int a = 0; a < R; ++a) nx[a] = src[(size_t)a * (K * K) + l];
-#pragma unroll 1
-    for (int b = 0; b < S; ++b) {
-      V x[R];
-#pragma unroll
-      for (int a = 0; a < R; ++a) x[a] = nx[a];
-      if (b + 1 < S) {
-#pragma unroll
-        for (int a = 0; a < R; ++a) nx[a] = src[(size_t)((b + 1) * R + a) * (K * K) + l];
-      }
-      dft<R>(x);
-#pragma unroll
-      for (int j = 0; j < K; ++j) cmac(acc[j], twk[b * K + j], x[((j - RCH) % R + R) % R]);
-    }
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      const int ig = chi_map[j * K * K + l];
-      if (ig >= 0) {
-        const float xr = acc[j].x * sp, xi = acc[j].y * sp;
-        const unsigned short hr = bf16_rne(xr), hi = bf16_rne(xi);
-        dst[ig] = ushort4{hr, hi, bf16_rne(xr - bf16_val(hr)), bf16_rne(xi - bf16_val(hi))};
-      }
-    }
-  }
-  for (int i = ng + threadIdx.x; i < ngp; i += blockDim.x) dst[i] = ushort4{0, 0, 0, 0};
-}
-
 template <typename T, int ND, int R, int K>
 hipError_t run_planes(const Geom& g, const void* psi_v, const void* psi_c, int nvs, int ncs, void* q, int minb,
                       hipStream_t st) {
@@ -482,14 +430,6 @@ hipError_t run_planes(const Geom& g, const void* psi_v, const void* psi_c, int n
     k_pair_planes<T, ND, R, K, 2><<<nblk, 256, 0, st>>>(pv, pc, nvs, ncs, tw, (cx<T>*)q);
   else
     k_pair_planes<T, ND, R, K, 1><<<nblk, 256, 0, st>>>(pv, pc, nvs, ncs, tw, (cx<T>*)q);
-  return hipGetLastError();
-}
-
-template <int ND, int R, int K>
-hipError_t run_finish_split(const Geom& g, const void* q, int npair, const double* w, void* m, hipStream_t st) {
-  const float scale = (float)(1.0 / ((double)ND * ND * ND));
-  k_pair_finish_split<ND, R, K><<<npair, 256, 0, st>>>((const float2*)q, g.d_chi_map, g.ng, g.ngp, scale, w,
-                                                       (const float2*)g.d_twk32, (ushort4*)m);
   return hipGetLastError();
 }
 
@@ -545,15 +485,6 @@ template <typename T>
 hipError_t launch_pair_finish(const Geom& g, const void* q, int npair, void* m, hipStream_t st) {
 #define X(nd_, r_, k_) \
   if (g.nd == nd_ && g.K == k_) return run_finish<T, nd_, r_, k_>(g, q, npair, m, st);
-  GW_PAIR_CASES(X)
-#undef X
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_pair_finish_split(const Geom& g, const void* q, int npair, const double* w, void* m,
-                                    hipStream_t st) {
-#define X(nd_, r_, k_) \
-  if (g.nd == nd_ && g.K == k_) return run_finish_split<nd_, r_, k_>(g, q, npair, w, m, st);
   GW_PAIR_CASES(X)
 #undef X
   return hipErrorInvalidValue;
