@@ -89,6 +89,9 @@ def main():
     ap.add_argument("--tune", action="store_true", help="run the launch-shape tuner before timing each mode")
     ap.add_argument("--inputs-cache", default=None,
                     help="npz file for the generated inputs: loaded if present, written otherwise")
+    ap.add_argument("--workload", default="static", choices=["static", "batched"],
+                    help="static: the 72^3 / 128x4000 / NG 2000 build (default); batched: 8 q-points x 16 "
+                         "frequencies, 128x6000 bands, NG 800..3000, one persistent launch per chunk")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
     args = ap.parse_args()
@@ -103,6 +106,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.workload == "batched":
+        run_batched(args, torch, synth, p, dev)
+        return
     cfg = synth.config(1)
     nd = cfg.nd
     gw = synth.wf_sphere(nd)
@@ -236,6 +242,96 @@ def main():
                        "pairs": npair, "q": list(cfg.qs[0]), "omega": 0.0},
             "band_pairs_per_s": hr["band_pairs_per_s"], "modes": results, "roofline": roofline,
             "cpu_baseline": cpu}
+    print(json.dumps(line))
+
+
+def run_batched(args, torch, synth, p, dev):
+    """The batched frequency-dependent workload: every q-point is one problem of the same
+    build call (uneven dielectric spheres), all frequencies with broadening in each call."""
+    cfg = synth.config(3)
+    nd = cfg.nd
+    gw = synth.wf_sphere(nd)
+    om = synth.omegas(cfg)
+    delta = synth.delta(cfg)
+    t0 = time.time()
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    ctx = p.gw_ctx_create(0)
+    probs, ngs, keep = [], [], []
+    cc = ec = None
+    for iq in range(len(cfg.qs)):
+        gc = synth.chi_sphere(cfg.ng[iq], cfg.qs[iq], cfg.cell)
+        b = synth.make_bands(cfg, gvec_wf=gw, iq=iq, device="cuda")
+        if cc is None:   # the conduction set (at k) is the same for every q-point
+            cc, ec = t(b.coef_c), t(b.e_c)
+        geom = p.gw_geom_create(ctx, (nd,) * 3, gw, gc)
+        cv, ev = t(b.coef_v), t(b.e_v)
+        keep += [cv, ev]
+        probs.append(p.make_problem(geom, cv, ev, cc, ec))
+        ngs.append(len(gc))
+        del b
+    log(f"batched inputs: {len(probs)} q-points, NG {ngs}, {len(om)} frequencies, ready in {time.time() - t0:.1f}s")
+    modes = [m for m in args.modes.split(",") if m]
+    npair = cfg.nv * cfg.nc
+    k = [2 * int(np.abs(synth.chi_sphere(n, q, cfg.cell)).max()) + 1 for n, q in zip(cfg.ng, cfg.qs)]
+    work = {"planes": 0.0, "finish": 0.0, "contract": 0.0, "band": 0.0}
+    for n, kk in zip(ngs, k):
+        f = flops_model(nd, kk, n, npair, cfg.nv + cfg.nc, with_inverse=False)
+        work["planes"] += f["planes"]
+        work["finish"] += f["finish"]
+        work["band"] += f["band"]
+        work["contract"] += 2.0 * f["contract"] * len(om)     # 8 NG^2 per pair per frequency
+    total = sum(work.values())
+    results = {}
+    for m in modes:
+        wsb = p.gw_chi0_workspace_size(ctx, probs, len(om), p.PRECISIONS[m])
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        out = torch.empty(sum(len(om) * n * n for n in ngs), dtype=torch.complex128, device=dev)
+        log(f"{m}: workspace {wsb / 2**30:.1f} GiB")
+
+        def run():
+            p.gw_chi0_build(ctx, probs, ngs, om, delta, p.PRECISIONS[m], workspace=ws, out=out)
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        p.gw_ctx_stage_times(ctx, reset=True)
+        p.gw_ctx_set_timing(ctx, True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(torch.cuda.current_stream())
+        for i in range(args.steps):
+            run()
+            log(f"{m}: step {i + 1}/{args.steps} enqueued")
+        e1.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        p.gw_ctx_set_timing(ctx, False)
+        stages = p.gw_ctx_stage_times(ctx, reset=True)
+        ms = e0.elapsed_time(e1) / args.steps
+        st = {s_: v[0] / args.steps for s_, v in stages.items() if v[1]}
+        nl = {s_: v[1] / args.steps for s_, v in stages.items() if v[1]}
+        results[m] = {"ms_per_step": ms, "tflops": total / (ms * 1e-3) / 1e12,
+                      "band_pairs_per_s": npair * len(ngs) / (ms * 1e-3), "stages_ms_per_step": st,
+                      "stage_launches_per_step": nl,
+                      "contract_tflops": work["contract"] / (st.get("contract", ms) * 1e-3) / 1e12}
+        log(f"{m}: {ms:.1f} ms/step, {results[m]['tflops']:.2f} TFLOP/s, stages {st}")
+        del ws, out
+    head = modes[0]
+    hr = results[head]
+    st = hr["stages_ms_per_step"]
+    peak = PEAK["fp64_mfma"] if head == "fp64" else PEAK["fp32_mfma"] if head == "fp32" else PEAK["bf16_mfma"]
+    avg = st["contract"] / hr["stage_launches_per_step"]["contract"]
+    per = work["contract"] / hr["stage_launches_per_step"]["contract"]
+    roofline = {"bound": "mfma", "kernel": "contract", "achieved": per / (avg * 1e-3) / 1e12, "peak": peak,
+                "unit": "TFLOP/s", "frac": per / (avg * 1e-3) / 1e12 / peak, "traffic": None, "avg_launch_ms": avg,
+                "algorithmic_work_per_launch": per}
+    line = {"metric": METRIC, "value": hr["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": hr["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[head],
+            "data": "synthetic",
+            "config": {"workload": cfg.name, "grid": nd, "npw": len(gw), "nv": cfg.nv, "ncol": cfg.nc, "ng": ngs,
+                       "pairs_per_q": npair, "q": [list(q) for q in cfg.qs], "omegas": len(om),
+                       "delta_ev": cfg.delta_ev},
+            "band_pairs_per_s": hr["band_pairs_per_s"], "modes": results, "roofline": roofline,
+            "cpu_baseline": None}
     print(json.dumps(line))
 
 

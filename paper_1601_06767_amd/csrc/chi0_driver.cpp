@@ -84,15 +84,22 @@ Layout make_layout(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nom
     items += (long long)q.ntl * nomega * L.nparts;
     L.pp.push_back(q);
   }
-  // Split the pair ranges so that (a) the batch has about 8 items per CU and (b) the rows
-  // of M that the items in flight share (one pair range) stay near 32 MB, so they are
-  // served from cache instead of HBM; a tuned choice overrides.
+  // Split the pair ranges so that (a) the batch has about 8 items per CU and (b) for a
+  // single job, the rows of M that the items in flight share (one pair range) stay near
+  // 32 MB, so they are served from cache instead of HBM (with several jobs the items of one
+  // range already share their rows).  Every split costs a float64 partial NG^2 per job, so
+  // the splits are capped to keep the partials within 16 GB (or their unsplit size).  A
+  // tuned choice overrides.
   const long long want = 8LL * 256;
   const int ks_par = items >= want ? 1 : (int)std::min<long long>(32, (want + items - 1) / items);
+  const int njobs = nomega * L.nparts;
+  size_t acc1 = 0;   // partials of all problems with one split each
+  for (const auto& q : L.pp) acc1 += (size_t)q.p->geom->g.ngp * q.p->geom->g.ngp * sizeof(double2) * njobs;
+  const int ks_mem = (int)std::max<size_t>(1, (size_t(16) << 30) / std::max<size_t>(acc1, 1));
   for (auto& q : L.pp) {
     const size_t mbytes = (size_t)q.npair * q.p->geom->g.ngp * L.csz;
-    const int ks_cache = (int)std::min<size_t>(32, (mbytes + (32u << 20) - 1) / (32u << 20));
-    int k = std::max(ks_par, ks_cache);
+    const int ks_cache = njobs > 1 ? 1 : (int)std::min<size_t>(32, (mbytes + (32u << 20) - 1) / (32u << 20));
+    int k = std::min(std::max(ks_par, ks_cache), ks_mem);
     auto it = ctx->tune.find(shape_key(q.p->geom->g, q.p->nv, q.p->ncol, prec));
     if (it != ctx->tune.end()) {
       q.minb = it->second.first;
