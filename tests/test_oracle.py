@@ -340,3 +340,40 @@ def test_grad_eps_inv_general_matches_finite_differences():
             m[i, j] -= unit * h
             fd = (loss(p) - loss(m)) / (2 * h)
             assert abs(fd - part(g[i, j])) < 1e-7
+
+
+@pytest.mark.parametrize("om,d", [([0.0], 0.0), ([0.05, 0.4], 0.01)])
+def test_coefficient_gradients_match_finite_differences(om, d):
+    # both terms of the matrix element (the valence set enters conjugated, the conduction
+    # set plainly), a grouped column layout with two columns on one coefficient row
+    t = tiny(nv=2, nc=4)
+    r = np.random.default_rng(11)
+    ng = len(t["gc"])
+    bmat = r.standard_normal((len(om), ng, ng)) + 1j * r.standard_normal((len(om), ng, ng))
+    col = np.array([0, 1, 3, 1])
+    e_col = t["e_c"][col] + np.array([0.0, 0.0, 0.0, 0.07])
+    n_col = np.array([1.0, 1.0, 2.0, 0.5])
+
+    def loss(cv, cc):
+        chi = oracle.chi0_bands(cv, t["e_v"], cc, e_col, t["gw"], t["gc"], t["nd"], omegas=om, delta=d,
+                                n_col=n_col, col_band=col)
+        return float(np.real(np.sum(np.conj(bmat) * chi)))
+
+    gv, gcc = og.grad_chi0_coefficients(t["cv"], t["e_v"], t["cc"], e_col, t["gw"], t["gc"], t["nd"], bmat,
+                                        omegas=om, delta=d, n_col=n_col, col_band=col)
+    assert gv.shape == t["cv"].shape and gcc.shape == t["cc"].shape
+    assert np.all(gcc[2] == 0)          # row 2 feeds no column
+    h = 1e-6
+    for which, idx in (("v", (0, 3)), ("v", (1, 20)), ("c", (1, 0)), ("c", (3, 11)), ("c", (0, 7))):
+        for unit, part in ((1.0, np.real), (1j, np.imag)):
+            cv_p, cv_m, cc_p, cc_m = t["cv"].copy(), t["cv"].copy(), t["cc"].copy(), t["cc"].copy()
+            if which == "v":
+                cv_p[idx] += unit * h
+                cv_m[idx] -= unit * h
+                want = part(gv[idx])
+            else:
+                cc_p[idx] += unit * h
+                cc_m[idx] -= unit * h
+                want = part(gcc[idx])
+            fd = (loss(cv_p, cc_p) - loss(cv_m, cc_m)) / (2 * h)
+            assert abs(fd - want) <= 1e-6 * max(1.0, abs(want)), (which, idx, fd, want)
