@@ -129,7 +129,10 @@ typedef struct {
   const double* n_col;
 } gw_chi0_problem;
 
-/* Workspace bytes gw_chi0_build / gw_chi0_backward need for these problems. */
+/* Workspace bytes gw_chi0_build / gw_chi0_backward need for these problems: the largest
+ * of the forward and backward layouts, static or dynamic, for any number of frequencies
+ * up to nomega.  In GW_FP64 the backward layout includes the coefficient-gradient buffers
+ * (two pair-density blocks and the real-space gradients of one conduction chunk). */
 gw_status gw_chi0_workspace_size(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega,
                                  gw_precision prec, size_t* bytes);
 
@@ -158,11 +161,19 @@ gw_status gw_chi0_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, in
  *               column is the derivative with respect to its energy E_i (nullable).
  *   grad_n_col  device, same length: dL/dn_col, the derivative with respect to the
  *               weight g(E_i) dE_i of Eq. (energyintegration) (nullable).
- *   grad_coef_v, grad_coef_c   must be NULL (coefficient gradients: GW_EUNSUPPORTED).
+ *   grad_coef_v  device complex128, sum over problems of nv x npw: dL/dRe + i dL/dIm of
+ *               coef_v (nullable = skip).  GW_FP64 only (GW_EUNSUPPORTED otherwise).
+ *   grad_coef_c  device complex128, sum over problems of nband x npw, per coefficient row
+ *               of coef_c: the columns that use one row (col_band) add up; rows no column
+ *               uses get zero (nullable = skip; GW_FP64 only).
  * With s_p = m_p^H chibar m_p (pair densities recomputed, never stored for all pairs):
  * dL/dE_v = sum_c Re(conj(s) dw/dx), dL/dE_c = -sum_v Re(conj(s) dw/dx),
  * dL/dn_c = sum_v Re(conj(s) dw/dn), summed over frequencies, x = E_v - E_c and w the
- * energy factor of Eq. (chi0).  Reductions are float64 in a fixed order. */
+ * energy factor of Eq. (chi0).  The coefficient gradients go back through the matrix
+ * element: mbar_p = sum_w [conj(w_p) chibar m_p + w_p chibar^H m_p], h_p = F^H mbar_p on
+ * the grid (F the transform of Eq. (chi0) including 1/N), dL/du_c = sum_v h_vc u_v,
+ * dL/du_v = sum_c conj(h_vc) u_c, then the transpose of the band transform.  Every
+ * reduction is float64 in a fixed order. */
 gw_status gw_chi0_backward(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, const double* omega,
                            double delta, gw_precision prec, void* workspace, size_t ws_bytes, const void* grad_chi0,
                            double* grad_e_v, double* grad_e_col, double* grad_n_col, void* grad_coef_v,

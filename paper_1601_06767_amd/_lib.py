@@ -159,7 +159,15 @@ def gw_geom_create(ctx, n_fft: Sequence[int], gvec_wf: np.ndarray, gvec_chi: np.
     out = vp()
     _check(lib.gw_geom_create(ctx, nf, gw_.shape[0], gw_.ctypes.data_as(i32p), gc.shape[0], gc.ctypes.data_as(i32p),
                               C.byref(out)), ctx)
+    _npw[out.value] = int(gw_.shape[0])
     return out
+
+
+_npw = {}   # wavefunction-sphere size per geometry handle
+
+
+def _geom_npw(geom) -> int:
+    return _npw[geom if isinstance(geom, int) else geom.value]
 
 
 def gw_geom_destroy(geom) -> None:
@@ -211,9 +219,12 @@ def gw_chi0_build(ctx, problems, ngs: Sequence[int], omegas: Sequence[float], de
 
 
 def gw_chi0_backward(ctx, problems, omegas: Sequence[float], delta: float, prec: int, grad_chi0, workspace=None,
-                     want=(True, True, True)):
-    """(dL/dE_v, dL/dE_col, dL/dn_col) over all problems (concatenated float64 tensors, None where
-    not wanted) from grad_chi0 in gw_chi0_build's output layout."""
+                     want=(True, True, True), coef=(False, False)):
+    """(dL/dE_v, dL/dE_col, dL/dn_col[, dL/dcoef_v, dL/dcoef_c]) over all problems
+    (concatenated tensors, None where not wanted) from grad_chi0 in gw_chi0_build's output
+    layout.  The coefficient gradients (float64 mode) are complex128, shaped like the
+    concatenated coefficient rows (sum of nv x npw, sum of nband x npw) and returned only
+    when one of them is asked for."""
     import torch
     arr = _probs(problems)
     om = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64))
@@ -223,10 +234,17 @@ def gw_chi0_backward(ctx, problems, omegas: Sequence[float], delta: float, prec:
     nv = sum(p.nv for p in arr)
     nc = sum(p.ncol for p in arr)
     g = [torch.zeros(n, dtype=torch.float64, device=dev) if w else None for n, w in zip((nv, nc, nc), want)]
+    gcoef = [None, None]
+    if any(coef):
+        npw = [_geom_npw(p.geom) for p in arr]
+        rows = (sum(p.nv * n for p, n in zip(arr, npw)), sum(p.nband * n for p, n in zip(arr, npw)))
+        gcoef = [torch.empty(r, dtype=torch.complex128, device=dev) if w else None for r, w in zip(rows, coef)]
     gc = grad_chi0.contiguous()
     _check(lib.gw_chi0_backward(ctx, arr, len(arr), len(om), om.ctypes.data_as(dp), float(delta), prec,
                                 _ptr(workspace), workspace.numel(), _ptr(gc), _ptr(g[0]), _ptr(g[1]), _ptr(g[2]),
-                                None, None), ctx)
+                                _ptr(gcoef[0]), _ptr(gcoef[1])), ctx)
+    if any(coef):
+        return tuple(g) + tuple(gcoef)
     return tuple(g)
 
 

@@ -1,8 +1,9 @@
 """torch.autograd wrappers of the differentiable entry points.
 
 ``chi0(...)`` differentiates with respect to the valence energies, the column energies
-(band energies or window energies E_i) and the column multiplicities (the weights
-g(E_i) dE_i of Eq. (energyintegration)); ``eps_inv(...)`` with respect to chi0.  Forward
+(band energies or window energies E_i), the column multiplicities (the weights
+g(E_i) dE_i of Eq. (energyintegration)) and, in the float64 mode, the wavefunction
+coefficients; ``eps_inv(...)`` with respect to chi0.  Forward
 and backward run in the library's kernels (gw_chi0_build / gw_chi0_backward,
 gw_eps_inv / gw_eps_inv_backward); the pair densities are recomputed in the backward
 pass, never stored.  Complex gradients follow torch's convention dL/dRe + i dL/dIm,
@@ -21,6 +22,7 @@ class _Chi0(torch.autograd.Function):
     @staticmethod
     def forward(ctx, e_v, e_col, n_col, gctx, geom, coef_v, coef_c, col_band, omegas, delta, prec):
         ev, ec, nc = e_v.detach().contiguous(), e_col.detach().contiguous(), n_col.detach().contiguous()
+        coef_v, coef_c = coef_v.detach().contiguous(), coef_c.detach().contiguous()
         prob = L.make_problem(geom, coef_v, ev, coef_c, ec, nc, col_band)
         if geom.value not in _geom_ng:
             raise ValueError("geometry not registered: create it with autograd.geometry()")
@@ -36,8 +38,11 @@ class _Chi0(torch.autograd.Function):
         gctx, geom, coef_v, coef_c, col_band, omegas, delta, prec, ng = ctx.meta
         prob = L.make_problem(geom, coef_v, ev, coef_c, ec, nc, col_band)
         want = tuple(ctx.needs_input_grad[:3])
-        g = L.gw_chi0_backward(gctx, [prob], omegas, delta, prec, gout.contiguous(), want=want)
-        return g[0], g[1], g[2], None, None, None, None, None, None, None, None
+        coef = tuple(ctx.needs_input_grad[5:7])
+        g = L.gw_chi0_backward(gctx, [prob], omegas, delta, prec, gout.contiguous(), want=want, coef=coef)
+        gcv = g[3].view(coef_v.shape) if any(coef) and g[3] is not None else None
+        gcc = g[4].view(coef_c.shape) if any(coef) and g[4] is not None else None
+        return g[0], g[1], g[2], None, None, gcv, gcc, None, None, None, None
 
 
 class _EpsInv(torch.autograd.Function):

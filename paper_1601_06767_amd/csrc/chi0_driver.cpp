@@ -50,6 +50,9 @@ struct Layout {
   int nparts = 1, nomega = 1, mode = 0;
   std::vector<ProbPlan> pp;
   size_t off_psic = 0, off_scr = 0, off_q = 0, off_part = 0, off_dx = 0, off_dn = 0, off_counter = 0, total = 0;
+  // coefficient gradients (backward, float64): mbar and a weighted copy of M per chunk,
+  // ubar of the chunk's columns and of the valence slots, column gradients of a chunk
+  size_t off_mbar = 0, off_atmp = 0, off_ubarc = 0, off_ubarv = 0, off_cbar = 0;
   int max_cc = 0;
 };
 
@@ -131,6 +134,22 @@ Layout make_layout(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nom
     L.off_part = take(max_part);
     L.off_dx = take(max_np * sizeof(double));
     L.off_dn = take(max_np * sizeof(double));
+    if (L.fp64) {
+      size_t mb = 0, uc = 0, uv = 0, cb = 0;
+      for (const auto& q : L.pp) {
+        const Geom& g = q.p->geom->g;
+        const size_t npts = (size_t)g.nd * g.nd * g.nd;
+        mb = std::max(mb, (size_t)q.npair * g.ngp * sizeof(double2));
+        uc = std::max(uc, (size_t)q.cc * npts * sizeof(double2));
+        uv = std::max(uv, (size_t)q.nvs * npts * sizeof(double2));
+        cb = std::max(cb, (size_t)std::max(q.cc, kBandBatch) * g.npw * sizeof(double2));
+      }
+      L.off_mbar = take(mb);
+      L.off_atmp = take(mb);
+      L.off_ubarc = take(uc);
+      L.off_ubarv = take(uv);
+      L.off_cbar = take(cb);
+    }
   }
   L.off_counter = take(256);
   L.total = o;
@@ -285,6 +304,48 @@ gw_status enqueue_build_all(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob
   return GW_OK;
 }
 
+// Coefficient gradients of one conduction chunk (float64; M of the chunk in the
+// workspace): mbar = sum_w [conj(w) chi0bar m + w chi0bar^H m], its transpose through the
+// finish stage into the Q buffer, then the column gradients of the chunk (added into gcc
+// through col_band) and, with want_v, the chunk's share of ubar_v.
+gw_status coef_grad_chunk(gw_ctx* ctx, const Layout& L, const ProbPlan& q, const Geom& g, const double* omega,
+                          int nomega, double delta, const double2* gbar, int c0, char* ws, double2* gcc, bool want_v) {
+  const gw_chi0_problem& p = *q.p;
+  const size_t npts = (size_t)g.nd * g.nd * g.nd;
+  double* w = (double*)(ws + q.off_w);
+  GW_HIP(ctx, gw::launch_fill_c128(ws + L.off_mbar, (size_t)q.npair * g.ngp, ctx->stream));
+  for (int iw = 0; iw < nomega; ++iw) {
+    GW_HIP(ctx, gw::launch_weights(p.e_v, 0, p.nv, q.nvs, p.e_col, p.n_col, c0, p.ncol, q.cc, omega[iw], delta,
+                                   L.nparts, w, ctx->stream));
+    const double2* gb = gbar + (size_t)iw * g.ng * g.ng;
+    // mbar += diag(conj w) M chi0bar^T  (rows: pairs, columns: G)
+    GW_HIP(ctx, gw::launch_weight_rows(ws + q.off_m, q.npair, g.ngp, w, L.nparts, true, ws + L.off_atmp, ctx->stream));
+    GW_HIP(ctx, gw::launch_zgemm_op(q.npair, g.ng, g.ng, double2{1.0, 0.0}, (const double2*)(ws + L.off_atmp), g.ngp,
+                                    gw::kOpN, gb, g.ng, gw::kOpT, double2{1.0, 0.0}, (double2*)(ws + L.off_mbar), g.ngp,
+                                    ctx->stream));
+    // mbar += diag(w) M conj(chi0bar)
+    GW_HIP(ctx, gw::launch_weight_rows(ws + q.off_m, q.npair, g.ngp, w, L.nparts, false, ws + L.off_atmp, ctx->stream));
+    GW_HIP(ctx, gw::launch_zgemm_op(q.npair, g.ng, g.ng, double2{1.0, 0.0}, (const double2*)(ws + L.off_atmp), g.ngp,
+                                    gw::kOpN, gb, g.ng, gw::kOpConj, double2{1.0, 0.0}, (double2*)(ws + L.off_mbar),
+                                    g.ngp, ctx->stream));
+  }
+  GW_HIP(ctx, gw::launch_qbar(g, ws + L.off_mbar, q.npair, ws + L.off_q, ctx->stream));
+  if (gcc) {
+    GW_HIP(ctx, gw::launch_ubar(g, ws + L.off_q, ws + q.off_psiv, q.nvs, q.cc, true, ws + L.off_ubarc, ctx->stream));
+    const int nvalid = std::min(q.cc, p.ncol - c0);
+    for (int s0 = 0; s0 < nvalid; s0 += kBandBatch) {
+      const int ns = std::min(kBandBatch, nvalid - s0);
+      GW_HIP(ctx, gw::launch_band_from_real(g, ws + L.off_ubarc + (size_t)s0 * npts * sizeof(double2), ns,
+                                            ws + L.off_scr, ws + L.off_cbar + (size_t)s0 * g.npw * sizeof(double2),
+                                            ctx->stream));
+    }
+    GW_HIP(ctx, gw::launch_scatter_cols(ws + L.off_cbar, nvalid, p.col_band, c0, g.npw, gcc, ctx->stream));
+  }
+  if (want_v)
+    GW_HIP(ctx, gw::launch_ubar(g, ws + L.off_q, ws + L.off_psic, q.nvs, q.cc, false, ws + L.off_ubarv, ctx->stream));
+  return GW_OK;
+}
+
 std::string graph_key(const gw_chi0_problem* probs, int nprob, int nomega, const double* omega, double delta,
                       gw_precision prec, const void* ws, size_t ws_bytes, const void* out) {
   std::string k;
@@ -317,9 +378,13 @@ gw_status gw_chi0_workspace_size(gw_ctx* ctx, const gw_chi0_problem* probs, int 
   }
   for (int b0 = 0; b0 < nprob; b0 += gw::kMaxBatch) {
     const int nb = std::min(gw::kMaxBatch, nprob - b0);
-    const Layout f = make_layout(ctx, probs + b0, nb, nomega, true, prec, false);
-    const Layout b = make_layout(ctx, probs + b0, nb, nomega, true, prec, true);
-    mx = std::max({mx, f.total, b.total});
+    // static and dynamic layouts split the contraction differently (one job, or two
+    // parts per frequency), so either can be the larger
+    for (const bool dyn : {false, true}) {
+      const Layout f = make_layout(ctx, probs + b0, nb, nomega, dyn, prec, false);
+      const Layout b = make_layout(ctx, probs + b0, nb, nomega, dyn, prec, true);
+      mx = std::max({mx, f.total, b.total});
+    }
   }
   *bytes = mx;
   return GW_OK;
@@ -386,12 +451,13 @@ gw_status gw_chi0_backward(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob,
   gw_status st = check_common(ctx, probs, nprob, nomega, omega, delta, prec);
   if (st != GW_OK) return st;
   if (!grad_chi0 || !workspace) return gw::fail(ctx, GW_EINVAL, "NULL workspace or gradient");
-  if (grad_coef_v || grad_coef_c)
-    return gw::fail(ctx, GW_EUNSUPPORTED, "gradients with respect to the coefficients are not built");
+  const bool want_coef = grad_coef_v || grad_coef_c;
+  if (want_coef && prec != GW_FP64)
+    return gw::fail(ctx, GW_EUNSUPPORTED, "coefficient gradients are computed in the float64 mode only");
   DeviceScope dev(ctx->device);
   char* ws = (char*)workspace;
   const char* gin = (const char*)grad_chi0;
-  size_t off_ev = 0, off_ec = 0;
+  size_t off_ev = 0, off_ec = 0, off_cv = 0, off_cc = 0;
   for (int ip = 0; ip < nprob; ++ip) {
     const gw_chi0_problem& p = probs[ip];
     const Geom& g = p.geom->g;
@@ -403,6 +469,11 @@ gw_status gw_chi0_backward(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob,
     double* gn = grad_n_col ? grad_n_col + off_ec : nullptr;
     gw::StageScope sc(ctx, gw::kStageBackward);
     if (gev) GW_HIP(ctx, gw::launch_fill_f64(gev, p.nv, 0.0, ctx->stream));
+    const size_t npts = (size_t)g.nd * g.nd * g.nd;
+    double2* gcv = grad_coef_v ? (double2*)grad_coef_v + off_cv : nullptr;
+    double2* gcc = grad_coef_c ? (double2*)grad_coef_c + off_cc : nullptr;
+    if (gcc) GW_HIP(ctx, gw::launch_fill_c128(gcc, (size_t)p.nband * g.npw, ctx->stream));
+    if (gcv) GW_HIP(ctx, gw::launch_fill_c128(ws + L.off_ubarv, (size_t)q.nvs * npts, ctx->stream));
     gw_status s = band_to_real(ctx, L, g, (const double2*)p.coef_v, p.nv, nullptr, 0, p.nv, q.nvs, ws, ws + q.off_psiv);
     if (s != GW_OK) return s;
     double* dx = (double*)(ws + L.off_dx);
@@ -424,10 +495,24 @@ gw_status gw_chi0_backward(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob,
                                              omega[iw], delta, dx, dn, ctx->stream));
       }
       GW_HIP(ctx, gw::launch_adjoint_reduce(dx, dn, p.nv, q.cc, c0, p.ncol, gev, gec, gn, ctx->stream));
+      if (want_coef) {
+        s = coef_grad_chunk(ctx, L, q, g, omega, nomega, delta, (const double2*)gin, c0, ws, gcc, gcv != nullptr);
+        if (s != GW_OK) return s;
+      }
+    }
+    if (gcv) {
+      // the valence gradients, from ubar_v summed over every chunk
+      for (int s0 = 0; s0 < p.nv; s0 += kBandBatch) {
+        const int ns = std::min(kBandBatch, p.nv - s0);
+        GW_HIP(ctx, gw::launch_band_from_real(g, ws + L.off_ubarv + (size_t)s0 * npts * sizeof(double2), ns,
+                                              ws + L.off_scr, gcv + (size_t)s0 * g.npw, ctx->stream));
+      }
     }
     gin += (size_t)nomega * g.ng * g.ng * sizeof(double2);
     off_ev += p.nv;
     off_ec += p.ncol;
+    off_cv += (size_t)p.nv * g.npw;
+    off_cc += (size_t)p.nband * g.npw;
   }
   return GW_OK;
 }

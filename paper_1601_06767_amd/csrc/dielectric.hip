@@ -226,15 +226,16 @@ __global__ void k_gather_cols(const double2* __restrict__ src, const int* __rest
 // ---------------------------------------------------------------- zgemm
 constexpr int ZT = 64, ZK = 16;
 
-// element (r, k) of op(X) for X row-major with leading dimension ld
-__device__ __forceinline__ double2 opget(const double2* x, int ld, int r, int k, bool ct) {
-  if (!ct) return x[(size_t)r * ld + k];
-  const double2 v = x[(size_t)k * ld + r];
-  return double2{v.x, -v.y};
+// element (r, k) of op(X) for X row-major with leading dimension ld; op: kOpN, kOpC
+// (conjugate transpose), kOpT (transpose), kOpConj (conjugate)
+__device__ __forceinline__ double2 opget(const double2* x, int ld, int r, int k, int op) {
+  const bool tr = op == kOpC || op == kOpT;
+  const double2 v = tr ? x[(size_t)k * ld + r] : x[(size_t)r * ld + k];
+  return (op == kOpC || op == kOpConj) ? double2{v.x, -v.y} : v;
 }
 
 __global__ __launch_bounds__(256) void k_zgemm(int m, int n, int kd, double2 alpha, const double2* __restrict__ A,
-                                               int lda, bool cta, const double2* __restrict__ B, int ldb, bool ctb,
+                                               int lda, int opa, const double2* __restrict__ B, int ldb, int opb,
                                                double2 beta, double2* __restrict__ C, int ldc) {
   __shared__ double2 sA[ZK][ZT + 1];   // sA[k][row]
   __shared__ double2 sB[ZK][ZT + 1];   // sB[k][col]
@@ -259,14 +260,13 @@ __global__ __launch_bounds__(256) void k_zgemm(int m, int n, int kd, double2 alp
       {
         const int kk = e / ZT, rr = e % ZT;
         double2 x{0.0, 0.0};
-        if (r0 + rr < m && k0 + kk < kd) x = opget(A, lda, r0 + rr, k0 + kk, cta);
+        if (r0 + rr < m && k0 + kk < kd) x = opget(A, lda, r0 + rr, k0 + kk, opa);
         sA[kk][rr] = x;
       }
       {
         const int kk = e / ZT, cc = e % ZT;
         double2 x{0.0, 0.0};
-        if (c0 + cc < n && k0 + kk < kd) x = ctb ? opget(B, ldb, k0 + kk, c0 + cc, true)
-                                                 : B[(size_t)(k0 + kk) * ldb + c0 + cc];
+        if (c0 + cc < n && k0 + kk < kd) x = opget(B, ldb, k0 + kk, c0 + cc, opb);
         sB[kk][cc] = x;
       }
     }
@@ -314,11 +314,17 @@ __global__ __launch_bounds__(256) void k_zgemm(int m, int n, int kd, double2 alp
 
 }  // namespace
 
+hipError_t launch_zgemm_op(int m, int n, int k, double2 alpha, const double2* A, int lda, int opa, const double2* B,
+                           int ldb, int opb, double2 beta, double2* C, int ldc, hipStream_t st) {
+  if (m < 1 || n < 1 || k < 1 || opa < kOpN || opa > kOpConj || opb < kOpN || opb > kOpConj) return hipErrorInvalidValue;
+  const int tiles = ((m + ZT - 1) / ZT) * ((n + ZT - 1) / ZT);
+  k_zgemm<<<tiles, 256, 0, st>>>(m, n, k, alpha, A, lda, opa, B, ldb, opb, beta, C, ldc);
+  return hipGetLastError();
+}
+
 hipError_t launch_zgemm(int m, int n, int k, double2 alpha, const double2* A, int lda, bool cta, const double2* B,
                         int ldb, bool ctb, double2 beta, double2* C, int ldc, hipStream_t st) {
-  const int tiles = ((m + ZT - 1) / ZT) * ((n + ZT - 1) / ZT);
-  k_zgemm<<<tiles, 256, 0, st>>>(m, n, k, alpha, A, lda, cta, B, ldb, ctb, beta, C, ldc);
-  return hipGetLastError();
+  return launch_zgemm_op(m, n, k, alpha, A, lda, cta ? kOpC : kOpN, B, ldb, ctb ? kOpC : kOpN, beta, C, ldc, st);
 }
 
 size_t eps_inv_workspace(int n) {

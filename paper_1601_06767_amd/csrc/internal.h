@@ -131,6 +131,25 @@ hipError_t launch_pair_planes(const Geom& g, const void* psi_v, const void* psi_
 template <typename T>
 hipError_t launch_pair_finish(const Geom& g, const void* q, int npair, void* m, hipStream_t st);
 bool pair_supported(int nd, int K);
+// (grid N, line radix R, pruned outputs K) of the compiled pair-transform instances
+#define GW_PAIR_CASES(X) \
+  X(24, 8, 5)            \
+  X(24, 8, 7)            \
+  X(24, 8, 9)            \
+  X(24, 8, 11)           \
+  X(72, 8, 9)            \
+  X(72, 8, 11)           \
+  X(72, 8, 13)           \
+  X(72, 8, 15)           \
+  X(72, 8, 17)           \
+  X(72, 8, 19)           \
+  X(96, 16, 17)          \
+  X(96, 16, 19)          \
+  X(96, 16, 21)          \
+  X(128, 16, 23)         \
+  X(128, 16, 25)         \
+  X(128, 16, 27)
+
 
 // Weights of Eq. (chi0) per pair p = v * ncs + c (zero for padded pairs):
 // part 0 = Re w, part 1 = Im w, w[part][p].
@@ -168,10 +187,32 @@ hipError_t launch_copy_m(const void* m, int nvs, int ncs, int ncs_pad, int ng, i
 constexpr int kTile = 128;  // the dielectric-sphere padding: a multiple of every contraction tile
 int contract_tile(int mode);   // G x G' tile of the contraction in this mode (64 or 128)
 
+// ---------------------------------------------------------------- coefficient gradients (float64)
+// a = diag(s) m over npair rows of ngp, s_p = w_p or conj(w_p) (w as launch_weights writes it)
+hipError_t launch_weight_rows(const void* m, int npair, int ngp, const double* w, int nparts, bool conj_w, void* a,
+                              hipStream_t st);
+// qbar[pair][p1][K^2] from mbar[pair][ngp]: the transpose of the pair finish stage
+hipError_t launch_qbar(const Geom& g, const void* mbar, int npair, void* qbar, hipStream_t st);
+// cond: ubar[c][x1][p2][p3] = sum_v h_vc u_v over the nvs valence slots (written);
+// else: ubar[v][...] += sum_c conj(h_vc) u_c over the ncs columns (added).  partner: the
+// other set's real-space bands (float64, band layout), qbar: pairs v * ncs + c.
+hipError_t launch_ubar(const Geom& g, const void* qbar, const void* partner, int nvs, int ncs, bool cond, void* ubar,
+                       hipStream_t st);
+// cbar[slot][npw] = the transpose of the band transform of ubar[slot] (tB: band scratch)
+hipError_t launch_band_from_real(const Geom& g, const void* ubar, int nslot, void* tB, void* cbar, hipStream_t st);
+// grad[row(c)] += cbar[c] for c < ncol, row(c) = col_band ? col_band[c0 + c] : c0 + c
+hipError_t launch_scatter_cols(const void* cbar, int ncol, const int32_t* col_band, int c0, int npw, void* grad,
+                               hipStream_t st);
+hipError_t launch_fill_c128(void* p, size_t n, hipStream_t st);
+
 // ---------------------------------------------------------------- dielectric
 constexpr int kNb = 64;     // Gauss-Jordan panel width
 hipError_t launch_zgemm(int m, int n, int k, double2 alpha, const double2* A, int lda, bool cta, const double2* B,
                         int ldb, bool ctb, double2 beta, double2* C, int ldc, hipStream_t st);
+// the same with op(X) in {X, X^H, X^T, conj X}
+enum { kOpN = 0, kOpC = 1, kOpT = 2, kOpConj = 3 };
+hipError_t launch_zgemm_op(int m, int n, int k, double2 alpha, const double2* A, int lda, int opa, const double2* B,
+                           int ldb, int opb, double2 beta, double2* C, int ldc, hipStream_t st);
 size_t eps_inv_workspace(int n);
 hipError_t launch_eps_inv(int n, const double* v, const double2* chi, double2* out, void* ws, int* flag,
                           hipStream_t st);

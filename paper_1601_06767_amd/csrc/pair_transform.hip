@@ -443,23 +443,6 @@ hipError_t run_finish(const Geom& g, const void* q, int npair, void* m, hipStrea
 }
 
 // (ND, R, K) instances: the grids and dielectric-sphere widths the kernels are built for.
-#define GW_PAIR_CASES(X) \
-  X(24, 8, 5)            \
-  X(24, 8, 7)            \
-  X(24, 8, 9)            \
-  X(24, 8, 11)           \
-  X(72, 8, 9)            \
-  X(72, 8, 11)           \
-  X(72, 8, 13)           \
-  X(72, 8, 15)           \
-  X(72, 8, 17)           \
-  X(72, 8, 19)           \
-  X(96, 16, 17)          \
-  X(96, 16, 19)          \
-  X(96, 16, 21)          \
-  X(128, 16, 23)         \
-  X(128, 16, 25)         \
-  X(128, 16, 27)
 
 }  // namespace
 
