@@ -89,9 +89,12 @@ def main():
     ap.add_argument("--tune", action="store_true", help="run the launch-shape tuner before timing each mode")
     ap.add_argument("--inputs-cache", default=None,
                     help="npz file for the generated inputs: loaded if present, written otherwise")
-    ap.add_argument("--workload", default="static", choices=["static", "batched"],
+    ap.add_argument("--workload", default="static", choices=["static", "batched", "grouped", "adjoint"],
                     help="static: the 72^3 / 128x4000 / NG 2000 build (default); batched: 8 q-points x 16 "
-                         "frequencies, 128x6000 bands, NG 800..3000, one persistent launch per chunk")
+                         "frequencies, 128x6000 bands, NG 800..3000, one persistent launch per chunk; grouped: "
+                         "96^3, 256 x 16000 bands grouped above 30 eV into 1 eV windows, NG 4000, with eps^-1; "
+                         "adjoint: 128^3, 512 x 25000 bands grouped the same way, NG 8000, build + eps^-1 + "
+                         "their adjoints down to the energy gradients")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
     args = ap.parse_args()
@@ -108,6 +111,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "batched":
         run_batched(args, torch, synth, p, dev)
+        return
+    if args.workload in ("grouped", "adjoint"):
+        run_grouped(args, torch, synth, p, dev, args.workload == "adjoint")
         return
     cfg = synth.config(1)
     nd = cfg.nd
@@ -330,6 +336,139 @@ def run_batched(args, torch, synth, p, dev):
             "config": {"workload": cfg.name, "grid": nd, "npw": len(gw), "nv": cfg.nv, "ncol": cfg.nc, "ng": ngs,
                        "pairs_per_q": npair, "q": [list(q) for q in cfg.qs], "omegas": len(om),
                        "delta_ev": cfg.delta_ev},
+            "band_pairs_per_s": hr["band_pairs_per_s"], "modes": results, "roofline": roofline,
+            "cpu_baseline": None}
+    print(json.dumps(line))
+
+
+def make_bands_logged(synth, cfg, c_index, gw, e_all):
+    """synth.make_bands (q = 0) in steps that each report progress: the Gaussian rows in
+    blocks of bands, then the orthonormalisation on the GPU."""
+    npw = len(gw)
+    bands_idx = np.concatenate([np.arange(cfg.nv), cfg.nv + np.asarray(c_index)])
+    rows = np.empty((len(bands_idx), npw), dtype=np.complex128)
+    for b0 in range(0, len(bands_idx), 1024):
+        rows[b0:b0 + 1024] = synth.gaussian_columns(cfg.index, 0, bands_idx[b0:b0 + 1024], npw)
+        log(f"  coefficient rows {min(b0 + 1024, len(bands_idx))}/{len(bands_idx)}")
+    q = synth.orthonormalize(rows, "cuda")
+    del rows
+    log("  orthonormalised")
+    ev = synth.valence_energies(cfg, 0)
+    return synth.Bands(q[:cfg.nv], ev[:cfg.nv], q[cfg.nv:], e_all[np.asarray(c_index)], np.arange(cfg.nv),
+                       np.asarray(c_index))
+
+
+def run_grouped(args, torch, synth, p, dev, backward):
+    """The grouped workloads (Eq. (energyintegration)): explicit bands up to E0 = 30 eV and
+    one representative per 1 eV window above, static.  With backward, one step is also the
+    adjoint of L = Re sum over the 27-G head block of eps^-1: gw_eps_inv_backward, then
+    gw_chi0_backward down to dL/dE_v, dL/dE_col and dL/dn_col (the pair densities are
+    recomputed)."""
+    cfg = synth.config(4 if backward else 2)
+    nd = cfg.nd
+    ev_ = synth.HARTREE_EV
+    gw = synth.wf_sphere(nd)
+    gc = synth.chi_sphere(cfg.ng[0], cfg.qs[0], cfg.cell)
+    e_all = synth.conduction_energies(cfg)
+    nwin = int(round((cfg.emax_ev - cfg.e0_ev) / cfg.de_ev))
+    col, e_col, n_col, n0 = p.gw_group_windows(e_all, cfg.e0_ev / ev_, cfg.de_ev / ev_, nwin)
+    t0 = time.time()
+    bands = make_bands_logged(synth, cfg, col, gw, e_all)
+    log(f"grouped inputs: {nd}^3, npw={len(gw)}, nv={cfg.nv}, {cfg.nc} bands -> {len(col)} columns "
+        f"({n0} explicit + {len(col) - n0} windows), NG={len(gc)}, ready in {time.time() - t0:.1f}s")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    ctx = p.gw_ctx_create(0)
+    geom = p.gw_geom_create(ctx, (nd,) * 3, gw, gc)
+    cv, ev, cc = t(bands.coef_v), t(bands.e_v), t(bands.coef_c)
+    del bands
+    ecol, ncol = t(e_col), t(n_col)
+    prob = p.make_problem(geom, cv, ev, cc, ecol, ncol)
+    ng = len(gc)
+    vcoul = t(synth.coulomb(gc, cfg.qs[0], cfg.cell))
+    head = torch.from_numpy(synth.loss_head_block(gc)).to(dev)
+    k = 2 * int(np.abs(gc).max()) + 1
+    npair = cfg.nv * len(col)
+    fl = flops_model(nd, k, ng, npair, cfg.nv + len(col))
+    # the adjoint recomputes the pair densities and forms Y = M Gbar^T (8 NG^2 per pair)
+    # and Zbar -> chi0bar (two NG^3 complex products, 16 NG^3)
+    bw = fl["planes"] + fl["finish"] + fl["band"] + 2.0 * fl["contract"] + 2.0 * fl["eps_inv"] if backward else 0.0
+    modes = [m for m in args.modes.split(",") if m]
+    wsb = max(p.gw_chi0_workspace_size(ctx, [prob], 1, p.PRECISIONS[m]) for m in modes)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    ws_inv = torch.empty(p.gw_eps_inv_workspace_size(ctx, ng, 1), dtype=torch.uint8, device=dev)
+    zout = torch.empty((ng, ng), dtype=torch.complex128, device=dev)
+    zbar = torch.zeros((ng, ng), dtype=torch.complex128, device=dev)
+    zbar[head, head] = 1.0
+    gchi = torch.empty((ng, ng), dtype=torch.complex128, device=dev)
+    log(f"workspace {wsb / 2**30:.1f} GiB")
+    stream = torch.cuda.current_stream()
+    results, chis, grads = {}, {}, {}
+    for m in modes:
+        out = torch.empty(ng * ng, dtype=torch.complex128, device=dev)
+        g = [None, None, None]
+        if args.tune:
+            p.gw_tune(ctx, [prob], 1, p.PRECISIONS[m], workspace=ws)
+            log(f"{m}: tuned (pair-kernel form, contraction splits) = {p.gw_tune_get(ctx, prob, p.PRECISIONS[m])}")
+
+        def run():
+            p.gw_chi0_build(ctx, [prob], [ng], [0.0], 0.0, p.PRECISIONS[m], workspace=ws, out=out)
+            p.gw_eps_inv(ctx, vcoul, out.view(ng, ng), workspace=ws_inv, out=zout)
+            if backward:
+                p.gw_eps_inv_backward(ctx, vcoul, zout, zbar, workspace=ws_inv, out=gchi)
+                g[:] = p.gw_chi0_backward(ctx, [prob], [0.0], 0.0, p.PRECISIONS[m], gchi.view(1, ng, ng),
+                                          workspace=ws)
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        p.gw_ctx_stage_times(ctx, reset=True)
+        p.gw_ctx_set_timing(ctx, True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for i in range(args.steps):
+            run()
+            log(f"{m}: step {i + 1}/{args.steps} enqueued")
+        e1.record(stream)
+        torch.cuda.synchronize()
+        p.gw_ctx_set_timing(ctx, False)
+        stages = p.gw_ctx_stage_times(ctx, reset=True)
+        ms = e0.elapsed_time(e1) / args.steps
+        p.gw_eps_inv_status(ctx)
+        chis[m] = out.view(ng, ng).cpu().numpy()
+        if backward:
+            grads[m] = [x.cpu().numpy() for x in g]
+        results[m] = {"ms_per_step": ms, "tflops": (fl["total"] + bw) / (ms * 1e-3) / 1e12,
+                      "band_pairs_per_s": npair / (ms * 1e-3),
+                      "stages_ms_per_step": {s_: v[0] / args.steps for s_, v in stages.items() if v[1]},
+                      "stage_launches_per_step": {s_: v[1] / args.steps for s_, v in stages.items() if v[1]},
+                      "eps_inf": float(1.0 / zout[0, 0].real.item())}
+        log(f"{m}: {ms:.1f} ms/step, {results[m]['tflops']:.2f} TFLOP/s, stages {results[m]['stages_ms_per_step']}")
+        del out
+    if "fp64" in chis:
+        ref = chis["fp64"]
+        nrm = np.linalg.norm(ref)
+        for m in chis:
+            results[m]["err_vs_fp64"] = float(np.linalg.norm(chis[m] - ref) / nrm)
+            if backward:
+                results[m]["grad_err_vs_fp64"] = [float(np.abs(a - b).max() / np.abs(b).max())
+                                                  for a, b in zip(grads[m], grads["fp64"])]
+    head_m = modes[0]
+    hr = results[head_m]
+    st = hr["stages_ms_per_step"]
+    launches = hr["stage_launches_per_step"]["contract"]
+    avg = st["contract"] / launches
+    per = fl["contract"] / launches
+    peak = PEAK["fp64_mfma"] if head_m == "fp64" else PEAK["fp32_mfma"] if head_m == "fp32" else PEAK["bf16_mfma"]
+    roofline = {"bound": "mfma", "kernel": "contract", "achieved": per / (avg * 1e-3) / 1e12, "peak": peak,
+                "unit": "TFLOP/s", "frac": per / (avg * 1e-3) / 1e12 / peak, "traffic": None, "avg_launch_ms": avg,
+                "algorithmic_work_per_launch": per}
+    line = {"metric": METRIC, "value": hr["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": hr["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[head_m],
+            "data": "synthetic",
+            "config": {"workload": cfg.name + ("-with-adjoint" if backward else ""), "grid": nd, "npw": len(gw),
+                       "nv": cfg.nv, "nc_generated": cfg.nc, "ncol": len(col), "explicit": n0, "ng": ng,
+                       "pairs": npair, "q": list(cfg.qs[0]), "omega": 0.0, "e0_ev": cfg.e0_ev, "de_ev": cfg.de_ev},
             "band_pairs_per_s": hr["band_pairs_per_s"], "modes": results, "roofline": roofline,
             "cpu_baseline": None}
     print(json.dumps(line))

@@ -199,6 +199,10 @@ gw_status gw_tune(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nome
  * per workgroup) and the number of pair-range splits of the contraction; both 0 if the
  * shape was not tuned. */
 gw_status gw_tune_get(gw_ctx* ctx, const gw_chi0_problem* prob, gw_precision prec, int* pair_variant, int* ksplit);
+/* Sets the shapes for prob's problem shape, e.g. to restore what gw_tune_get reported in
+ * an earlier process: pair_variant 0..4 (0 = automatic), ksplit 0..32 (0 = automatic);
+ * both 0 forgets the shape.  GW_EINVAL outside those ranges. */
+gw_status gw_tune_set(gw_ctx* ctx, const gw_chi0_problem* prob, gw_precision prec, int pair_variant, int ksplit);
 
 /* Workspace bytes for gw_pair_density with an nvs x ncs block. */
 gw_status gw_pair_density_workspace_size(gw_ctx* ctx, const gw_chi0_problem* prob, int nvs, int ncs,

@@ -70,11 +70,12 @@ _sig("gw_ctx_set_timing", C.c_int, [vp, C.c_int])
 _sig("gw_ctx_set_graph", C.c_int, [vp, C.c_int])
 _sig("gw_tune", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, C.c_int, vp, C.c_size_t])
 _sig("gw_tune_get", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)])
+_sig("gw_tune_set", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, C.c_int])
 _sig("gw_ctx_stage_times", C.c_int, [vp, dp, C.POINTER(C.c_longlong), C.c_int])
 
 STAGES = ["band", "planes", "finish", "weights", "contract", "finalize", "eps_inv", "backward"]
 
-EXPORTED = ["gw_ctx_set_timing", "gw_ctx_stage_times", "gw_ctx_set_graph", "gw_tune", "gw_tune_get",
+EXPORTED = ["gw_ctx_set_timing", "gw_ctx_stage_times", "gw_ctx_set_graph", "gw_tune", "gw_tune_get", "gw_tune_set",
             "gw_version", "gw_ctx_create", "gw_ctx_destroy", "gw_last_error", "gw_geom_create", "gw_geom_destroy",
             "gw_chi0_workspace_size", "gw_chi0_build", "gw_chi0_backward", "gw_pair_density_workspace_size", "gw_pair_density",
             "gw_eps_inv_workspace_size", "gw_eps_inv", "gw_eps_inv_status", "gw_eps_inv_backward",
@@ -137,6 +138,11 @@ def gw_tune(ctx, problems, nomega: int, prec: int, workspace=None) -> None:
     _check(lib.gw_tune(ctx, arr, len(arr), nomega, prec, _ptr(workspace), workspace.numel()), ctx)
 
 
+def gw_tune_set(ctx, problem, prec: int, pair_variant: int, ksplit: int) -> None:
+    """Sets the tuned shapes for this problem's shape (0 = automatic; both 0 forgets it)."""
+    _check(lib.gw_tune_set(ctx, C.byref(problem), prec, int(pair_variant), int(ksplit)), ctx)
+
+
 def gw_tune_get(ctx, problem, prec: int):
     """(pair-kernel form, contraction splits) tuned for this problem's shape, (0, 0) if untuned."""
     a, b = C.c_int(), C.c_int()
@@ -179,8 +185,11 @@ def make_problem(geom, coef_v, e_v, coef_c, e_col, n_col=None, col_band=None) ->
     """Problem record over torch device tensors (complex128 coefficients, float64 energies, int32 col_band)."""
     for t in (coef_v, coef_c):
         assert t.dtype.is_complex and t.element_size() == 16 and t.is_contiguous()
-    return gw_chi0_problem(geom, coef_v.shape[0], _ptr(coef_v), _ptr(e_v), coef_c.shape[0], _ptr(coef_c),
-                           e_col.shape[0], _ptr(col_band), _ptr(e_col), _ptr(n_col))
+    rec = gw_chi0_problem(geom, coef_v.shape[0], _ptr(coef_v), _ptr(e_v), coef_c.shape[0], _ptr(coef_c),
+                          e_col.shape[0], _ptr(col_band), _ptr(e_col), _ptr(n_col))
+    # the record holds raw device pointers: keep the tensors alive as long as the record
+    rec._tensors = (coef_v, e_v, coef_c, e_col, n_col, col_band)
+    return rec
 
 
 def _probs(problems) -> "C.Array":

@@ -106,7 +106,7 @@ Layout make_layout(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nom
     auto it = ctx->tune.find(shape_key(q.p->geom->g, q.p->nv, q.p->ncol, prec));
     if (it != ctx->tune.end()) {
       q.minb = it->second.first;
-      k = it->second.second;
+      if (it->second.second > 0) k = it->second.second;
     }
     if (force_ksplit) k = force_ksplit;
     q.ksplit = std::max(1, std::min(k, std::max(1, q.npair / 64)));
@@ -663,6 +663,20 @@ gw_status gw_tune(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nome
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   return result;
+}
+
+gw_status gw_tune_set(gw_ctx* ctx, const gw_chi0_problem* prob, gw_precision prec, int pair_variant, int ksplit) {
+  if (!ctx) return GW_EINVAL;
+  if (!prob || !prob->geom) return gw::fail(ctx, GW_EINVAL, "bad arguments");
+  if (prec != GW_FP64 && prec != GW_FP32 && prec != GW_BF16X3) return gw::fail(ctx, GW_EINVAL, "bad precision");
+  if (pair_variant < 0 || pair_variant > gw::kPairVariants || ksplit < 0 || ksplit > 32)
+    return gw::fail(ctx, GW_EINVAL, "pair-kernel form or split count out of range");
+  const std::string key = shape_key(prob->geom->g, prob->nv, prob->ncol, prec);
+  if (pair_variant == 0 && ksplit == 0)
+    ctx->tune.erase(key);
+  else
+    ctx->tune[key] = std::make_pair(pair_variant, ksplit);
+  return GW_OK;
 }
 
 gw_status gw_tune_get(gw_ctx* ctx, const gw_chi0_problem* prob, gw_precision prec, int* pair_variant, int* ksplit) {

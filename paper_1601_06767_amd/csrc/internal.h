@@ -121,6 +121,7 @@ size_t band_scratch_bytes(const Geom& g, int nslot, bool fp64);
 
 // Pair planes: Q[pair][p1][j2][j3] for pairs (v, c), v < nvs (multiple of 4), c < ncs (multiple of 8);
 // pair = v * ncs + c.
+constexpr int kPairVariants = 4;   // forms of the pair kernel a tuned shape may name
 // minb: 0 = automatic, 1 or 2 = 256-thread kernel with that many resident workgroups per CU,
 // 3 / 4 = split-line kernel with 4 / 2 valence bands per workgroup (falls back to the
 // 256-thread kernel where its LDS does not fit).

@@ -199,11 +199,20 @@ constexpr bool split_fits() {
   return SplitLds<T, R, K, TV>::bytes <= 160 * 1024;
 }
 
-// float64 shapes whose two-valence split-line kernel holds its state in registers: there
-// it runs ahead of the 256-thread kernel, which needs one resident workgroup per CU
+// Automatic form (measured per 32k-pair launch on one MI355X).  float64: the two-valence
+// split-line kernel wherever it fits (72^3 K 15: 18.7 against 31.7 ms; 96^3 K 19: 66 against
+// 102 ms; 128^3 K 25: 211 against 433 ms), since it halves the per-lane state that
+// otherwise costs the 256-thread kernel its second resident workgroup or spills.  float32:
+// the 256-thread kernel up to K = 21 (72^3: 9.0 ms, 96^3: 24.5 ms, both ahead of the split
+// forms), the four-valence split-line kernel from K = 23 on (128^3 K 25: 92 against 115 ms).
 template <typename T, int R, int K>
-constexpr bool split_preferred() {
-  return std::is_same<T, double>::value && R == 8 && K <= 15 && split_fits<T, R, K, 2>();
+constexpr int auto_variant() {
+  if constexpr (std::is_same<T, double>::value) {
+    if constexpr (split_fits<T, R, K, 2>()) return 4;
+  } else {
+    if constexpr (K >= 23 && split_fits<T, R, K, 4>()) return 3;
+  }
+  return planes_min_blocks<T, R, K>();
 }
 
 template <typename T, int ND, int R, int K, int TV>
@@ -407,10 +416,9 @@ hipError_t run_planes(const Geom& g, const void* psi_v, const void* psi_c, int n
   const cx<T>* pv = (const cx<T>*)psi_v;
   const cx<T>* pc = (const cx<T>*)psi_c;
   // variant: 1 / 2 = 256-thread kernel with one / two resident workgroups per CU,
-  // 3 / 4 = split-line kernel with 4 / 2 valence bands per workgroup,
-  // 0 = split-line where preferred, else by register demand
+  // 3 / 4 = split-line kernel with 4 / 2 valence bands per workgroup, 0 = automatic
   int variant = minb;
-  if (variant == 0) variant = split_preferred<T, R, K>() ? 4 : planes_min_blocks<T, R, K>();
+  if (variant == 0) variant = auto_variant<T, R, K>();
   if constexpr (split_fits<T, R, K, 4>()) {
     if (variant == 3) {
       const int nblk = ND * (nvs / 4) * (ncs / kTC);
