@@ -95,6 +95,8 @@ def main():
                          "96^3, 256 x 16000 bands grouped above 30 eV into 1 eV windows, NG 4000, with eps^-1; "
                          "adjoint: 128^3, 512 x 25000 bands grouped the same way, NG 8000, build + eps^-1 + "
                          "their adjoints down to the energy gradients")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="run every conduction chunk's contraction on the context's stream (no second stream)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
     args = ap.parse_args()
@@ -132,6 +134,7 @@ def main():
     log(f"inputs: npw={len(gw)} ng={len(gc)} nv={cfg.nv} nc={cfg.nc} ready in {time.time() - t0:.1f}s")
 
     ctx = p.gw_ctx_create(0)
+    p.gw_ctx_set_overlap(ctx, 0 if args.no_overlap else 1)
     geom = p.gw_geom_create(ctx, (nd,) * 3, gw, gc)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     cv, ev, cc, ec = t(bands.coef_v), t(bands.e_v), t(bands.coef_c), t(bands.e_c)
@@ -262,6 +265,7 @@ def run_batched(args, torch, synth, p, dev):
     t0 = time.time()
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     ctx = p.gw_ctx_create(0)
+    p.gw_ctx_set_overlap(ctx, 0 if args.no_overlap else 1)
     probs, ngs, keep = [], [], []
     cc = ec = None
     for iq in range(len(cfg.qs)):
@@ -378,6 +382,7 @@ def run_grouped(args, torch, synth, p, dev, backward):
         f"({n0} explicit + {len(col) - n0} windows), NG={len(gc)}, ready in {time.time() - t0:.1f}s")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     ctx = p.gw_ctx_create(0)
+    p.gw_ctx_set_overlap(ctx, 0 if args.no_overlap else 1)
     geom = p.gw_geom_create(ctx, (nd,) * 3, gw, gc)
     cv, ev, cc = t(bands.coef_v), t(bands.e_v), t(bands.coef_c)
     del bands

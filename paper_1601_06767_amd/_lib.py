@@ -71,11 +71,12 @@ _sig("gw_ctx_set_graph", C.c_int, [vp, C.c_int])
 _sig("gw_tune", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, C.c_int, vp, C.c_size_t])
 _sig("gw_tune_get", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)])
 _sig("gw_tune_set", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, C.c_int])
+_sig("gw_ctx_set_overlap", C.c_int, [vp, C.c_int])
 _sig("gw_ctx_stage_times", C.c_int, [vp, dp, C.POINTER(C.c_longlong), C.c_int])
 
 STAGES = ["band", "planes", "finish", "weights", "contract", "finalize", "eps_inv", "backward"]
 
-EXPORTED = ["gw_ctx_set_timing", "gw_ctx_stage_times", "gw_ctx_set_graph", "gw_tune", "gw_tune_get", "gw_tune_set",
+EXPORTED = ["gw_ctx_set_timing", "gw_ctx_stage_times", "gw_ctx_set_graph", "gw_tune", "gw_tune_get", "gw_tune_set", "gw_ctx_set_overlap",
             "gw_version", "gw_ctx_create", "gw_ctx_destroy", "gw_last_error", "gw_geom_create", "gw_geom_destroy",
             "gw_chi0_workspace_size", "gw_chi0_build", "gw_chi0_backward", "gw_pair_density_workspace_size", "gw_pair_density",
             "gw_eps_inv_workspace_size", "gw_eps_inv", "gw_eps_inv_status", "gw_eps_inv_backward",
@@ -136,6 +137,12 @@ def gw_tune(ctx, problems, nomega: int, prec: int, workspace=None) -> None:
         workspace = torch.empty(gw_chi0_workspace_size(ctx, arr, nomega, prec), dtype=torch.uint8,
                                 device=torch.device("cuda", torch.cuda.current_device()))
     _check(lib.gw_tune(ctx, arr, len(arr), nomega, prec, _ptr(workspace), workspace.numel()), ctx)
+
+
+def gw_ctx_set_overlap(ctx, mode: int) -> None:
+    """Chunk overlap of gw_chi0_build on a second stream: 0 off, 1 where it pays (default,
+    split-BF16x3), 2 always."""
+    _check(lib.gw_ctx_set_overlap(ctx, int(mode)), ctx)
 
 
 def gw_tune_set(ctx, problem, prec: int, pair_variant: int, ksplit: int) -> None:

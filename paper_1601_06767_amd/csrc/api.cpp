@@ -75,10 +75,16 @@ gw_status gw_ctx_create(int device, void* hip_stream, gw_ctx** out) {
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(device);
   hipError_t e = hipMalloc(&c->d_pivot_flag, sizeof(int));
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+    e = hipEventCreateWithFlags(&c->ev_ready[i], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_free[i], hipEventDisableTiming);
+  }
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
   (void)hipSetDevice(prev);
   if (e != hipSuccess) {
-    delete c;
-    g_create_error = "hipMalloc of the context flag failed";
+    gw_ctx_destroy(c);
+    g_create_error = "context set-up failed (device flag, side stream or events)";
     return GW_ENOMEM;
   }
   *out = c;
@@ -88,6 +94,15 @@ gw_status gw_ctx_create(int device, void* hip_stream, gw_ctx** out) {
 gw_status gw_ctx_destroy(gw_ctx* ctx) {
   if (!ctx) return GW_EINVAL;
   if (ctx->d_pivot_flag) (void)hipFree(ctx->d_pivot_flag);
+  if (ctx->side) {
+    (void)hipStreamSynchronize(ctx->side);
+    (void)hipStreamDestroy(ctx->side);
+  }
+  for (int i = 0; i < 2; ++i) {
+    if (ctx->ev_ready[i]) (void)hipEventDestroy(ctx->ev_ready[i]);
+    if (ctx->ev_free[i]) (void)hipEventDestroy(ctx->ev_free[i]);
+  }
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   for (auto& ge : ctx->graphs) {
     (void)hipGraphExecDestroy(ge.exec);
     (void)hipGraphDestroy(ge.graph);
@@ -271,6 +286,13 @@ gw_status gw_group_windows(int nband, const double* e_band, double e0, double de
 gw_status gw_ctx_set_timing(gw_ctx* ctx, int enable) {
   if (!ctx) return GW_EINVAL;
   ctx->timing = enable != 0;
+  return GW_OK;
+}
+
+gw_status gw_ctx_set_overlap(gw_ctx* ctx, int mode) {
+  if (!ctx) return GW_EINVAL;
+  if (mode < 0 || mode > 2) return gw::fail(ctx, GW_EINVAL, "overlap mode must be 0, 1 or 2");
+  ctx->overlap = mode;
   return GW_OK;
 }
 

@@ -42,6 +42,7 @@ struct ProbPlan {
   const gw_chi0_problem* p = nullptr;
   int nvs = 0, cc = 0, npair = 0, ksplit = 1, ntl = 0, minb = 0;
   size_t off_psiv = 0, off_m = 0, off_w = 0, off_acc = 0, acc_one = 0;
+  size_t off_m2 = 0, off_w2 = 0;   // second pair-density / weight buffers of the forward build
 };
 
 struct Layout {
@@ -118,6 +119,9 @@ Layout make_layout(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nom
     q.off_psiv = take((size_t)q.nvs * npts * L.csz);
     q.off_m = take((size_t)q.npair * g.ngp * L.csz);
     q.off_w = take((size_t)nomega * L.nparts * q.npair * sizeof(double));
+    // the forward build alternates two buffers between consecutive conduction chunks
+    q.off_m2 = backward ? q.off_m : take((size_t)q.npair * g.ngp * L.csz);
+    q.off_w2 = backward ? q.off_w : take((size_t)nomega * L.nparts * q.npair * sizeof(double));
     q.acc_one = (size_t)q.ksplit * g.ngp * g.ngp * sizeof(double2);
     q.off_acc = backward ? 0 : take(q.acc_one * nomega * L.nparts);
     max_psic = std::max(max_psic, (size_t)q.cc * npts * L.csz);
@@ -239,11 +243,29 @@ gw_status enqueue_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, in
   }
   int nchunk = 0;
   for (const ProbPlan& q : L.pp) nchunk = std::max(nchunk, (q.p->ncol + q.cc - 1) / q.cc);
-  for (int j = 0; j < nchunk; ++j) {
+  // Chunk j uses buffer set j % 2.  With overlap, its contraction runs on the side stream:
+  // ev_ready[b] (main) -> contraction j (side) -> ev_free[b] (side) -> transforms of
+  // chunk j + 2 (main), and ev_join before the finalisation.
+  // Overlap pays where the contraction leaves registers for a pair-kernel workgroup on the
+  // same CU: the split-BF16x3 form (160 VGPRs, one 512-thread workgroup per CU; measured
+  // 256 -> 229 ms per 72^3 / 512k-pair step).  The float64 and float32 contractions fill
+  // the register file, so the next chunk's transforms queue behind them (no gain measured;
+  // capping the contraction at one workgroup per CU made float64 slower, 519 -> 558 ms).
+  const bool ovl = nchunk > 1 && (ctx->overlap == 2 || (ctx->overlap == 1 && L.mode == 2));
+  hipStream_t cs = ovl ? ctx->side : ctx->stream;
+  auto chunk = [&](int j) -> gw_status {
+    const int buf = j & 1;
+    if (ovl && j >= 2) GW_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_free[buf], 0));
     gw::ContractBatch bt{};
     std::vector<int> active;
+    std::vector<ProbPlan> plans(L.pp.size());
     for (int i = 0; i < (int)L.pp.size(); ++i) {
-      const ProbPlan& q = L.pp[i];
+      ProbPlan& q = plans[i];
+      q = L.pp[i];
+      if (buf) {
+        q.off_m = q.off_m2;
+        q.off_w = q.off_w2;
+      }
       const int c0 = j * q.cc;
       if (c0 >= q.p->ncol) continue;
       gw_status s = band_to_real(ctx, L, q.p->geom->g, (const double2*)q.p->coef_c, q.p->nband, q.p->col_band, c0,
@@ -260,6 +282,10 @@ gw_status enqueue_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, in
       if (s != GW_OK) return s;
       active.push_back(i);
     }
+    if (ovl) {
+      GW_HIP(ctx, hipEventRecord(ctx->ev_ready[buf], ctx->stream));
+      GW_HIP(ctx, hipStreamWaitEvent(cs, ctx->ev_ready[buf], 0));
+    }
     // largest dielectric spheres first
     std::stable_sort(active.begin(), active.end(), [&](int a, int b) {
       return L.pp[a].p->geom->g.ngp > L.pp[b].p->geom->g.ngp;
@@ -267,7 +293,7 @@ gw_status enqueue_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, in
     bt.nprob = (int)active.size();
     long long item = 0;
     for (int k = 0; k < bt.nprob; ++k) {
-      const ProbPlan& q = L.pp[active[k]];
+      const ProbPlan& q = plans[active[k]];
       bt.item0[k] = item;
       bt.p[k] = gw::ContractProb{ws + q.off_m, (const double*)(ws + q.off_w), (double2*)(ws + q.off_acc), q.npair,
                                  q.p->geom->g.ngp, q.ksplit, q.ntl};
@@ -275,11 +301,22 @@ gw_status enqueue_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, in
     }
     bt.item0[bt.nprob] = item;
     int* counter = (int*)(ws + L.off_counter);
-    GW_HIP(ctx, gw::launch_zero(counter, 256, ctx->stream));
+    GW_HIP(ctx, gw::launch_zero(counter, 256, cs));
     const int grid = (int)std::min<long long>(item, 256LL * 8);
-    gw::StageScope sc(ctx, gw::kStageContract);
-    GW_HIP(ctx, gw::launch_contract_batch(L.mode, bt, counter, grid, ctx->stream));
+    {
+      gw::StageScope sc(ctx, gw::kStageContract, cs);
+      GW_HIP(ctx, gw::launch_contract_batch(L.mode, bt, counter, grid, cs));
+    }
+    if (ovl) GW_HIP(ctx, hipEventRecord(ctx->ev_free[buf], cs));
+    return GW_OK;
+  };
+  gw_status cst = GW_OK;
+  for (int j = 0; j < nchunk && cst == GW_OK; ++j) cst = chunk(j);
+  if (ovl) {   // join the side stream, also after an error
+    GW_HIP(ctx, hipEventRecord(ctx->ev_join, cs));
+    GW_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
   }
+  if (cst != GW_OK) return cst;
   for (const ProbPlan& q : L.pp) {
     const Geom& g = q.p->geom->g;
     for (int iw = 0; iw < nomega; ++iw) {

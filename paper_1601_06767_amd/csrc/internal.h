@@ -20,6 +20,11 @@ enum Stage { kStageBand = 0, kStagePlanes, kStageFinish, kStageWeights, kStageCo
 struct gw_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  // second stream of the forward build: the contraction of a conduction chunk runs there
+  // while the pair transforms of the next chunk run on `stream` (events order the two)
+  int overlap = 1;   // 0 off, 1 where it pays (split-BF16x3), 2 always
+  hipStream_t side = nullptr;
+  hipEvent_t ev_ready[2] = {}, ev_free[2] = {}, ev_join = nullptr;
   std::string err;
   int* d_pivot_flag = nullptr;   // set by the inversion kernels on a zero pivot
   // stage timers: events recorded around launches while timing is on
@@ -63,15 +68,17 @@ struct StageScope {
   gw_ctx* ctx;
   gw_ctx::Mark m{};
   bool on;
-  StageScope(gw_ctx* c, int stage) : ctx(c), on(c->timing) {
+  hipStream_t st;
+  StageScope(gw_ctx* c, int stage) : StageScope(c, stage, c->stream) {}
+  StageScope(gw_ctx* c, int stage, hipStream_t s) : ctx(c), on(c->timing), st(s) {
     if (on) {
       m.stage = stage;
       on = hipEventCreate(&m.a) == hipSuccess && hipEventCreate(&m.b) == hipSuccess &&
-           hipEventRecord(m.a, c->stream) == hipSuccess;
+           hipEventRecord(m.a, st) == hipSuccess;
     }
   }
   ~StageScope() {
-    if (on && hipEventRecord(m.b, ctx->stream) == hipSuccess) ctx->marks.push_back(m);
+    if (on && hipEventRecord(m.b, st) == hipSuccess) ctx->marks.push_back(m);
   }
 };
 }  // namespace gw

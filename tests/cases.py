@@ -44,6 +44,19 @@ def make_case(cfg_index: int, nv: Optional[int] = None, nc: Optional[int] = None
     return Case(cfg, cfg.nd, gw, gc, b.coef_v, b.e_v, b.coef_c, b.e_c)
 
 
+def many_valence_rows(case: Case, nv: int, seed: int = 12) -> Case:
+    """nv valence rows from the generated ones, each copy scaled by a random complex factor
+    and shifted a little in energy: a problem with more valence rows than the workload's
+    generator holds, so that a build or backward call spans several conduction chunks
+    (every result checked here holds for any coefficients)."""
+    r = np.random.default_rng(seed)
+    reps = -(-nv // len(case.e_v))
+    fac = r.uniform(0.5, 1.5, (reps, 1, 1)) * np.exp(2j * np.pi * r.uniform(size=(reps, 1, 1)))
+    case.coef_v = np.ascontiguousarray((fac * case.coef_v[None]).reshape(-1, case.coef_v.shape[1])[:nv])
+    case.e_v = (case.e_v[None] - 1e-3 * np.arange(reps)[:, None]).reshape(-1)[:nv].copy()
+    return case
+
+
 class Gpu:
     """One context on cuda:0 plus helpers that keep device copies alive."""
 

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import synth
-from cases import Gpu, make_case, rel_err
+from cases import Gpu, make_case, many_valence_rows, rel_err
 
 pytestmark = pytest.mark.gpu
 EV = synth.HARTREE_EV
@@ -121,3 +121,78 @@ def test_every_pair_kernel_form_matches_oracle(g, cfg, ng):
         p.gw_tune_set(g.ctx, prob, p.GW_FP64, 5, 0)
     with pytest.raises(p.GwError):
         p.gw_tune_set(g.ctx, prob, p.GW_FP64, 1, 33)
+
+
+def _build(g, ctx, probs, ngs, om, d, prec, ws):
+    p = g.p
+    out = p.gw_chi0_build(ctx, probs, ngs, om, d, p.PRECISIONS[prec], workspace=ws)
+    g.torch.cuda.synchronize()
+    return [x.cpu().numpy() for x in out]
+
+
+@pytest.mark.parametrize("om,d", [((0.0,), 0.0), ((0.0, 7.0), 0.1)], ids=["static", "dynamic"])
+def test_chunk_overlap_is_bitwise_neutral_and_matches_oracle(g, om, d):
+    # 400 valence rows make the conduction chunk 80 columns: three chunks of 240, so the
+    # contraction of one chunk overlaps the transforms of the next and a buffer is reused
+    p = g.p
+    torch = g.torch
+    case = many_valence_rows(make_case(0), 400)
+    prob = g.problem(case)
+    ng = len(case.gc)
+    om = np.asarray(om) / EV
+    ref = ref_chi0(case, om, d / EV)
+    for prec, tol in (("fp64", 1e-10), ("fp32", 2e-5), ("bf16x3", 1e-4)):
+        ws = torch.empty(p.gw_chi0_workspace_size(g.ctx, [prob], len(om), p.PRECISIONS[prec]), dtype=torch.uint8,
+                         device=g.dev)
+        p.gw_ctx_set_overlap(g.ctx, 0)
+        seq = _build(g, g.ctx, [prob], [ng], om, d / EV, prec, ws)[0]
+        p.gw_ctx_set_overlap(g.ctx, 2)
+        ovl = _build(g, g.ctx, [prob], [ng], om, d / EV, prec, ws)[0]
+        p.gw_ctx_set_overlap(g.ctx, 1)
+        auto = _build(g, g.ctx, [prob], [ng], om, d / EV, prec, ws)[0]
+        assert np.array_equal(seq, ovl) and np.array_equal(seq, auto), prec
+        for iw in range(len(om)):
+            fro, mx = rel_err(ovl[iw], ref[iw])
+            assert fro <= tol and mx <= tol, (prec, iw, fro, mx)
+
+
+def test_chunk_overlap_with_several_problems_and_graph_replay(g):
+    # two q-points with different dielectric spheres, three chunks each, in eager mode and
+    # replayed from a captured graph (with eager work between the replays)
+    p = g.p
+    torch = g.torch
+    cases = [many_valence_rows(make_case(0, ng=ng), 400) for ng in (259, 150)]
+    stream = torch.cuda.Stream()
+    ctx = p.gw_ctx_create(0, stream)
+    geoms = [p.gw_geom_create(ctx, (c.nd,) * 3, c.gw, c.gc) for c in cases]
+    probs = [p.make_problem(gm, g.t(c.coef_v), g.t(c.e_v), g.t(c.coef_c), g.t(c.e_c)) for gm, c in zip(geoms, cases)]
+    ngs = [len(c.gc) for c in cases]
+    om = [0.0, 3.0 / EV]
+    d = 0.1 / EV
+    ws = torch.empty(p.gw_chi0_workspace_size(ctx, probs, 2, p.GW_FP64), dtype=torch.uint8, device=g.dev)
+    with torch.cuda.stream(stream):
+        p.gw_ctx_set_overlap(ctx, 0)
+        seq = _build(g, ctx, probs, ngs, om, d, "fp64", ws)
+        p.gw_ctx_set_overlap(ctx, 2)
+        eager = _build(g, ctx, probs, ngs, om, d, "fp64", ws)
+        for a, b in zip(seq, eager):
+            assert np.array_equal(a, b)
+        out = torch.empty(sum(2 * n * n for n in ngs), dtype=torch.complex128, device=g.dev)
+        p.gw_ctx_set_graph(ctx, True)
+        for rep in range(3):
+            got = p.gw_chi0_build(ctx, probs, ngs, om, d, p.GW_FP64, workspace=ws, out=out)
+            torch.cuda.synchronize()
+            _ = (out.abs() ** 2).sum().item()
+            for a, b in zip(got, eager):
+                assert np.array_equal(a.cpu().numpy(), b), rep
+        p.gw_ctx_set_graph(ctx, False)
+    for c, e in zip(cases, eager):
+        ref = ref_chi0(c, om, d)
+        for iw in range(2):
+            fro, mx = rel_err(e[iw], ref[iw])
+            assert fro <= 1e-10 and mx <= 1e-10, (iw, fro, mx)
+    with pytest.raises(p.GwError):
+        p.gw_ctx_set_overlap(ctx, 3)
+    for gm in geoms:
+        p.gw_geom_destroy(gm)
+    p.gw_ctx_destroy(ctx)

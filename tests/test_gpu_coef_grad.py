@@ -6,7 +6,7 @@ import pytest
 
 import synth
 from oracle import grad as og
-from cases import Gpu, make_case
+from cases import Gpu, make_case, many_valence_rows
 
 pytestmark = pytest.mark.gpu
 EV = synth.HARTREE_EV
@@ -32,17 +32,6 @@ def grouped_columns(case, seed):
     case.col_band = col.astype(np.int32)
     case.e_col = case.e_c[col] + r.uniform(0.0, 0.02, len(col))
     case.n_col = r.uniform(1.0, 4.0, len(col))
-
-
-def many_valence_rows(case, nv):
-    """nv valence rows from the generated ones, each copy scaled by a random complex factor
-    and shifted a little in energy (the gradients hold for any coefficients)."""
-    r = np.random.default_rng(12)
-    reps = -(-nv // len(case.e_v))
-    fac = r.uniform(0.5, 1.5, (reps, 1, 1)) * np.exp(2j * np.pi * r.uniform(size=(reps, 1, 1)))
-    case.coef_v = np.ascontiguousarray((fac * case.coef_v[None]).reshape(-1, case.coef_v.shape[1])[:nv])
-    case.e_v = (case.e_v[None] - 1e-3 * np.arange(reps)[:, None]).reshape(-1)[:nv].copy()
-    return case
 
 
 def run(g, case, gbar, omegas, delta, prec="fp64", want=(True, True, True)):
