@@ -20,7 +20,7 @@ inverse, and central finite differences for every gradient.
 """
 from .chi0 import (  # noqa: F401
     box_map, psi_real_space, pair_density_fft, pair_density_direct, weights, weights_static,
-    chi0_from_pair_densities, chi0_bands, chi0_grouped_static, group_windows, free_electron_dos,
+    chi0_from_pair_densities, chi0_bands, chi0_grouped_static, group_windows, group_edges, free_electron_dos,
     speedup_factor, alias_free,
 )
 from .dielectric import eps_matrix, eps_inv, eps_inv_static_cholesky, eps_inf  # noqa: F401

@@ -226,6 +226,67 @@ def group_windows(e_c: np.ndarray, e0: float, de: float, nwin: int, mode: str = 
     return (np.asarray(col_band, dtype=np.int64), np.asarray(e_col), np.asarray(n_col), len(explicit))
 
 
+def group_edges(e_c: np.ndarray, edges: np.ndarray, mode: str = "count", rule: str = "midpoint",
+                dos_a: float = 0.0, dos_v0: float = 0.0):
+    """Columns of Eq. (energyintegration) on an arbitrary (uniform or non-uniform) energy grid.
+
+    Window k is [edges[k], edges[k+1]) (the last one closed); bands at or below edges[0]
+    (= E_0) are explicit columns.  Each window with at least one band gets integration
+    nodes: rule "midpoint" one node at the window centre, rule "gauss2" the two
+    Gauss-Legendre nodes centre -+ dE / (2 sqrt 3) (the higher-order rule the paper allows).
+    A node's column is (the window's band nearest the node, lower index on a tie; the node
+    energy; its weight).  Weights: mode "count" = the number of bands in the window (midpoint
+    rule only: a count is exact, a quadrature rule does not apply to it); mode "dos" = the
+    quadrature weight times g(E) = dos_a sqrt(E - dos_v0): dE for the midpoint, dE / 2 per
+    Gauss node.  Returns (col_band, e_col, n_col, n0) like group_windows."""
+    e_c = np.asarray(e_c, dtype=np.float64)
+    edges = np.asarray(edges, dtype=np.float64)
+    nwin = len(edges) - 1
+    if nwin < 0 or np.any(np.diff(edges) <= 0.0):
+        raise ValueError("edges must increase strictly")
+    if rule not in ("midpoint", "gauss2") or mode not in ("count", "dos"):
+        raise ValueError((mode, rule))
+    if rule == "gauss2" and mode == "count":
+        raise ValueError("the two-point rule needs density weights")
+    explicit = [i for i in range(len(e_c)) if e_c[i] <= edges[0]]
+    members = [[] for _ in range(nwin)]
+    for i in range(len(e_c)):
+        e = e_c[i]
+        if e <= edges[0]:
+            continue
+        if nwin == 0 or e > edges[-1]:
+            raise ValueError("band energy above the last window")
+        k = nwin - 1
+        for j in range(nwin):
+            if edges[j] < e < edges[j + 1] or (e == edges[j] and j > 0):
+                k = j
+                break
+        members[k].append(i)
+    col_band = list(explicit)
+    e_col = [float(e_c[i]) for i in explicit]
+    n_col = [1.0] * len(explicit)
+    for k in range(nwin):
+        if not members[k]:
+            continue
+        lo, hi = edges[k], edges[k + 1]
+        de = hi - lo
+        mid = 0.5 * (lo + hi)
+        if rule == "midpoint":
+            nodes = [(mid, de)]
+        else:
+            off = de / (2.0 * math.sqrt(3.0))
+            nodes = [(mid - off, 0.5 * de), (mid + off, 0.5 * de)]
+        for x, wq in nodes:
+            best = min(members[k], key=lambda i: (abs(e_c[i] - x), i))
+            col_band.append(best)
+            e_col.append(x)
+            if mode == "count":
+                n_col.append(float(len(members[k])))
+            else:
+                n_col.append(dos_a * math.sqrt(max(x - dos_v0, 0.0)) * wq)
+    return (np.asarray(col_band, dtype=np.int64), np.asarray(e_col), np.asarray(n_col), len(explicit))
+
+
 def speedup_factor(n_c: float, n_0_plus_n_e: float) -> float:
     """Tables 1-2: speed-up of the method = conventional band count / (N_0 + N_E)."""
     return n_c / n_0_plus_n_e

@@ -217,6 +217,62 @@ def test_grouping_counts_and_representatives():
         oracle.group_windows(np.array([0.5, 2.5]), e0, de, nwin)
 
 
+def test_group_edges_on_a_uniform_grid_is_group_windows():
+    r = np.random.default_rng(12)
+    e_c = r.uniform(0.1, 2.0, 400)
+    e0, de, nwin = 1.1, 0.09, 10
+    edges = e0 + de * np.arange(nwin + 1)
+    for mode in ("count", "dos"):
+        a = oracle.group_windows(e_c, e0, de, nwin, mode, dos_a=3.0, dos_v0=0.05)
+        b = oracle.group_edges(e_c, edges, mode, "midpoint", dos_a=3.0, dos_v0=0.05)
+        assert a[3] == b[3] and np.array_equal(a[0], b[0])
+        assert np.allclose(a[1], b[1], rtol=0, atol=1e-15) and np.allclose(a[2], b[2], rtol=1e-14, atol=0)
+
+
+def test_group_edges_quadrature_orders():
+    # density weights summed over the windows integrate g(E) = A sqrt(E - V0) over
+    # [E0, Emax]: the midpoint rule with error O(h^2), the two-point Gauss rule O(h^4)
+    A, v0, e0, emax = 2.5, 0.2, 1.0, 3.0
+    e_c = np.linspace(e0 + 1e-9, emax, 4001)        # every window holds bands
+    exact = 2.0 * A / 3.0 * ((emax - v0) ** 1.5 - (e0 - v0) ** 1.5)
+    errs = {}
+    for rule in ("midpoint", "gauss2"):
+        for nwin in (4, 8):
+            edges = np.linspace(e0, emax, nwin + 1)
+            col, e_col, n_col, n0 = oracle.group_edges(e_c, edges, "dos", rule, dos_a=A, dos_v0=v0)
+            assert n0 == 0 and len(col) == nwin * (1 if rule == "midpoint" else 2)
+            errs[rule, nwin] = abs(n_col.sum() - exact)
+    assert 3.5 < errs["midpoint", 4] / errs["midpoint", 8] < 4.5
+    assert 13.0 < errs["gauss2", 4] / errs["gauss2", 8] < 19.0
+    assert errs["gauss2", 8] < 1e-2 * errs["midpoint", 8]
+
+
+def test_group_edges_non_uniform_counts_and_representatives():
+    r = np.random.default_rng(13)
+    e_c = r.uniform(0.1, 2.0, 500)
+    edges = 1.0 + np.cumsum(np.concatenate([[0.0], 0.02 * 1.3 ** np.arange(9)]))
+    edges[-1] = 2.0
+    col, e_col, n_col, n0 = oracle.group_edges(e_c, edges, "count")
+    assert n0 == int((e_c <= edges[0]).sum())
+    assert n_col[n0:].sum() == 500 - n0
+    for j in range(n0, len(col)):
+        k = int(np.searchsorted(edges, e_col[j]) - 1)
+        assert abs(e_col[j] - 0.5 * (edges[k] + edges[k + 1])) < 1e-15
+        mem = [i for i in range(500) if edges[k] < e_c[i] and (e_c[i] < edges[k + 1] or
+                                                                (k == len(edges) - 2 and e_c[i] <= edges[k + 1]))]
+        assert len(mem) == n_col[j] and col[j] in mem
+        assert abs(e_c[col[j]] - e_col[j]) == min(abs(e_c[i] - e_col[j]) for i in mem)
+    # two Gauss nodes per window, each inside its window and represented by a member
+    col, e_col, n_col, n0 = oracle.group_edges(e_c, edges, "dos", "gauss2", dos_a=1.0)
+    assert len(col) - n0 == 2 * (len(edges) - 1)
+    with pytest.raises(ValueError):
+        oracle.group_edges(e_c, edges, "count", "gauss2")
+    with pytest.raises(ValueError):
+        oracle.group_edges(e_c, edges[::-1], "count")
+    with pytest.raises(ValueError):
+        oracle.group_edges(np.array([2.5]), edges, "count")
+
+
 def test_speedup_matches_printed_tables():
     with open(os.path.join(HERE, "golden", "paper_tables.json")) as f:
         tab = json.load(f)
