@@ -268,6 +268,24 @@ gw_status gw_group_windows(int nband, const double* e_band, double e0, double de
                            double dos_v0, int32_t* col_band, double* e_col, double* n_col, int* ncol_out,
                            int* n0_out);
 
+/* Columns of Eq. (energyintegration) on an arbitrary energy grid: the uniform or
+ * nonuniform grids and the higher-order rules the paper allows for the integral.
+ *   edges     host, nwin + 1 strictly increasing energies; window i is
+ *             [edges[i], edges[i+1]) (the last one closed), bands with E <= edges[0] = E0
+ *             are explicit columns.
+ *   rule      0 = midpoint: one node at the window centre;
+ *             1 = two-point Gauss-Legendre: nodes centre -+ dE / (2 sqrt 3), weight dE / 2
+ *             each (mode 1 only).
+ *   mode      0 = count (the number of bands in the window, midpoint rule only),
+ *             1 = dos (dos_a * sqrt(node - dos_v0) times the rule's weight).
+ * Each window holding at least one band gives one column per node: the window's band
+ * nearest the node (lower index on a tie), energy = the node.  Outputs (host, capacity
+ * >= nband + 2 nwin) as for gw_group_windows.  GW_EINVAL for edges that do not increase,
+ * a band above the last edge, an unknown rule or mode, or rule 1 with mode 0. */
+gw_status gw_group_windows_edges(int nband, const double* e_band, int nwin, const double* edges, int mode, int rule,
+                                 double dos_a, double dos_v0, int32_t* col_band, double* e_col, double* n_col,
+                                 int* ncol_out, int* n0_out);
+
 #ifdef __cplusplus
 }
 #endif

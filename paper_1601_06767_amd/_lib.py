@@ -65,6 +65,8 @@ _sig("gw_eps_inv_status", C.c_int, [vp])
 _sig("gw_eps_inv_backward", C.c_int, [vp, C.c_int, C.c_int, vp, vp, vp, vp, C.c_size_t, vp])
 _sig("gw_group_windows", C.c_int, [C.c_int, dp, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double, C.c_double,
                                    i32p, dp, dp, C.POINTER(C.c_int), C.POINTER(C.c_int)])
+_sig("gw_group_windows_edges", C.c_int, [C.c_int, dp, C.c_int, dp, C.c_int, C.c_int, C.c_double, C.c_double,
+                                          i32p, dp, dp, C.POINTER(C.c_int), C.POINTER(C.c_int)])
 
 _sig("gw_ctx_set_timing", C.c_int, [vp, C.c_int])
 _sig("gw_ctx_set_graph", C.c_int, [vp, C.c_int])
@@ -76,7 +78,7 @@ _sig("gw_ctx_stage_times", C.c_int, [vp, dp, C.POINTER(C.c_longlong), C.c_int])
 
 STAGES = ["band", "planes", "finish", "weights", "contract", "finalize", "eps_inv", "backward"]
 
-EXPORTED = ["gw_ctx_set_timing", "gw_ctx_stage_times", "gw_ctx_set_graph", "gw_tune", "gw_tune_get", "gw_tune_set", "gw_ctx_set_overlap",
+EXPORTED = ["gw_ctx_set_timing", "gw_ctx_stage_times", "gw_ctx_set_graph", "gw_tune", "gw_tune_get", "gw_tune_set", "gw_ctx_set_overlap", "gw_group_windows_edges",
             "gw_version", "gw_ctx_create", "gw_ctx_destroy", "gw_last_error", "gw_geom_create", "gw_geom_destroy",
             "gw_chi0_workspace_size", "gw_chi0_build", "gw_chi0_backward", "gw_pair_density_workspace_size", "gw_pair_density",
             "gw_eps_inv_workspace_size", "gw_eps_inv", "gw_eps_inv_status", "gw_eps_inv_backward",
@@ -328,6 +330,28 @@ def gw_eps_inv_backward(ctx, vcoul, eps_inv, grad_eps_inv, workspace=None, out=N
 
 
 # ---------------------------------------------------------------- grouping (host)
+def gw_group_windows_edges(e_band: np.ndarray, edges: np.ndarray, mode: int = 0, rule: int = 0, dos_a: float = 0.0,
+                           dos_v0: float = 0.0):
+    """Columns of Eq. (energyintegration) on window edges (uniform or not), rule 0 midpoint or
+    1 two-point Gauss: (col_band int32, e_col, n_col, n0) as numpy arrays."""
+    e = np.ascontiguousarray(e_band, dtype=np.float64)
+    ed = np.ascontiguousarray(edges, dtype=np.float64)
+    nwin = len(ed) - 1
+    cap = len(e) + 2 * max(nwin, 0)
+    col = np.zeros(cap, dtype=np.int32)
+    ec = np.zeros(cap)
+    nc = np.zeros(cap)
+    ncol, n0 = C.c_int(), C.c_int()
+    st = lib.gw_group_windows_edges(len(e), e.ctypes.data_as(dp), nwin, ed.ctypes.data_as(dp), mode, rule, dos_a,
+                                    dos_v0, col.ctypes.data_as(i32p), ec.ctypes.data_as(dp), nc.ctypes.data_as(dp),
+                                    C.byref(ncol), C.byref(n0))
+    if st != GW_OK:
+        raise GwError(st, "gw_group_windows_edges: edges not increasing, a band above the last edge, or a bad "
+                          "mode / rule")
+    k = ncol.value
+    return col[:k].copy(), ec[:k].copy(), nc[:k].copy(), n0.value
+
+
 def gw_group_windows(e_band: np.ndarray, e0: float, de: float, nwin: int, mode: int = 0, dos_a: float = 0.0,
                      dos_v0: float = 0.0):
     """Columns of Eq. (energyintegration): (col_band int32, e_col, n_col, n0) as numpy arrays."""

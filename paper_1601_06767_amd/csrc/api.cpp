@@ -283,6 +283,68 @@ gw_status gw_group_windows(int nband, const double* e_band, double e0, double de
   return GW_OK;
 }
 
+gw_status gw_group_windows_edges(int nband, const double* e_band, int nwin, const double* edges, int mode, int rule,
+                                 double dos_a, double dos_v0, int32_t* col_band, double* e_col, double* n_col,
+                                 int* ncol_out, int* n0_out) {
+  if (nband < 0 || (nband > 0 && !e_band) || nwin < 0 || !edges || !col_band || !e_col || !n_col || !ncol_out ||
+      !n0_out)
+    return GW_EINVAL;
+  if ((mode != 0 && mode != 1) || (rule != 0 && rule != 1) || (rule == 1 && mode == 0)) return GW_EINVAL;
+  for (int k = 0; k <= nwin; ++k)
+    if (!std::isfinite(edges[k]) || (k > 0 && !(edges[k] > edges[k - 1]))) return GW_EINVAL;
+  std::vector<int> win(nband, -1);
+  int ncol = 0;
+  for (int i = 0; i < nband; ++i) {
+    const double e = e_band[i];
+    if (!std::isfinite(e)) return GW_EINVAL;
+    if (e <= edges[0]) {
+      col_band[ncol] = i;
+      e_col[ncol] = e;
+      n_col[ncol] = 1.0;
+      ++ncol;
+      continue;
+    }
+    if (nwin == 0 || e > edges[nwin]) return GW_EINVAL;
+    // window k with edges[k] <= e < edges[k+1]; a band on the top edge joins the last window
+    const int k = (int)(std::upper_bound(edges, edges + nwin + 1, e) - edges) - 1;
+    win[i] = std::min(k, nwin - 1);
+  }
+  *n0_out = ncol;
+  std::vector<std::vector<int>> members(nwin);
+  for (int i = 0; i < nband; ++i)
+    if (win[i] >= 0) members[win[i]].push_back(i);
+  const double goff = 0.5 / std::sqrt(3.0);
+  for (int k = 0; k < nwin; ++k) {
+    if (members[k].empty()) continue;
+    const double de = edges[k + 1] - edges[k];
+    const double mid = 0.5 * (edges[k] + edges[k + 1]);
+    double node[2];
+    double wq;
+    int nnode;
+    if (rule == 0) {
+      node[0] = mid;
+      wq = de;
+      nnode = 1;
+    } else {
+      node[0] = mid - goff * de;
+      node[1] = mid + goff * de;
+      wq = 0.5 * de;
+      nnode = 2;
+    }
+    for (int t = 0; t < nnode; ++t) {
+      int best = -1;
+      for (int i : members[k])   // index order: a tie keeps the lower index
+        if (best < 0 || std::fabs(e_band[i] - node[t]) < std::fabs(e_band[best] - node[t])) best = i;
+      col_band[ncol] = best;
+      e_col[ncol] = node[t];
+      n_col[ncol] = mode == 0 ? (double)members[k].size() : dos_a * std::sqrt(std::max(node[t] - dos_v0, 0.0)) * wq;
+      ++ncol;
+    }
+  }
+  *ncol_out = ncol;
+  return GW_OK;
+}
+
 gw_status gw_ctx_set_timing(gw_ctx* ctx, int enable) {
   if (!ctx) return GW_EINVAL;
   ctx->timing = enable != 0;

@@ -66,6 +66,35 @@ def test_group_windows_edges():
     assert list(col) == [0, 1] and n0 == 2
 
 
+@pytest.mark.parametrize("seed", [0, 1])
+def test_group_windows_on_edges_matches_oracle(seed):
+    p = _lib()
+    r = np.random.default_rng(20 + seed)
+    e = r.uniform(0.1, 2.2, 700)
+    # geometric (non-uniform) windows from E_0 = 1.1 to 2.2, and a uniform grid
+    grids = [1.1 + 1.1 * (np.geomspace(1.0, 9.0, 12) - 1.0) / 8.0, np.linspace(1.1, 2.2, 23)]
+    for edges in grids:
+        for mode, rule, a, v0 in ((0, 0, 0.0, 0.0), (1, 0, 37.5, -0.3), (1, 1, 37.5, -0.3)):
+            got = p.gw_group_windows_edges(e, edges, mode, rule, a, v0)
+            want = oracle.group_edges(e, edges, "count" if mode == 0 else "dos", "midpoint" if rule == 0 else "gauss2",
+                                      a, v0)
+            assert got[3] == want[3]
+            assert np.array_equal(got[0], want[0])
+            assert np.array_equal(got[1], want[1])
+            assert np.array_equal(got[2], want[2])
+    # bands exactly on edges: E_0 explicit, an inner edge opens its window, the top closes the last
+    edges = np.array([1.0, 1.25, 1.5, 2.0])
+    e = np.array([1.0, 1.25, 2.0, 1.5, 0.2])
+    got = p.gw_group_windows_edges(e, edges)
+    want = oracle.group_edges(e, edges)
+    assert got[3] == want[3] == 2 and np.array_equal(got[0], want[0]) and np.array_equal(got[2], want[2])
+    for bad in (dict(edges=edges[::-1]), dict(edges=edges, mode=0, rule=1), dict(edges=edges, rule=2)):
+        with pytest.raises(p.GwError):
+            p.gw_group_windows_edges(e, **bad)
+    with pytest.raises(p.GwError):
+        p.gw_group_windows_edges(np.array([2.5]), edges)
+
+
 def test_context_create_without_gpu_reports_error():
     p = _lib()
     import torch
