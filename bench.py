@@ -89,12 +89,14 @@ def main():
     ap.add_argument("--tune", action="store_true", help="run the launch-shape tuner before timing each mode")
     ap.add_argument("--inputs-cache", default=None,
                     help="npz file for the generated inputs: loaded if present, written otherwise")
-    ap.add_argument("--workload", default="static", choices=["static", "batched", "grouped", "adjoint"],
+    ap.add_argument("--workload", default="static",
+                    choices=["static", "batched", "grouped", "adjoint", "grouping-study"],
                     help="static: the 72^3 / 128x4000 / NG 2000 build (default); batched: 8 q-points x 16 "
                          "frequencies, 128x6000 bands, NG 800..3000, one persistent launch per chunk; grouped: "
                          "96^3, 256 x 16000 bands grouped above 30 eV into 1 eV windows, NG 4000, with eps^-1; "
                          "adjoint: 128^3, 512 x 25000 bands grouped the same way, NG 8000, build + eps^-1 + "
-                         "their adjoints down to the energy gradients")
+                         "their adjoints down to the energy gradients; grouping-study: the 96^3 spectrum summed "
+                         "exactly and grouped on several energy grids (accuracy and time against the exact sum)")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run every conduction chunk's contraction on the context's stream (no second stream)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -116,6 +118,9 @@ def main():
         return
     if args.workload in ("grouped", "adjoint"):
         run_grouped(args, torch, synth, p, dev, args.workload == "adjoint")
+        return
+    if args.workload == "grouping-study":
+        run_grouping_study(args, torch, synth, p, dev)
         return
     cfg = synth.config(1)
     nd = cfg.nd
@@ -477,6 +482,96 @@ def run_grouped(args, torch, synth, p, dev, backward):
             "band_pairs_per_s": hr["band_pairs_per_s"], "modes": results, "roofline": roofline,
             "cpu_baseline": None}
     print(json.dumps(line))
+
+
+def run_grouping_study(args, torch, synth, p, dev):
+    """Accuracy and cost of the energy integration (Eqs. (chi02), (energyintegration)) on the
+    96^3 spectrum (256 valence, 16,000 conduction bands with density ~ sqrt(E) on 5..60 eV,
+    NG 4000): chi0 of the exact band sum against grouped sums above E0 = 30 eV on uniform
+    grids of dE = 1..5 eV (band-count weights), with density weights g(E) dE under the
+    midpoint and the two-point Gauss rule, on two nonuniform grids (geometric windows;
+    windows of equal band count), and with E0 lowered to 20, 15 and 10 eV.  Per grid: N0 + N_E, the paper's speed-up N_c / (N0 + N_E),
+    the measured build-time ratio, ||chi_grp - chi_exact||_F / ||chi_exact||_F and the change
+    of L = Re sum over the 27-G head block of eps^-1."""
+    cfg = synth.config(2)
+    nd = cfg.nd
+    hev = synth.HARTREE_EV
+    gw = synth.wf_sphere(nd)
+    gc = synth.chi_sphere(cfg.ng[0], cfg.qs[0], cfg.cell)
+    e_all = synth.conduction_energies(cfg)
+    t0 = time.time()
+    bands = make_bands_logged(synth, cfg, np.arange(cfg.nc), gw, e_all)
+    log(f"study inputs: {nd}^3, npw={len(gw)}, nv={cfg.nv}, nc={cfg.nc}, NG={len(gc)}, ready in "
+        f"{time.time() - t0:.1f}s")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    ctx = p.gw_ctx_create(0)
+    geom = p.gw_geom_create(ctx, (nd,) * 3, gw, gc)
+    cv, ev, cc = t(bands.coef_v), t(bands.e_v), t(bands.coef_c)
+    del bands
+    ng = len(gc)
+    vcoul = t(synth.coulomb(gc, cfg.qs[0], cfg.cell))
+    head = torch.from_numpy(synth.loss_head_block(gc)).to(dev)
+    mode = [m for m in args.modes.split(",") if m][0]
+    prec = p.PRECISIONS[mode]
+    e0 = cfg.e0_ev / hev
+    top = cfg.emax_ev / hev
+    # density of the generator's spectrum, dN/dE = A sqrt(E) (A per Hartree^(3/2))
+    dos_a = 1.5 * cfg.nc / (cfg.emax_ev ** 1.5 - 5.0 ** 1.5) * hev ** 1.5
+    above = np.sort(e_all[e_all > e0])
+    grids = [(f"uniform dE={de:g} eV, counts", np.append(np.arange(e0, top - 1e-12, de / hev), top), 0, 0)
+             for de in (1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0, 5.0)]
+    for de in (2.0, 4.0):
+        edges = np.append(np.arange(e0, top - 1e-12, de / hev), top)
+        grids.append((f"uniform dE={de:g} eV, g(E) dE midpoint", edges, 1, 0))
+        grids.append((f"uniform dE={de:g} eV, g(E) dE two-point Gauss", edges, 1, 1))
+    geo = [e0]
+    while geo[-1] < top:
+        geo.append(geo[-1] + (0.5 / hev) * 1.15 ** (len(geo) - 1))
+    geo[-1] = top
+    grids.append(("geometric dE 0.5 eV x 1.15^i, counts", np.array(geo), 0, 0))
+    q = np.quantile(above, np.linspace(0.0, 1.0, 31)[1:-1])
+    grids.append(("30 windows of equal band count, counts", np.concatenate([[e0], q, [top]]), 0, 0))
+    for e0_ev in (20.0, 15.0, 10.0):   # fewer explicit bands: the regime of the paper's N0 = 8 per atom
+        grids.append((f"E0={e0_ev:g} eV, uniform dE=2 eV, counts",
+                      np.append(np.arange(e0_ev / hev, top - 1e-12, 2.0 / hev), top), 0, 0))
+
+    ws = torch.empty(p.gw_chi0_workspace_size(ctx, [p.make_problem(geom, cv, ev, cc, t(e_all))], 1, prec),
+                     dtype=torch.uint8, device=dev)
+    ws_inv = torch.empty(p.gw_eps_inv_workspace_size(ctx, ng, 1), dtype=torch.uint8, device=dev)
+    out = torch.empty(ng * ng, dtype=torch.complex128, device=dev)
+    z = torch.empty((ng, ng), dtype=torch.complex128, device=dev)
+
+    def build(prob):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        p.gw_chi0_build(ctx, [prob], [ng], [0.0], 0.0, prec, workspace=ws, out=out)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - a
+        p.gw_eps_inv(ctx, vcoul, out.view(ng, ng), workspace=ws_inv, out=z)
+        p.gw_eps_inv_status(ctx)
+        return dt, out.view(ng, ng).clone(), float(z[head, head].real.sum().item())
+
+    exact_prob = p.make_problem(geom, cv, ev, cc, t(e_all))
+    build(exact_prob)   # warm-up
+    t_ex, chi_ex, l_ex = build(exact_prob)
+    nrm = float(torch.linalg.norm(chi_ex).item())
+    log(f"exact: {cfg.nc} columns, {t_ex:.2f} s, L = {l_ex:.6f}")
+    rows = [{"grid": "exact band sum", "columns": cfg.nc, "explicit": cfg.nc, "speedup_predicted": 1.0,
+             "build_s": t_ex, "speedup_measured": 1.0, "chi_rel_err": 0.0, "head_trace": l_ex, "head_trace_rel": 0.0}]
+    for name, edges, md, rule in grids:
+        col, e_col, n_col, n0 = p.gw_group_windows_edges(e_all, edges, md, rule, dos_a, 0.0)
+        prob = p.make_problem(geom, cv, ev, cc, t(e_col), t(n_col), t(col))
+        dt, chi, l_g = build(prob)
+        err = float(torch.linalg.norm(chi - chi_ex).item()) / nrm
+        row = {"grid": name, "columns": len(col), "explicit": n0, "speedup_predicted": cfg.nc / len(col),
+               "build_s": dt, "speedup_measured": t_ex / dt, "chi_rel_err": err, "head_trace": l_g,
+               "head_trace_rel": (l_g - l_ex) / abs(l_ex)}
+        rows.append(row)
+        log(f"{name}: {len(col)} columns ({n0} explicit), {dt:.2f} s, speed-up {t_ex / dt:.2f} "
+            f"(N_c/(N0+N_E) = {cfg.nc / len(col):.2f}), chi err {err:.3e}, L rel {row['head_trace_rel']:+.3e}")
+    print(json.dumps({"metric": METRIC, "workload": "grouping-study-" + cfg.name, "dtype": mode,
+                      "data": "synthetic", "grid": nd, "nv": cfg.nv, "nc": cfg.nc, "ng": ng, "e0_ev": cfg.e0_ev,
+                      "rows": rows}))
 
 
 if __name__ == "__main__":
