@@ -433,3 +433,40 @@ def test_coefficient_gradients_match_finite_differences(om, d):
                 want = part(gcc[idx])
             fd = (loss(cv_p, cc_p) - loss(cv_m, cc_m)) / (2 * h)
             assert abs(fd - want) <= 1e-6 * max(1.0, abs(want)), (which, idx, fd, want)
+
+
+# ---------------------------------------------------------------- static COH self-energy
+def _static_eps_inv(t, nv=3):
+    chi = oracle.chi0_bands(t["cv"][:nv], t["e_v"][:nv], t["cc"], t["e_c"], t["gw"], t["gc"], t["nd"])[0]
+    v = synth.coulomb(t["gc"], (0.01, 0, 0), t["cell"])
+    return oracle.eps_inv(chi, v), v
+
+
+def test_sigma_coh_over_a_complete_set_is_the_plane_wave_convolution():
+    # every orthonormal band of the 7^3-box wavefunction sphere (npw of them): the band sum
+    # equals the band-free closed form of the completeness relation
+    t = tiny(nd=12, rw=2, ng=19, nv=3, nc=5)
+    z, v = _static_eps_inv(t)
+    npw = t["gw"].shape[0]
+    full = synth.orthonormalize(synth.gaussian_columns(98, 3, range(npw), npw))
+    states = t["cv"][:2]
+    got = oracle.sigma_coh_static(states, full, t["gw"], t["gc"], t["nd"], z, v)
+    want = oracle.sigma_coh_complete_set(states, t["gw"], t["gc"], z, v)
+    assert np.abs(got - want).max() < 1e-12 * np.abs(want).max()
+    # a truncated band sum does not reach it (the slow convergence the grouping addresses)
+    part = oracle.sigma_coh_static(states, full[: npw // 2], t["gw"], t["gc"], t["nd"], z, v)
+    assert np.abs(part - want).max() > 1e-2 * np.abs(want).max()
+
+
+def test_sigma_coh_is_hermitian_and_negative_semidefinite():
+    t = tiny(nd=12, rw=3, ng=27, nv=3, nc=8)
+    z, v = _static_eps_inv(t)
+    states = np.concatenate([t["cv"], t["cc"][:2]])
+    w = np.random.default_rng(4).uniform(0.5, 3.0, len(t["cc"]))
+    s = oracle.sigma_coh_static(states, t["cc"], t["gw"], t["gc"], t["nd"], z, v, n_col=w)
+    assert np.abs(s - s.conj().T).max() < 1e-13 * np.abs(s).max()
+    ev = np.linalg.eigvalsh(0.5 * (s + s.conj().T))
+    assert ev.max() <= 1e-12 * np.abs(ev).max() and ev.min() < 0
+    # weights enter linearly: doubling every weight doubles Sigma
+    s2 = oracle.sigma_coh_static(states, t["cc"], t["gw"], t["gc"], t["nd"], z, v, n_col=2 * w)
+    assert np.abs(s2 - 2 * s).max() < 1e-13 * np.abs(s).max()
