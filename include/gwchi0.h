@@ -250,6 +250,28 @@ gw_status gw_eps_inv_status(gw_ctx* ctx);
 gw_status gw_eps_inv_backward(gw_ctx* ctx, int ng, int nbatch, const double* vcoul, const void* eps_inv,
                               const void* grad_eps_inv, void* workspace, size_t ws_bytes, void* grad_chi0);
 
+/* ---------------------------------------------------------------- COH self-energy */
+
+/* Static limit of the COH self-energy of Eq. (sigmach): with the energy denominator taken
+ * as -E', the frequency integral of eps^r^-1 - eps^a^-1 gives half the static
+ * eps^-1 - 1 (Kramers-Kronig), and for states n, n' (Gamma, q -> 0)
+ *   <n|Sigma_COH|n'> = 1/2 sum_c w_c sum_{G G'} M_{n c}(G) [eps^-1 - I]_{G G'} v(G')
+ *                      conj(M_{n' c}(G')),
+ * M the matrix element of Eq. (chi0) between state n and band c.  The sum over "all bands"
+ * runs over the problem's columns with the weights of Eq. (energyintegration), which the
+ * paper applies to this sum as well: bands with w = 1 and window representatives with
+ * w = g(E_i) dE_i (any valence, conduction and window columns the caller lists).
+ *   prob      coef_v / nv: the states n (1 .. 32 rows); coef_c, nband, ncol, col_band,
+ *             n_col (NULL = all 1): the columns.  Energies are not read in this limit.
+ *   vcoul     device, ng doubles v(q+G);  eps_inv  device complex128 ng x ng (static,
+ *             gw_eps_inv's output layout).
+ *   sigma     device complex128 nv x nv, row-major [n][n'] (overwritten).
+ * Float64 throughout.  Workspace: gw_sigma_coh_workspace_size.  GW_EINVAL for more than 32
+ * states, NULL arguments or a small workspace. */
+gw_status gw_sigma_coh_workspace_size(gw_ctx* ctx, const gw_chi0_problem* prob, size_t* bytes);
+gw_status gw_sigma_coh_static(gw_ctx* ctx, const gw_chi0_problem* prob, const double* vcoul, const void* eps_inv,
+                              void* workspace, size_t ws_bytes, void* sigma);
+
 /* ---------------------------------------------------------------- grouping */
 
 /* Columns of Eq. (energyintegration) from a conduction spectrum (host arrays).

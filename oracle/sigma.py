@@ -41,8 +41,10 @@ def sigma_coh_static(coef_n: np.ndarray, coef_cols: np.ndarray, gvec_wf: np.ndar
     psi_c = psi_real_space(coef_cols, gvec_wf, nd)
     m = pair_density_fft(psi_n, psi_c, gvec_chi)                  # (Ns, Nc, ng): M_{n n''}(G)
     a = coh_kernel(eps_inv_mat, vcoul)
-    z = np.einsum("gh,pch->pcg", a, np.conj(m))                   # sum_G' A_{GG'} conj(M_{n' n''}(G'))
-    return 0.5 * np.einsum("c,ncg,pcg->np", w, m, z)
+    z = np.conj(m) @ a.T                                          # z[n', n'', G] = sum_G' A_{GG'} conj(M_{n' n''}(G'))
+    ns, nc, ng = m.shape
+    x = (m * w[None, :, None]).reshape(ns, nc * ng)               # w_{n''} M_{n n''}(G), (n'', G) flattened
+    return 0.5 * (x @ z.reshape(ns, nc * ng).T)
 
 
 def sigma_coh_complete_set(coef_n: np.ndarray, gvec_wf: np.ndarray, gvec_chi: np.ndarray, eps_inv_mat: np.ndarray,

@@ -74,11 +74,14 @@ _sig("gw_tune", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, C.c_
 _sig("gw_tune_get", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)])
 _sig("gw_tune_set", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, C.c_int])
 _sig("gw_ctx_set_overlap", C.c_int, [vp, C.c_int])
+_sig("gw_sigma_coh_workspace_size", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.POINTER(C.c_size_t)])
+_sig("gw_sigma_coh_static", C.c_int, [vp, C.POINTER(gw_chi0_problem), vp, vp, vp, C.c_size_t, vp])
 _sig("gw_ctx_stage_times", C.c_int, [vp, dp, C.POINTER(C.c_longlong), C.c_int])
 
 STAGES = ["band", "planes", "finish", "weights", "contract", "finalize", "eps_inv", "backward"]
 
 EXPORTED = ["gw_ctx_set_timing", "gw_ctx_stage_times", "gw_ctx_set_graph", "gw_tune", "gw_tune_get", "gw_tune_set", "gw_ctx_set_overlap", "gw_group_windows_edges",
+            "gw_sigma_coh_workspace_size", "gw_sigma_coh_static",
             "gw_version", "gw_ctx_create", "gw_ctx_destroy", "gw_last_error", "gw_geom_create", "gw_geom_destroy",
             "gw_chi0_workspace_size", "gw_chi0_build", "gw_chi0_backward", "gw_pair_density_workspace_size", "gw_pair_density",
             "gw_eps_inv_workspace_size", "gw_eps_inv", "gw_eps_inv_status", "gw_eps_inv_backward",
@@ -282,6 +285,29 @@ def gw_pair_density(ctx, problem, v0: int, nvs: int, c0: int, ncs: int, ng: int,
     out = torch.empty((nvs, ncs, ng), dtype=torch.complex128, device=dev)
     _check(lib.gw_pair_density(ctx, C.byref(problem), v0, nvs, c0, ncs, prec, _ptr(workspace), workspace.numel(),
                                _ptr(out)), ctx)
+    return out
+
+
+# ---------------------------------------------------------------- COH self-energy
+def gw_sigma_coh_workspace_size(ctx, problem) -> int:
+    n = C.c_size_t()
+    _check(lib.gw_sigma_coh_workspace_size(ctx, C.byref(problem), C.byref(n)), ctx)
+    return n.value
+
+
+def gw_sigma_coh_static(ctx, problem, vcoul, eps_inv, workspace=None, out=None):
+    """Static COH self-energy <n|Sigma_COH|n'> (nv x nv complex128) of the problem's states
+    (coef_v rows) over its weighted columns, from a static eps^-1 (ng x ng) and v(q+G)."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if workspace is None:
+        workspace = torch.empty(gw_sigma_coh_workspace_size(ctx, problem), dtype=torch.uint8, device=dev)
+    if out is None:
+        out = torch.empty((problem.nv, problem.nv), dtype=torch.complex128, device=dev)
+    z = eps_inv.contiguous()
+    v = vcoul.contiguous()
+    _check(lib.gw_sigma_coh_static(ctx, C.byref(problem), _ptr(v), _ptr(z), _ptr(workspace),
+                                   workspace.numel(), _ptr(out)), ctx)
     return out
 
 

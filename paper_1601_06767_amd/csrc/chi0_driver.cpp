@@ -597,6 +597,88 @@ gw_status gw_pair_density(gw_ctx* ctx, const gw_chi0_problem* prob, int v0, int 
   return GW_OK;
 }
 
+namespace {
+// workspace of gw_sigma_coh_static: the float64 pair-transform layout of the states x one
+// chunk of columns, A^T (padded), Z of one chunk and the reduction partials
+struct CohLayout {
+  Layout L;
+  size_t off_a = 0, off_z = 0, off_part = 0, total = 0;
+  int nblk = 0;
+};
+constexpr int kCohBlocks = 1024;
+
+gw_status check_coh(gw_ctx* ctx, const gw_chi0_problem* p) {
+  if (!p || !p->geom) return gw::fail(ctx, GW_EINVAL, "NULL problem or geometry");
+  if (p->nv < 1 || p->nv > gw::coh_max_states())
+    return gw::fail(ctx, GW_EINVAL, "1 .. " + std::to_string(gw::coh_max_states()) + " states");
+  if (p->ncol < 1 || p->nband < 1 || !p->coef_v || !p->coef_c) return gw::fail(ctx, GW_EINVAL, "bad columns");
+  if (!p->col_band && p->ncol > p->nband) return gw::fail(ctx, GW_EINVAL, "ncol > nband without col_band");
+  return GW_OK;
+}
+
+CohLayout coh_layout(gw_ctx* ctx, const gw_chi0_problem& p) {
+  CohLayout c;
+  c.L = make_layout(ctx, &p, 1, 1, false, GW_FP64, false);
+  const Geom& g = p.geom->g;
+  const ProbPlan& q = c.L.pp[0];
+  size_t o = c.L.total;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = round_up(o + bytes, 256);
+    return at;
+  };
+  c.off_a = take((size_t)g.ngp * g.ngp * sizeof(double2));
+  c.off_z = take((size_t)q.npair * g.ngp * sizeof(double2));
+  c.nblk = kCohBlocks;
+  c.off_part = take((size_t)c.nblk * p.nv * p.nv * sizeof(double2));
+  c.total = o;
+  return c;
+}
+}  // namespace
+
+gw_status gw_sigma_coh_workspace_size(gw_ctx* ctx, const gw_chi0_problem* prob, size_t* bytes) {
+  if (!ctx) return GW_EINVAL;
+  if (!bytes) return gw::fail(ctx, GW_EINVAL, "NULL argument");
+  gw_status s = check_coh(ctx, prob);
+  if (s != GW_OK) return s;
+  *bytes = coh_layout(ctx, *prob).total;
+  return GW_OK;
+}
+
+gw_status gw_sigma_coh_static(gw_ctx* ctx, const gw_chi0_problem* prob, const double* vcoul, const void* eps_inv,
+                              void* workspace, size_t ws_bytes, void* sigma) {
+  if (!ctx) return GW_EINVAL;
+  gw_status s = check_coh(ctx, prob);
+  if (s != GW_OK) return s;
+  if (!vcoul || !eps_inv || !workspace || !sigma) return gw::fail(ctx, GW_EINVAL, "NULL argument");
+  const gw_chi0_problem& p = *prob;
+  const CohLayout c = coh_layout(ctx, p);
+  if (c.total > ws_bytes) return gw::fail(ctx, GW_EINVAL, "workspace too small: need " + std::to_string(c.total));
+  const Layout& L = c.L;
+  const ProbPlan& q = L.pp[0];
+  const Geom& g = p.geom->g;
+  DeviceScope dev(ctx->device);
+  char* ws = (char*)workspace;
+  GW_HIP(ctx, gw::launch_fill_c128(sigma, (size_t)p.nv * p.nv, ctx->stream));
+  GW_HIP(ctx, gw::launch_coh_kernel(eps_inv, vcoul, g.ng, g.ngp, ws + c.off_a, ctx->stream));
+  s = band_to_real(ctx, L, g, (const double2*)p.coef_v, p.nv, nullptr, 0, p.nv, q.nvs, ws, ws + q.off_psiv);
+  if (s != GW_OK) return s;
+  for (int c0 = 0; c0 < p.ncol; c0 += q.cc) {
+    s = band_to_real(ctx, L, g, (const double2*)p.coef_c, p.nband, p.col_band, c0, p.ncol, q.cc, ws, ws + L.off_psic);
+    if (s != GW_OK) return s;
+    s = pair_block(ctx, L, q, ws);
+    if (s != GW_OK) return s;
+    // Z = conj(M) A^T over the padded sphere (zero rows and columns beyond ng)
+    GW_HIP(ctx, gw::launch_zgemm_op(q.npair, g.ngp, g.ngp, double2{1.0, 0.0}, (const double2*)(ws + q.off_m), g.ngp,
+                                    gw::kOpConj, (const double2*)(ws + c.off_a), g.ngp, gw::kOpN, double2{0.0, 0.0},
+                                    (double2*)(ws + c.off_z), g.ngp, ctx->stream));
+    const int nvalid = std::min(q.cc, p.ncol - c0);
+    GW_HIP(ctx, gw::launch_coh_reduce(ws + q.off_m, ws + c.off_z, p.nv, q.cc, g.ngp, nvalid, p.n_col, c0, c.nblk,
+                                      ws + c.off_part, sigma, ctx->stream));
+  }
+  return GW_OK;
+}
+
 // Launch-shape tuner: times the candidates of the tunable launches on the first chunk
 // of each problem shape and keeps the fastest in the context.
 gw_status gw_tune(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, gw_precision prec,

@@ -128,6 +128,11 @@ size_t band_scratch_bytes(const Geom& g, int nslot, bool fp64);
 
 // Pair planes: Q[pair][p1][j2][j3] for pairs (v, c), v < nvs (multiple of 4), c < ncs (multiple of 8);
 // pair = v * ncs + c.
+// static COH self-energy (sigma.hip)
+int coh_max_states();
+hipError_t launch_coh_kernel(const void* eps_inv, const double* v, int ng, int ngp, void* at, hipStream_t st);
+hipError_t launch_coh_reduce(const void* m, const void* z, int ns, int cc, int ngp, int nvalid, const double* n_col,
+                             int c0, int nblk, void* part, void* s, hipStream_t st);
 constexpr int kPairVariants = 4;   // forms of the pair kernel a tuned shape may name
 // minb: 0 = automatic, 1 or 2 = 256-thread kernel with that many resident workgroups per CU,
 // 3 / 4 = split-line kernel with 4 / 2 valence bands per workgroup (falls back to the
