@@ -114,6 +114,54 @@ def wf_sphere(nd: int, radius: Optional[int] = None) -> np.ndarray:
     return np.ascontiguousarray(g[order].astype(np.int32))
 
 
+def wf_sphere_k(k: Sequence[float], radius: float) -> np.ndarray:
+    """Wavefunction sphere of a k-point (fractional, simple cubic): Miller indices g with
+    |k + g| <= radius, ordered by (|k + g|^2, n1, n2, n3). int32 (npw, 3)."""
+    k = np.asarray(k, dtype=np.float64)
+    g = _box(int(math.ceil(radius)) + 1)
+    d = ((g + k) ** 2).sum(1)
+    g, d = g[d <= radius * radius + 1e-9], d[d <= radius * radius + 1e-9]
+    order = np.lexsort((g[:, 2], g[:, 1], g[:, 0], d))
+    return np.ascontiguousarray(g[order].astype(np.int32))
+
+
+def kpoint_grid(n: int) -> np.ndarray:
+    """Gamma-centred n x n x n grid of fractional k-points in [0, 1), (n^3, 3)."""
+    f = np.arange(n) / n
+    return np.array([(a, b, c) for a in f for b in f for c in f], dtype=np.float64)
+
+
+@dataclasses.dataclass
+class KBands:
+    """Per k-point: sphere (npw_k, 3), valence / conduction coefficient rows on it, energies (Hartree)."""
+    gw: List[np.ndarray]
+    coef_v: List[np.ndarray]
+    e_v: List[np.ndarray]
+    coef_c: List[np.ndarray]
+    e_c: List[np.ndarray]
+
+
+def make_kbands(cfg_index: int, kpts: np.ndarray, radius: float, nv: int, nc: int,
+                emax_ev: float = 60.0) -> KBands:
+    """Orthonormal random bands per k-point (stream 40 + k for the coefficients, 60 + k for
+    the energies): valence E uniform in [-10, 0] eV, conduction with density ~ sqrt(E) on
+    [5, emax] eV, each sorted."""
+    out = KBands([], [], [], [], [])
+    for ik, k in enumerate(kpts):
+        gw = wf_sphere_k(k, radius)
+        q = orthonormalize(gaussian_columns(cfg_index, 40 + ik, range(nv + nc), gw.shape[0]))
+        r = rng(cfg_index, 60 + ik)
+        ev = np.sort(r.uniform(-10.0, 0.0, nv)) / HARTREE_EV
+        u = r.uniform(0.0, 1.0, nc)
+        ec = np.sort((5.0 ** 1.5 + u * (emax_ev ** 1.5 - 5.0 ** 1.5)) ** (2.0 / 3.0)) / HARTREE_EV
+        out.gw.append(gw)
+        out.coef_v.append(q[:nv])
+        out.e_v.append(ev)
+        out.coef_c.append(q[nv:])
+        out.e_c.append(ec)
+    return out
+
+
 def recip(cell: np.ndarray) -> np.ndarray:
     """Reciprocal lattice vectors (rows), b_i . a_j = 2 pi delta_ij."""
     return 2.0 * math.pi * np.linalg.inv(cell).T

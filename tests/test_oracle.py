@@ -470,3 +470,59 @@ def test_sigma_coh_is_hermitian_and_negative_semidefinite():
     # weights enter linearly: doubling every weight doubles Sigma
     s2 = oracle.sigma_coh_static(states, t["cc"], t["gw"], t["gc"], t["nd"], z, v, n_col=2 * w)
     assert np.abs(s2 - 2 * s).max() < 1e-13 * np.abs(s).max()
+
+
+# ---------------------------------------------------------------- k-point sum
+def test_kq_map_folds_k_plus_q_onto_the_grid():
+    k = synth.kpoint_grid(2)
+    idx, g0 = oracle.kq_map(k, (0.5, 0.0, 0.0))
+    for i in range(len(k)):
+        assert np.allclose(k[i] + (0.5, 0, 0), k[idx[i]] + g0[i])
+    assert any(np.abs(g0).sum(1) > 0)                       # some k + q leave the cell
+    with pytest.raises(ValueError):
+        oracle.kq_map(k, (0.25, 0.0, 0.0))
+
+
+def test_pair_density_kq_conserves_crystal_momentum():
+    # plane waves psi_c = e^{i(k + gb).r} at k = (1/2, 0, 0) and psi_v = e^{i(k'' + ga).r} at
+    # k'' = 0 = k + q - G0 with q = (1/2, 0, 0), G0 = (1, 0, 0): the matrix element is 1
+    # exactly at G = ga - gb - G0 (momentum conservation) and 0 elsewhere
+    k, kk, q = np.array([0.5, 0, 0]), np.zeros(3), np.array([0.5, 0, 0])
+    idx, g0 = oracle.kq_map(np.array([kk, k]), q)
+    assert idx[1] == 0 and tuple(g0[1]) == (1, 0, 0)
+    gw_k, gw_kk = synth.wf_sphere_k(k, 2.2), synth.wf_sphere_k(kk, 2.2)
+    gc = synth.chi_sphere(57, (0.5, 0, 0), np.eye(3) * 7.0)
+    ga_i, gb_i = 5, 9
+    cv = np.zeros((1, len(gw_kk)), dtype=np.complex128)
+    cc = np.zeros((1, len(gw_k)), dtype=np.complex128)
+    cv[0, ga_i] = 1.0
+    cc[0, gb_i] = 1.0
+    m = oracle.pair_density_kq(cv, gw_kk, cc, gw_k, g0[1], gc)[0, 0]
+    want = gw_kk[ga_i] - gw_k[gb_i] - g0[1]
+    for a, G in enumerate(gc):
+        assert m[a] == (1.0 if np.array_equal(G, want) else 0.0)
+    assert any(np.array_equal(G, want) for G in gc)
+
+
+def test_chi0_ksum_gamma_only_is_chi0_bands():
+    t = tiny(nv=3, nc=6)
+    gw = t["gw"]
+    got = oracle.chi0_ksum([t["cv"]], [t["e_v"]], [t["cc"]], [t["e_c"]], [gw], np.zeros((1, 3)), (0, 0, 0),
+                           t["gc"], omegas=(0.0, 0.3), delta=0.02)
+    want = oracle.chi0_bands(t["cv"], t["e_v"], t["cc"], t["e_c"], gw, t["gc"], t["nd"], (0.0, 0.3), 0.02)
+    assert np.abs(got - want).max() < 1e-13 * np.abs(want).max()
+
+
+def test_chi0_ksum_static_is_hermitian_nsd_and_label_free():
+    kp = synth.kpoint_grid(2)
+    b = synth.make_kbands(5, kp, 2.2, nv=3, nc=6)
+    gc = synth.chi_sphere(27, (0.5, 0, 0), np.eye(3) * 7.0)
+    chi = oracle.chi0_ksum(b.coef_v, b.e_v, b.coef_c, b.e_c, b.gw, kp, (0.5, 0, 0), gc)[0]
+    assert np.abs(chi - chi.conj().T).max() < 1e-14 * np.abs(chi).max()
+    ev = np.linalg.eigvalsh(chi)
+    assert ev.max() <= 1e-12 * np.abs(ev).max()
+    perm = np.random.default_rng(0).permutation(len(kp))
+    sel = lambda x: [x[i] for i in perm]
+    chi2 = oracle.chi0_ksum(sel(b.coef_v), sel(b.e_v), sel(b.coef_c), sel(b.e_c), sel(b.gw), kp[perm], (0.5, 0, 0),
+                            gc)[0]
+    assert np.abs(chi2 - chi).max() < 1e-13 * np.abs(chi).max()
