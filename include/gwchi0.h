@@ -163,6 +163,21 @@ gw_status gw_chi0_workspace_size(gw_ctx* ctx, const gw_chi0_problem* probs, int 
 gw_status gw_chi0_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, const double* omega,
                         double delta, gw_precision prec, void* workspace, size_t ws_bytes, void* chi0);
 
+/* The k-point sum of Eq. (chi0) for one q: chi0 = sum over the nk problems, one per k, all
+ * with the same dielectric-sphere size; the output is one set of nomega ng x ng blocks
+ * (gw_chi0_build's layout for a single problem), the problems added in order.  Problem k
+ * holds, on a wavefunction sphere that contains the spheres of k and of k'' (gw_kq_map:
+ * k + q = k'' + G0; coefficients outside a k-point's own sphere are zero):
+ *   coef_v, e_v   the valence rows and energies at k'' (the states at k + q),
+ *   coef_c, e_col the conduction columns at k,
+ *   geometry      dielectric sphere entered as G + G0 (Miller indices, same order for every
+ *                 k): the matrix element <v,k+q| e^{i(q+G).r} |c,k> is the pair density of
+ *                 the two rows at G + G0.
+ * Arguments, workspace (gw_chi0_workspace_size over the nk problems), modes and errors as
+ * for gw_chi0_build; GW_EINVAL if the sphere sizes differ. */
+gw_status gw_chi0_build_ksum(gw_ctx* ctx, const gw_chi0_problem* probs, int nk, int nomega, const double* omega,
+                             double delta, gw_precision prec, void* workspace, size_t ws_bytes, void* chi0);
+
 /* Adjoint of gw_chi0_build for a real loss L (same problems, frequencies, precision and
  * workspace size as the forward call).
  *   grad_chi0   device complex128, the layout of gw_chi0_build's output, holding
@@ -271,6 +286,14 @@ gw_status gw_eps_inv_backward(gw_ctx* ctx, int ng, int nbatch, const double* vco
 gw_status gw_sigma_coh_workspace_size(gw_ctx* ctx, const gw_chi0_problem* prob, size_t* bytes);
 gw_status gw_sigma_coh_static(gw_ctx* ctx, const gw_chi0_problem* prob, const double* vcoul, const void* eps_inv,
                               void* workspace, size_t ws_bytes, void* sigma);
+
+/* ---------------------------------------------------------------- k-points */
+
+/* k + q mapping of a k-point set (host arrays): for each k (fractional coordinates,
+ * nk x 3), kq_index[k] = the first k'' of the set with k + q - k'' integral (each
+ * coordinate within tol of an integer, 0 < tol < 0.5) and g0[3 k ..] = that integer vector
+ * G0, so that k + q = k'' + G0.  GW_EINVAL if some k + q is not in the set modulo G. */
+gw_status gw_kq_map(int nk, const double* kpts, const double* q, double tol, int32_t* kq_index, int32_t* g0);
 
 /* ---------------------------------------------------------------- grouping */
 

@@ -75,13 +75,16 @@ _sig("gw_tune_get", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.POINTER
 _sig("gw_tune_set", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, C.c_int])
 _sig("gw_ctx_set_overlap", C.c_int, [vp, C.c_int])
 _sig("gw_sigma_coh_workspace_size", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.POINTER(C.c_size_t)])
+_sig("gw_chi0_build_ksum", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, dp, C.c_double, C.c_int, vp,
+                                     C.c_size_t, vp])
+_sig("gw_kq_map", C.c_int, [C.c_int, dp, dp, C.c_double, i32p, i32p])
 _sig("gw_sigma_coh_static", C.c_int, [vp, C.POINTER(gw_chi0_problem), vp, vp, vp, C.c_size_t, vp])
 _sig("gw_ctx_stage_times", C.c_int, [vp, dp, C.POINTER(C.c_longlong), C.c_int])
 
 STAGES = ["band", "planes", "finish", "weights", "contract", "finalize", "eps_inv", "backward"]
 
 EXPORTED = ["gw_ctx_set_timing", "gw_ctx_stage_times", "gw_ctx_set_graph", "gw_tune", "gw_tune_get", "gw_tune_set", "gw_ctx_set_overlap", "gw_group_windows_edges",
-            "gw_sigma_coh_workspace_size", "gw_sigma_coh_static",
+            "gw_sigma_coh_workspace_size", "gw_sigma_coh_static", "gw_chi0_build_ksum", "gw_kq_map",
             "gw_version", "gw_ctx_create", "gw_ctx_destroy", "gw_last_error", "gw_geom_create", "gw_geom_destroy",
             "gw_chi0_workspace_size", "gw_chi0_build", "gw_chi0_backward", "gw_pair_density_workspace_size", "gw_pair_density",
             "gw_eps_inv_workspace_size", "gw_eps_inv", "gw_eps_inv_status", "gw_eps_inv_backward",
@@ -237,6 +240,35 @@ def gw_chi0_build(ctx, problems, ngs: Sequence[int], omegas: Sequence[float], de
         res.append(out[o: o + len(om) * g * g].view(len(om), g, g))
         o += len(om) * g * g
     return res
+
+
+def gw_chi0_build_ksum(ctx, problems, ng: int, omegas: Sequence[float], delta: float, prec: int, workspace=None,
+                       out=None):
+    """k-point sum of chi0 over the problems (one per k, same ng): (nomega, ng, ng) complex128."""
+    import torch
+    arr = _probs(problems)
+    om = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64))
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if workspace is None:
+        workspace = torch.empty(gw_chi0_workspace_size(ctx, arr, len(om), prec), dtype=torch.uint8, device=dev)
+    if out is None:
+        out = torch.empty((len(om), ng, ng), dtype=torch.complex128, device=dev)
+    _check(lib.gw_chi0_build_ksum(ctx, arr, len(arr), len(om), om.ctypes.data_as(dp), float(delta), prec,
+                                  _ptr(workspace), workspace.numel(), _ptr(out)), ctx)
+    return out
+
+
+def gw_kq_map(kpts: np.ndarray, q, tol: float = 1e-8):
+    """(kq_index int32 (nk,), g0 int32 (nk, 3)) with k + q = kpts[kq_index] + g0."""
+    k = np.ascontiguousarray(kpts, dtype=np.float64).reshape(-1, 3)
+    qq = np.ascontiguousarray(q, dtype=np.float64).reshape(3)
+    idx = np.zeros(len(k), dtype=np.int32)
+    g0 = np.zeros((len(k), 3), dtype=np.int32)
+    st = lib.gw_kq_map(len(k), k.ctypes.data_as(dp), qq.ctypes.data_as(dp), float(tol), idx.ctypes.data_as(i32p),
+                       g0.ctypes.data_as(i32p))
+    if st != GW_OK:
+        raise GwError(st, "gw_kq_map: some k + q is not on the k-point set")
+    return idx, g0
 
 
 def gw_chi0_backward(ctx, problems, omegas: Sequence[float], delta: float, prec: int, grad_chi0, workspace=None,

@@ -345,6 +345,26 @@ gw_status gw_group_windows_edges(int nband, const double* e_band, int nwin, cons
   return GW_OK;
 }
 
+gw_status gw_kq_map(int nk, const double* kpts, const double* q, double tol, int32_t* kq_index, int32_t* g0) {
+  if (nk < 1 || !kpts || !q || !kq_index || !g0 || !(tol > 0.0) || !(tol < 0.5)) return GW_EINVAL;
+  for (int i = 0; i < nk; ++i) {
+    int found = -1;
+    double d[3];
+    for (int j = 0; j < nk && found < 0; ++j) {
+      bool ok = true;
+      for (int a = 0; a < 3; ++a) {
+        d[a] = kpts[3 * i + a] + q[a] - kpts[3 * j + a];
+        if (!std::isfinite(d[a]) || std::fabs(d[a] - std::nearbyint(d[a])) >= tol) ok = false;
+      }
+      if (ok) found = j;
+    }
+    if (found < 0) return GW_EINVAL;
+    kq_index[i] = found;
+    for (int a = 0; a < 3; ++a) g0[3 * i + a] = (int32_t)std::nearbyint(d[a]);
+  }
+  return GW_OK;
+}
+
 gw_status gw_ctx_set_timing(gw_ctx* ctx, int enable) {
   if (!ctx) return GW_EINVAL;
   ctx->timing = enable != 0;

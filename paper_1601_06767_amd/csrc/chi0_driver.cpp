@@ -230,8 +230,11 @@ struct DeviceScope {
 };
 
 // Enqueue one batch (<= kMaxBatch problems) of the forward band sum.
+// ksum: every problem's chi0 goes into the same output (a k-point sum), added in problem
+// order after the first (or after earlier batches, with acc_out).
 gw_status enqueue_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, const double* omega,
-                        double delta, gw_precision prec, char* ws, size_t ws_bytes, char* out) {
+                        double delta, gw_precision prec, char* ws, size_t ws_bytes, char* out, bool ksum = false,
+                        bool acc_out = false) {
   const Layout L = make_layout(ctx, probs, nprob, nomega, delta > 0.0, prec, false);
   if (L.total > ws_bytes)
     return gw::fail(ctx, GW_EINVAL, "workspace too small: need " + std::to_string(L.total) + " bytes");
@@ -317,26 +320,31 @@ gw_status enqueue_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, in
     GW_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
   }
   if (cst != GW_OK) return cst;
-  for (const ProbPlan& q : L.pp) {
+  for (size_t i = 0; i < L.pp.size(); ++i) {
+    const ProbPlan& q = L.pp[i];
     const Geom& g = q.p->geom->g;
+    char* o = out;
     for (int iw = 0; iw < nomega; ++iw) {
       const double2* accA = (const double2*)(ws + q.off_acc + q.acc_one * ((size_t)iw * L.nparts));
       const double2* accB = L.nparts == 2 ? accA + q.acc_one / sizeof(double2) : nullptr;
       gw::StageScope sc(ctx, gw::kStageFinalize);
-      GW_HIP(ctx, gw::launch_finalize(accA, accB, q.ksplit, g.ng, g.ngp, (double2*)out, ctx->stream));
-      out += (size_t)g.ng * g.ng * sizeof(double2);
+      GW_HIP(ctx, gw::launch_finalize(accA, accB, q.ksplit, g.ng, g.ngp, (double2*)o, ksum && (i > 0 || acc_out),
+                                      ctx->stream));
+      o += (size_t)g.ng * g.ng * sizeof(double2);
     }
+    if (!ksum) out = o;
   }
   return GW_OK;
 }
 
 gw_status enqueue_build_all(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, const double* omega,
-                            double delta, gw_precision prec, char* ws, size_t ws_bytes, char* out) {
+                            double delta, gw_precision prec, char* ws, size_t ws_bytes, char* out, bool ksum = false) {
   for (int b0 = 0; b0 < nprob; b0 += gw::kMaxBatch) {
     const int nb = std::min(gw::kMaxBatch, nprob - b0);
-    gw_status s = enqueue_build(ctx, probs + b0, nb, nomega, omega, delta, prec, ws, ws_bytes, out);
+    gw_status s = enqueue_build(ctx, probs + b0, nb, nomega, omega, delta, prec, ws, ws_bytes, out, ksum, b0 > 0);
     if (s != GW_OK) return s;
-    for (int i = b0; i < b0 + nb; ++i) out += (size_t)nomega * probs[i].geom->g.ng * probs[i].geom->g.ng * 16;
+    if (!ksum)
+      for (int i = b0; i < b0 + nb; ++i) out += (size_t)nomega * probs[i].geom->g.ng * probs[i].geom->g.ng * 16;
   }
   return GW_OK;
 }
@@ -384,9 +392,10 @@ gw_status coef_grad_chunk(gw_ctx* ctx, const Layout& L, const ProbPlan& q, const
 }
 
 std::string graph_key(const gw_chi0_problem* probs, int nprob, int nomega, const double* omega, double delta,
-                      gw_precision prec, const void* ws, size_t ws_bytes, const void* out) {
+                      gw_precision prec, const void* ws, size_t ws_bytes, const void* out, bool ksum) {
   std::string k;
   auto add = [&](const void* p, size_t n) { k.append((const char*)p, n); };
+  add(&ksum, sizeof ksum);
   add(&nprob, sizeof nprob);
   add(probs, sizeof(gw_chi0_problem) * nprob);
   add(&nomega, sizeof nomega);
@@ -427,18 +436,26 @@ gw_status gw_chi0_workspace_size(gw_ctx* ctx, const gw_chi0_problem* probs, int 
   return GW_OK;
 }
 
-gw_status gw_chi0_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, const double* omega,
-                        double delta, gw_precision prec, void* workspace, size_t ws_bytes, void* chi0) {
+}  // extern "C"
+
+namespace {
+gw_status build_entry(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, const double* omega,
+                      double delta, gw_precision prec, void* workspace, size_t ws_bytes, void* chi0, bool ksum) {
   if (!ctx) return GW_EINVAL;
   gw_status s = check_common(ctx, probs, nprob, nomega, omega, delta, prec);
   if (s != GW_OK) return s;
   if (!chi0 || !workspace) return gw::fail(ctx, GW_EINVAL, "NULL workspace or output");
+  if (ksum)
+    for (int i = 1; i < nprob; ++i)
+      if (probs[i].geom->g.ng != probs[0].geom->g.ng)
+        return gw::fail(ctx, GW_EINVAL, "a k-point sum needs the same dielectric-sphere size in every problem");
   DeviceScope dev(ctx->device);
   if (!ctx->graph)
-    return enqueue_build_all(ctx, probs, nprob, nomega, omega, delta, prec, (char*)workspace, ws_bytes, (char*)chi0);
+    return enqueue_build_all(ctx, probs, nprob, nomega, omega, delta, prec, (char*)workspace, ws_bytes, (char*)chi0,
+                             ksum);
   // graph mode: replay the captured launch sequence of an identical call
   if (!ctx->stream) return gw::fail(ctx, GW_EINVAL, "graph mode needs a context on a non-null stream");
-  const std::string key = graph_key(probs, nprob, nomega, omega, delta, prec, workspace, ws_bytes, chi0);
+  const std::string key = graph_key(probs, nprob, nomega, omega, delta, prec, workspace, ws_bytes, chi0, ksum);
   for (auto& ge : ctx->graphs)
     if (ge.key == key) {
       GW_HIP(ctx, hipGraphLaunch(ge.exec, ctx->stream));
@@ -447,7 +464,7 @@ gw_status gw_chi0_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, in
   const bool timing = ctx->timing;
   ctx->timing = false;   // no event nodes in a captured graph
   GW_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-  s = enqueue_build_all(ctx, probs, nprob, nomega, omega, delta, prec, (char*)workspace, ws_bytes, (char*)chi0);
+  s = enqueue_build_all(ctx, probs, nprob, nomega, omega, delta, prec, (char*)workspace, ws_bytes, (char*)chi0, ksum);
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
   ctx->timing = timing;
@@ -465,6 +482,19 @@ gw_status gw_chi0_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, in
   ctx->graphs.push_back(gw_ctx::GraphEntry{key, graph, exec});
   GW_HIP(ctx, hipGraphLaunch(exec, ctx->stream));
   return GW_OK;
+}
+}  // namespace
+
+extern "C" {
+
+gw_status gw_chi0_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, const double* omega,
+                        double delta, gw_precision prec, void* workspace, size_t ws_bytes, void* chi0) {
+  return build_entry(ctx, probs, nprob, nomega, omega, delta, prec, workspace, ws_bytes, chi0, false);
+}
+
+gw_status gw_chi0_build_ksum(gw_ctx* ctx, const gw_chi0_problem* probs, int nk, int nomega, const double* omega,
+                             double delta, gw_precision prec, void* workspace, size_t ws_bytes, void* chi0) {
+  return build_entry(ctx, probs, nk, nomega, omega, delta, prec, workspace, ws_bytes, chi0, true);
 }
 
 gw_status gw_ctx_set_graph(gw_ctx* ctx, int enable) {

@@ -362,7 +362,7 @@ __global__ __launch_bounds__(64 * TileGeo<TILE>::NW) void k_contract_batch(Contr
 }
 
 __global__ void k_finalize(const double2* __restrict__ accA, const double2* __restrict__ accB, int ksplit, int ng,
-                           int ngp, double2* __restrict__ chi) {
+                           int ngp, int accumulate, double2* __restrict__ chi) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (size_t)ng * ng) return;
   const int g = (int)(e / ng), h = (int)(e % ng);
@@ -387,7 +387,13 @@ __global__ void k_finalize(const double2* __restrict__ accA, const double2* __re
     a.y = 0.0;
     b.y = 0.0;
   }
-  chi[e] = double2{a.x - b.y, a.y + b.x};
+  const double2 r{a.x - b.y, a.y + b.x};
+  if (accumulate) {
+    const double2 o = chi[e];
+    chi[e] = double2{o.x + r.x, o.y + r.y};
+  } else {
+    chi[e] = r;
+  }
 }
 
 __global__ void k_zero(uint4* p, size_t n16) {
@@ -465,9 +471,9 @@ hipError_t launch_contract_batch(int mode, const ContractBatch& bt, int* counter
 }
 
 hipError_t launch_finalize(const double2* accA, const double2* accB, int ksplit, int ng, int ngp, double2* chi,
-                           hipStream_t st) {
+                           bool accumulate, hipStream_t st) {
   const size_t n = (size_t)ng * ng;
-  k_finalize<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(accA, accB, ksplit, ng, ngp, chi);
+  k_finalize<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(accA, accB, ksplit, ng, ngp, accumulate ? 1 : 0, chi);
   return hipGetLastError();
 }
 

@@ -192,7 +192,7 @@ struct ContractBatch {
 hipError_t launch_contract_batch(int mode, const ContractBatch& bt, int* counter, int grid, hipStream_t st);
 // chi[G][G'] = sum_ks accA + i sum_ks accB (Hermitian parts mirrored), for G, G' < ng.
 hipError_t launch_finalize(const double2* accA, const double2* accB, int ksplit, int ng, int ngp, double2* chi,
-                           hipStream_t st);
+                           bool accumulate, hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_copy_m(const void* m, int nvs, int ncs, int ncs_pad, int ng, int ngp, bool fp64, double2* out,
                          hipStream_t st);

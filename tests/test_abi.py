@@ -95,6 +95,18 @@ def test_group_windows_on_edges_matches_oracle(seed):
         p.gw_group_windows_edges(np.array([2.5]), edges)
 
 
+def test_kq_map_matches_oracle():
+    p = _lib()
+    import synth
+    for n, q in ((2, (0.5, 0.0, 0.0)), (3, (1 / 3, 2 / 3, 0.0)), (1, (0.0, 0.0, 0.0))):
+        k = synth.kpoint_grid(n)
+        idx, g0 = p.gw_kq_map(k, q)
+        want = oracle.kq_map(k, q)
+        assert np.array_equal(idx, want[0]) and np.array_equal(g0, want[1])
+    with pytest.raises(p.GwError):
+        p.gw_kq_map(synth.kpoint_grid(2), (0.25, 0.0, 0.0))
+
+
 def test_context_create_without_gpu_reports_error():
     p = _lib()
     import torch
