@@ -51,7 +51,7 @@ def flops_model(nd, k, ng, npair, nband, with_inverse=True):
 
 KERNEL_OF_STAGE = {"planes": ("pair_transform.hip", ("k_pair_planes<{t}, 72, 8, 15", "k_pair_planes_split<{t}, 72, 8, 15")),
                    "finish": ("pair_transform.hip", "k_pair_finish<{t}, 72, 8, 15"),
-                   "contract": ("contract.hip", "k_contract_batch<{m}>")}
+                   "contract": ("contract.hip", "k_contract_batch<{m},")}
 
 
 def measured_traffic(stage, mode):
