@@ -162,6 +162,24 @@ def make_kbands(cfg_index: int, kpts: np.ndarray, radius: float, nv: int, nc: in
     return out
 
 
+def density_box(half: int, cell: np.ndarray, n_electrons: float, width: float = 0.6) -> np.ndarray:
+    """Synthetic valence density rho(G) on the Miller box |n_i| <= half (complex128,
+    (2 half + 1)^3, index (n1 + half, n2 + half, n3 + half)): electrons per bohr^3, a smooth
+    real density rho(G) = rho0 exp(-|G|^2 width^2 / 2) with rho(-G) = conj(rho(G)), plus a
+    seeded small phase so the off-diagonal structure is not symmetric in G."""
+    b = recip(cell)
+    vol = abs(np.linalg.det(cell))
+    rho0 = n_electrons / vol
+    a = np.arange(-half, half + 1)
+    n = np.stack(np.meshgrid(a, a, a, indexing="ij"), -1)
+    gg = ((n @ b) ** 2).sum(-1)
+    phase = rng(0, 77).uniform(-0.3, 0.3, n.shape[:3])
+    phase = 0.5 * (phase - phase[::-1, ::-1, ::-1])             # odd in G: rho(-G) = conj(rho(G))
+    box = rho0 * np.exp(-0.5 * gg * width * width) * np.exp(1j * phase)
+    box[half, half, half] = rho0
+    return box
+
+
 def recip(cell: np.ndarray) -> np.ndarray:
     """Reciprocal lattice vectors (rows), b_i . a_j = 2 pi delta_ij."""
     return 2.0 * math.pi * np.linalg.inv(cell).T

@@ -526,3 +526,56 @@ def test_chi0_ksum_static_is_hermitian_nsd_and_label_free():
     chi2 = oracle.chi0_ksum(sel(b.coef_v), sel(b.e_v), sel(b.coef_c), sel(b.e_c), sel(b.gw), kp[perm], (0.5, 0, 0),
                             gc)[0]
     assert np.abs(chi2 - chi).max() < 1e-13 * np.abs(chi).max()
+
+
+# ---------------------------------------------------------------- plasmon-pole extension
+def _gpp_inputs(ng=27):
+    t = tiny(nd=12, rw=3, ng=ng, nv=3, nc=6)
+    z, v = _static_eps_inv(t)
+    half = 2 * int(np.abs(t["gc"]).max())
+    box = synth.density_box(half, t["cell"], 8.0)
+    rho = lambda n: box[n[0] + half, n[1] + half, n[2] + half]
+    b = synth.recip(t["cell"])
+    return t, z, b, rho, box[half, half, half].real
+
+
+def test_gpp_static_limit_and_hermitian_density_weights():
+    t, z, b, rho, rho0 = _gpp_inputs()
+    om2, wt2 = oracle.gpp_modes(z, t["gc"], (0.01, 0, 0), b, rho, rho0)
+    e0 = oracle.gpp_eps_inv(om2, wt2, [0.0], 0.0)[0]
+    assert np.abs(e0 - z).max() < 1e-12 * np.abs(z).max()
+    # the density factor is Hermitian: rho(G - G') = conj(rho(G' - G))
+    r = np.array([[rho(ga - gb) for gb in t["gc"]] for ga in t["gc"]])
+    assert np.abs(r - r.conj().T).max() < 1e-15
+
+
+def test_gpp_homogeneous_gas_is_a_single_plasmon():
+    # no density modulation: Omega^2 = w_p^2 on the diagonal and 0 elsewhere
+    t, z, b, _, _ = _gpp_inputs()
+    rho0 = 0.05
+    om2, wt2 = oracle.gpp_modes(z, t["gc"], (0.01, 0, 0), b, lambda n: rho0 if not np.any(n) else 0.0, rho0)
+    assert np.allclose(om2, 4 * np.pi * rho0 * np.eye(len(t["gc"])), rtol=1e-14, atol=1e-16)
+
+
+def test_gpp_f_sum_rule():
+    # -(2/pi) int_0^inf w Im eps^-1(w) dw = Omega^2 for an element with real wt^2 > 0
+    t, z, b, rho, rho0 = _gpp_inputs()
+    om2, wt2 = oracle.gpp_modes(z, t["gc"], (0.01, 0, 0), b, rho, rho0)
+    # the most screened diagonal element (the head is unscreened here: its row of chi0 is 0)
+    a = int(np.argmax((np.eye(len(z)) - z).diagonal().real))
+    wt = np.sqrt(wt2[a, a].real)
+    assert abs(wt2[a, a].imag) < 1e-12 * abs(wt2[a, a]) and wt2[a, a].real > 0
+    eta = 1e-3 * wt
+    w = np.linspace(0.0, 40.0 * wt, 400001)
+    f = oracle.gpp_eps_inv(om2[a:a + 1, a:a + 1], wt2[a:a + 1, a:a + 1], w, eta)[:, 0, 0]
+    integral = -(2.0 / np.pi) * np.trapezoid(w * f.imag, w)
+    assert abs(integral - om2[a, a].real) < 2e-2 * abs(om2[a, a].real), (integral, om2[a, a])
+
+
+def test_gpp_unscreened_element_keeps_its_static_value():
+    t, z, b, rho, rho0 = _gpp_inputs()
+    z = z.copy()
+    z[3, 3] = 1.0                                          # delta - eps^-1 = 0 exactly
+    om2, wt2 = oracle.gpp_modes(z, t["gc"], (0.01, 0, 0), b, rho, rho0)
+    e = oracle.gpp_eps_inv(om2, wt2, [0.0, 0.2, 1.0], 1e-3)
+    assert np.all(e[:, 3, 3] == 1.0) and np.all(np.isfinite(e))
