@@ -287,6 +287,32 @@ gw_status gw_sigma_coh_workspace_size(gw_ctx* ctx, const gw_chi0_problem* prob, 
 gw_status gw_sigma_coh_static(gw_ctx* ctx, const gw_chi0_problem* prob, const double* vcoul, const void* eps_inv,
                               void* workspace, size_t ws_bytes, void* sigma);
 
+/* ---------------------------------------------------------------- plasmon pole */
+
+/* Generalized plasmon-pole extension of a static eps^-1 to real frequencies, the frequency
+ * model of the paper's calculations (Hybertsen-Louie).  Hartree atomic units:
+ *   Omega^2_GG' = 4 pi [(q+G).(q+G') / |q+G|^2] rho(G - G')        (= w_p^2 ... rho/rho(0))
+ *   wt^2_GG'    = Omega^2_GG' / (delta_GG' - eps^-1_GG'(0))
+ *   eps^-1_GG'(w) = delta_GG' + Omega^2_GG' / ((w + i eta)^2 - wt^2_GG')
+ * An element with delta - eps^-1(0) = 0 exactly has no pole (wt^2 = +inf) and keeps its
+ * static value at every w.
+ *   gvec_chi  host, ng x 3 Miller indices of the dielectric sphere (gw_eps_inv's order).
+ *   q, bvec   host: q in reciprocal-lattice units (3), reciprocal lattice vectors as rows
+ *             (9, 1/bohr); |q + G| must not vanish.
+ *   rho       device complex128 valence density rho(G) (electrons / bohr^3) on the Miller
+ *             box |n_i| <= rho_half, index ((n1 + h) W + n2 + h) W + n3 + h, W = 2 h + 1;
+ *             the box must cover every G - G' of the sphere (GW_EINVAL otherwise).
+ *   eps_inv_static  device complex128 ng x ng.
+ *   omega     host, nomega >= 0 real frequencies; eta >= 0 broadening.
+ *   modes     device complex128 2 ng^2 or NULL: Omega^2 then wt^2, row-major.
+ *   eps_inv_omega  device complex128 nomega x ng x ng.
+ * Synchronises the stream.  Workspace: gw_gpp_workspace_size (device copies of the sphere
+ * and the frequencies). */
+gw_status gw_gpp_workspace_size(gw_ctx* ctx, int ng, int nomega, size_t* bytes);
+gw_status gw_gpp_eps_inv(gw_ctx* ctx, int ng, const int32_t* gvec_chi, const double* q, const double* bvec,
+                         int rho_half, const void* rho, const void* eps_inv_static, int nomega, const double* omega,
+                         double eta, void* workspace, size_t ws_bytes, void* modes, void* eps_inv_omega);
+
 /* ---------------------------------------------------------------- k-points */
 
 /* k + q mapping of a k-point set (host arrays): for each k (fractional coordinates,

@@ -78,6 +78,9 @@ _sig("gw_sigma_coh_workspace_size", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.
 _sig("gw_chi0_build_ksum", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, dp, C.c_double, C.c_int, vp,
                                      C.c_size_t, vp])
 _sig("gw_kq_map", C.c_int, [C.c_int, dp, dp, C.c_double, i32p, i32p])
+_sig("gw_gpp_workspace_size", C.c_int, [vp, C.c_int, C.c_int, C.POINTER(C.c_size_t)])
+_sig("gw_gpp_eps_inv", C.c_int, [vp, C.c_int, i32p, dp, dp, C.c_int, vp, vp, C.c_int, dp, C.c_double, vp, C.c_size_t,
+                                 vp, vp])
 _sig("gw_sigma_coh_static", C.c_int, [vp, C.POINTER(gw_chi0_problem), vp, vp, vp, C.c_size_t, vp])
 _sig("gw_ctx_stage_times", C.c_int, [vp, dp, C.POINTER(C.c_longlong), C.c_int])
 
@@ -85,6 +88,7 @@ STAGES = ["band", "planes", "finish", "weights", "contract", "finalize", "eps_in
 
 EXPORTED = ["gw_ctx_set_timing", "gw_ctx_stage_times", "gw_ctx_set_graph", "gw_tune", "gw_tune_get", "gw_tune_set", "gw_ctx_set_overlap", "gw_group_windows_edges",
             "gw_sigma_coh_workspace_size", "gw_sigma_coh_static", "gw_chi0_build_ksum", "gw_kq_map",
+            "gw_gpp_workspace_size", "gw_gpp_eps_inv",
             "gw_version", "gw_ctx_create", "gw_ctx_destroy", "gw_last_error", "gw_geom_create", "gw_geom_destroy",
             "gw_chi0_workspace_size", "gw_chi0_build", "gw_chi0_backward", "gw_pair_density_workspace_size", "gw_pair_density",
             "gw_eps_inv_workspace_size", "gw_eps_inv", "gw_eps_inv_status", "gw_eps_inv_backward",
@@ -256,6 +260,29 @@ def gw_chi0_build_ksum(ctx, problems, ng: int, omegas: Sequence[float], delta: f
     _check(lib.gw_chi0_build_ksum(ctx, arr, len(arr), len(om), om.ctypes.data_as(dp), float(delta), prec,
                                   _ptr(workspace), workspace.numel(), _ptr(out)), ctx)
     return out
+
+
+def gw_gpp_eps_inv(ctx, gvec_chi: np.ndarray, q, bvec: np.ndarray, rho_box, eps_inv_static, omegas, eta: float,
+                   want_modes: bool = False):
+    """Plasmon-pole eps^-1(w) (nomega, ng, ng) from the static eps^-1 and the density box
+    rho_box (device complex128 (2h+1)^3); with want_modes also (Omega^2, wt^2)."""
+    import torch
+    g = np.ascontiguousarray(gvec_chi, dtype=np.int32)
+    ng = g.shape[0]
+    qq = np.ascontiguousarray(q, dtype=np.float64).reshape(3)
+    b = np.ascontiguousarray(bvec, dtype=np.float64).reshape(9)
+    om = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64))
+    w = rho_box.shape[0]
+    dev = torch.device("cuda", torch.cuda.current_device())
+    n = C.c_size_t()
+    _check(lib.gw_gpp_workspace_size(ctx, ng, len(om), C.byref(n)), ctx)
+    ws = torch.empty(n.value, dtype=torch.uint8, device=dev)
+    out = torch.empty((len(om), ng, ng), dtype=torch.complex128, device=dev)
+    modes = torch.empty((2, ng, ng), dtype=torch.complex128, device=dev) if want_modes else None
+    _check(lib.gw_gpp_eps_inv(ctx, ng, g.ctypes.data_as(i32p), qq.ctypes.data_as(dp), b.ctypes.data_as(dp), (w - 1) // 2,
+                              _ptr(rho_box.contiguous()), _ptr(eps_inv_static.contiguous()), len(om),
+                              om.ctypes.data_as(dp), float(eta), _ptr(ws), ws.numel(), _ptr(modes), _ptr(out)), ctx)
+    return (out, modes) if want_modes else out
 
 
 def gw_kq_map(kpts: np.ndarray, q, tol: float = 1e-8):

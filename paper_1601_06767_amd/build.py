@@ -18,7 +18,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgwchi0.so")
 ARCH = os.environ.get("GWCHI0_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "chi0_driver.cpp", "band_fft.hip", "pair_transform.hip", "contract.hip", "dielectric.hip", "adjoint.hip", "coef_grad.hip", "sigma.hip"]
+SOURCES = ["api.cpp", "chi0_driver.cpp", "band_fft.hip", "pair_transform.hip", "contract.hip", "dielectric.hip", "adjoint.hip", "coef_grad.hip", "sigma.hip", "gpp.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
+#include <cstdint>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -362,6 +364,69 @@ gw_status gw_kq_map(int nk, const double* kpts, const double* q, double tol, int
     kq_index[i] = found;
     for (int a = 0; a < 3; ++a) g0[3 * i + a] = (int32_t)std::nearbyint(d[a]);
   }
+  return GW_OK;
+}
+
+namespace {
+size_t gpp_ws(int ng, int nomega) {
+  auto r = [](size_t b) { return (b + 255) / 256 * 256; };
+  return r((size_t)ng * 3 * sizeof(double)) + r((size_t)ng * 3 * sizeof(int32_t)) +
+         r((size_t)std::max(nomega, 1) * sizeof(double));
+}
+}  // namespace
+
+gw_status gw_gpp_workspace_size(gw_ctx* ctx, int ng, int nomega, size_t* bytes) {
+  if (!ctx) return GW_EINVAL;
+  if (ng < 1 || nomega < 0 || !bytes) return gw::fail(ctx, GW_EINVAL, "bad arguments");
+  *bytes = gpp_ws(ng, nomega);
+  return GW_OK;
+}
+
+gw_status gw_gpp_eps_inv(gw_ctx* ctx, int ng, const int32_t* gvec_chi, const double* q, const double* bvec,
+                         int rho_half, const void* rho, const void* eps_inv_static, int nomega, const double* omega,
+                         double eta, void* workspace, size_t ws_bytes, void* modes, void* eps_inv_omega) {
+  if (!ctx) return GW_EINVAL;
+  if (ng < 1 || nomega < 0 || !gvec_chi || !q || !bvec || !rho || !eps_inv_static || !workspace ||
+      (nomega > 0 && (!omega || !eps_inv_omega)) || rho_half < 0 || !(eta >= 0.0) || !std::isfinite(eta))
+    return gw::fail(ctx, GW_EINVAL, "bad arguments");
+  if (ws_bytes < gpp_ws(ng, nomega)) return gw::fail(ctx, GW_EINVAL, "workspace too small");
+  int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+  std::vector<double> kv((size_t)ng * 3);
+  for (int a = 0; a < ng; ++a) {
+    double k2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = std::min(lo[d], gvec_chi[3 * a + d]);
+      hi[d] = std::max(hi[d], gvec_chi[3 * a + d]);
+      double x = 0.0;
+      for (int e = 0; e < 3; ++e) x += (gvec_chi[3 * a + e] + q[e]) * bvec[3 * e + d];
+      kv[3 * a + d] = x;
+      k2 += x * x;
+    }
+    if (!(k2 > 0.0) || !std::isfinite(k2)) return gw::fail(ctx, GW_EINVAL, "q + G = 0 or not finite");
+  }
+  for (int d = 0; d < 3; ++d)
+    if (hi[d] - lo[d] > rho_half) return gw::fail(ctx, GW_EINVAL, "density box does not cover every G - G'");
+  for (int i = 0; i < nomega; ++i)
+    if (!std::isfinite(omega[i])) return gw::fail(ctx, GW_EINVAL, "non-finite frequency");
+  char* ws = (char*)workspace;
+  double* d_k = (double*)ws;
+  int32_t* d_g = (int32_t*)(ws + ((size_t)ng * 3 * sizeof(double) + 255) / 256 * 256);
+  double* d_w = (double*)((char*)d_g + ((size_t)ng * 3 * sizeof(int32_t) + 255) / 256 * 256);
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(ctx->device);
+  hipError_t e = hipMemcpyAsync(d_k, kv.data(), kv.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_g, gvec_chi, (size_t)ng * 3 * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess && nomega > 0)
+    e = hipMemcpyAsync(d_w, omega, (size_t)nomega * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = gw::launch_gpp(eps_inv_static, ng, d_k, d_g, rho, rho_half, d_w, nomega, eta, modes, eps_inv_omega,
+                       ctx->stream);
+  // the host arrays are staged before the copies return; the kernel reads the device copies
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  (void)hipSetDevice(prev);
+  if (e != hipSuccess) return gw::fail(ctx, GW_EDEVICE, std::string("plasmon-pole launch: ") + hipGetErrorString(e));
   return GW_OK;
 }
 
