@@ -205,6 +205,15 @@ gw_status gw_chi0_backward(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob,
                            double* grad_e_v, double* grad_e_col, double* grad_n_col, void* grad_coef_v,
                            void* grad_coef_c);
 
+/* Adjoint of gw_chi0_build_ksum: as gw_chi0_backward, except that grad_chi0 is one set of
+ * nomega ng x ng blocks (the layout of the k-summed output), read by every problem.  The
+ * gradients are per problem (concatenated like gw_chi0_backward's): a problem's e_v and
+ * coef_v rows are the states at k'' = k + q - G0, so the caller adds them into those. */
+gw_status gw_chi0_backward_ksum(gw_ctx* ctx, const gw_chi0_problem* probs, int nk, int nomega, const double* omega,
+                                double delta, gw_precision prec, void* workspace, size_t ws_bytes,
+                                const void* grad_chi0, double* grad_e_v, double* grad_e_col, double* grad_n_col,
+                                void* grad_coef_v, void* grad_coef_c);
+
 /* Graph mode (enable != 0): gw_chi0_build captures its launch sequence into a HIP
  * graph the first time it sees a given argument signature (problem records, frequency
  * values, delta, precision, workspace and output pointers) and replays the graph on

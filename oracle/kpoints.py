@@ -70,3 +70,27 @@ def chi0_ksum(coef_v: Sequence[np.ndarray], e_v: Sequence[np.ndarray], coef_c: S
             mw = m * w[:, :, None]
             out[iw] += np.einsum("vcg,vch->gh", mw, np.conj(m))
     return out
+
+
+def grad_chi0_ksum_energies(coef_v: Sequence[np.ndarray], e_v: Sequence[np.ndarray], coef_c: Sequence[np.ndarray],
+                            e_c: Sequence[np.ndarray], gw: Sequence[np.ndarray], kpts: np.ndarray, q: Sequence[float],
+                            gvec_chi: np.ndarray, chibar: np.ndarray, omegas: Sequence[float] = (0.0,),
+                            delta: float = 0.0):
+    """Per k-point term of the sum: (dL/dE_v of the states at k + q, dL/dE_c at k) for a real
+    loss with chibar = dL/dRe chi0 + i dL/dIm chi0 of the summed chi0.  A term's valence
+    gradient belongs to k'' = k + q - G0; adding the terms with the same k'' gives dL/dE_{v,k''}."""
+    from .grad import grad_weights_dynamic
+    idx, g0 = kq_map(kpts, q)
+    gv, gcl = [], []
+    for k in range(len(kpts)):
+        kk = idx[k]
+        m = pair_density_kq(coef_v[kk], gw[kk], coef_c[k], gw[k], g0[k], gvec_chi)
+        x = e_v[kk][:, None] - e_c[k][None, :]
+        gx = np.zeros_like(x)
+        for iw, om in enumerate(omegas):
+            s = np.einsum("vcg,gh,vch->vc", np.conj(m), chibar[iw], m)
+            dwdx, _ = grad_weights_dynamic(x, np.ones_like(x), om, delta)
+            gx += np.real(np.conj(s) * dwdx)
+        gv.append(gx.sum(1))
+        gcl.append(-gx.sum(0))
+    return gv, gcl

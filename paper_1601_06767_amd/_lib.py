@@ -55,6 +55,8 @@ _sig("gw_chi0_build", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int
                                 C.c_size_t, vp])
 _sig("gw_chi0_backward", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, dp, C.c_double, C.c_int,
                                    vp, C.c_size_t, vp, vp, vp, vp, vp, vp])
+_sig("gw_chi0_backward_ksum", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, dp, C.c_double, C.c_int,
+                                   vp, C.c_size_t, vp, vp, vp, vp, vp, vp])
 _sig("gw_pair_density_workspace_size", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, C.c_int,
                                                  C.POINTER(C.c_size_t)])
 _sig("gw_pair_density", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
@@ -87,7 +89,7 @@ _sig("gw_ctx_stage_times", C.c_int, [vp, dp, C.POINTER(C.c_longlong), C.c_int])
 STAGES = ["band", "planes", "finish", "weights", "contract", "finalize", "eps_inv", "backward"]
 
 EXPORTED = ["gw_ctx_set_timing", "gw_ctx_stage_times", "gw_ctx_set_graph", "gw_tune", "gw_tune_get", "gw_tune_set", "gw_ctx_set_overlap", "gw_group_windows_edges",
-            "gw_sigma_coh_workspace_size", "gw_sigma_coh_static", "gw_chi0_build_ksum", "gw_kq_map",
+            "gw_sigma_coh_workspace_size", "gw_sigma_coh_static", "gw_chi0_build_ksum", "gw_chi0_backward_ksum", "gw_kq_map",
             "gw_gpp_workspace_size", "gw_gpp_eps_inv",
             "gw_version", "gw_ctx_create", "gw_ctx_destroy", "gw_last_error", "gw_geom_create", "gw_geom_destroy",
             "gw_chi0_workspace_size", "gw_chi0_build", "gw_chi0_backward", "gw_pair_density_workspace_size", "gw_pair_density",
@@ -299,10 +301,10 @@ def gw_kq_map(kpts: np.ndarray, q, tol: float = 1e-8):
 
 
 def gw_chi0_backward(ctx, problems, omegas: Sequence[float], delta: float, prec: int, grad_chi0, workspace=None,
-                     want=(True, True, True), coef=(False, False)):
+                     want=(True, True, True), coef=(False, False), ksum: bool = False):
     """(dL/dE_v, dL/dE_col, dL/dn_col[, dL/dcoef_v, dL/dcoef_c]) over all problems
     (concatenated tensors, None where not wanted) from grad_chi0 in gw_chi0_build's output
-    layout.  The coefficient gradients (float64 mode) are complex128, shaped like the
+    layout (with ksum: gw_chi0_build_ksum's single block, shared by every problem).  The coefficient gradients (float64 mode) are complex128, shaped like the
     concatenated coefficient rows (sum of nv x npw, sum of nband x npw) and returned only
     when one of them is asked for."""
     import torch
@@ -320,9 +322,9 @@ def gw_chi0_backward(ctx, problems, omegas: Sequence[float], delta: float, prec:
         rows = (sum(p.nv * n for p, n in zip(arr, npw)), sum(p.nband * n for p, n in zip(arr, npw)))
         gcoef = [torch.empty(r, dtype=torch.complex128, device=dev) if w else None for r, w in zip(rows, coef)]
     gc = grad_chi0.contiguous()
-    _check(lib.gw_chi0_backward(ctx, arr, len(arr), len(om), om.ctypes.data_as(dp), float(delta), prec,
-                                _ptr(workspace), workspace.numel(), _ptr(gc), _ptr(g[0]), _ptr(g[1]), _ptr(g[2]),
-                                _ptr(gcoef[0]), _ptr(gcoef[1])), ctx)
+    fn = lib.gw_chi0_backward_ksum if ksum else lib.gw_chi0_backward
+    _check(fn(ctx, arr, len(arr), len(om), om.ctypes.data_as(dp), float(delta), prec, _ptr(workspace),
+              workspace.numel(), _ptr(gc), _ptr(g[0]), _ptr(g[1]), _ptr(g[2]), _ptr(gcoef[0]), _ptr(gcoef[1])), ctx)
     if any(coef):
         return tuple(g) + tuple(gcoef)
     return tuple(g)

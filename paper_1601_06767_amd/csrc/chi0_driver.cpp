@@ -510,11 +510,20 @@ gw_status gw_ctx_set_graph(gw_ctx* ctx, int enable) {
   return GW_OK;
 }
 
-gw_status gw_chi0_backward(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, const double* omega,
-                           double delta, gw_precision prec, void* workspace, size_t ws_bytes, const void* grad_chi0,
-                           double* grad_e_v, double* grad_e_col, double* grad_n_col, void* grad_coef_v,
-                           void* grad_coef_c) {
+}  // extern "C"
+
+namespace {
+// ksum: the problems are the k-points of one chi0 (gw_chi0_build_ksum), so every problem
+// reads the same grad_chi0 block
+gw_status backward_entry(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, const double* omega,
+                         double delta, gw_precision prec, void* workspace, size_t ws_bytes, const void* grad_chi0,
+                         double* grad_e_v, double* grad_e_col, double* grad_n_col, void* grad_coef_v,
+                         void* grad_coef_c, bool ksum) {
   if (!ctx) return GW_EINVAL;
+  if (ksum)
+    for (int i = 1; i < nprob; ++i)
+      if (probs && probs[i].geom && probs[0].geom && probs[i].geom->g.ng != probs[0].geom->g.ng)
+        return gw::fail(ctx, GW_EINVAL, "a k-point sum needs the same dielectric-sphere size in every problem");
   gw_status st = check_common(ctx, probs, nprob, nomega, omega, delta, prec);
   if (st != GW_OK) return st;
   if (!grad_chi0 || !workspace) return gw::fail(ctx, GW_EINVAL, "NULL workspace or gradient");
@@ -575,13 +584,32 @@ gw_status gw_chi0_backward(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob,
                                               ws + L.off_scr, gcv + (size_t)s0 * g.npw, ctx->stream));
       }
     }
-    gin += (size_t)nomega * g.ng * g.ng * sizeof(double2);
+    if (!ksum) gin += (size_t)nomega * g.ng * g.ng * sizeof(double2);
     off_ev += p.nv;
     off_ec += p.ncol;
     off_cv += (size_t)p.nv * g.npw;
     off_cc += (size_t)p.nband * g.npw;
   }
   return GW_OK;
+}
+}  // namespace
+
+extern "C" {
+
+gw_status gw_chi0_backward(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, const double* omega,
+                           double delta, gw_precision prec, void* workspace, size_t ws_bytes, const void* grad_chi0,
+                           double* grad_e_v, double* grad_e_col, double* grad_n_col, void* grad_coef_v,
+                           void* grad_coef_c) {
+  return backward_entry(ctx, probs, nprob, nomega, omega, delta, prec, workspace, ws_bytes, grad_chi0, grad_e_v,
+                        grad_e_col, grad_n_col, grad_coef_v, grad_coef_c, false);
+}
+
+gw_status gw_chi0_backward_ksum(gw_ctx* ctx, const gw_chi0_problem* probs, int nk, int nomega, const double* omega,
+                                double delta, gw_precision prec, void* workspace, size_t ws_bytes,
+                                const void* grad_chi0, double* grad_e_v, double* grad_e_col, double* grad_n_col,
+                                void* grad_coef_v, void* grad_coef_c) {
+  return backward_entry(ctx, probs, nk, nomega, omega, delta, prec, workspace, ws_bytes, grad_chi0, grad_e_v,
+                        grad_e_col, grad_n_col, grad_coef_v, grad_coef_c, true);
 }
 
 gw_status gw_pair_density_workspace_size(gw_ctx* ctx, const gw_chi0_problem* prob, int nvs, int ncs,

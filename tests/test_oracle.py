@@ -579,3 +579,36 @@ def test_gpp_unscreened_element_keeps_its_static_value():
     om2, wt2 = oracle.gpp_modes(z, t["gc"], (0.01, 0, 0), b, rho, rho0)
     e = oracle.gpp_eps_inv(om2, wt2, [0.0, 0.2, 1.0], 1e-3)
     assert np.all(e[:, 3, 3] == 1.0) and np.all(np.isfinite(e))
+
+
+def test_chi0_ksum_energy_gradients_match_finite_differences():
+    kp = synth.kpoint_grid(2)
+    q = (0.5, 0.0, 0.0)
+    b = synth.make_kbands(6, kp, 2.2, nv=2, nc=4)
+    gc = synth.chi_sphere(19, q, np.eye(3) * 7.0)
+    om, d = (0.0, 0.4), 0.05
+    r = np.random.default_rng(9)
+    gbar = r.standard_normal((2, 19, 19)) + 1j * r.standard_normal((2, 19, 19))
+
+    def loss(ev, ec):
+        chi = oracle.chi0_ksum(b.coef_v, ev, b.coef_c, ec, b.gw, kp, q, gc, om, d)
+        return float(np.real(np.sum(np.conj(gbar) * chi)))
+
+    gv, gcl = oracle.grad_chi0_ksum_energies(b.coef_v, b.e_v, b.coef_c, b.e_c, b.gw, kp, q, gc, gbar, om, d)
+    idx, _ = oracle.kq_map(kp, q)
+    h = 1e-5
+    for kk, i in ((0, 0), (3, 1), (6, 1)):            # valence energy of state i at k-point kk
+        plus = [e.copy() for e in b.e_v]
+        minus = [e.copy() for e in b.e_v]
+        plus[kk][i] += h
+        minus[kk][i] -= h
+        fd = (loss(plus, b.e_c) - loss(minus, b.e_c)) / (2 * h)
+        an = sum(gv[k][i] for k in range(len(kp)) if idx[k] == kk)
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (kk, i, fd, an)
+    for k, j in ((1, 0), (5, 3)):                     # conduction energy j at k-point k
+        plus = [e.copy() for e in b.e_c]
+        minus = [e.copy() for e in b.e_c]
+        plus[k][j] += h
+        minus[k][j] -= h
+        fd = (loss(b.e_v, plus) - loss(b.e_v, minus)) / (2 * h)
+        assert abs(fd - gcl[k][j]) <= 1e-6 * max(1.0, abs(gcl[k][j])), (k, j, fd, gcl[k][j])
