@@ -79,3 +79,22 @@ def test_ksum_of_one_problem_is_the_build(g):
         g.p.gw_chi0_build_ksum(g.ctx, [probs[0], bad], len(gc), [0.0], 0.0, g.p.GW_FP64)
     for gm in list(geoms.values()) + [other]:
         g.p.gw_geom_destroy(gm)
+
+
+@pytest.mark.parametrize("omegas,delta", [((0.0,), 0.0), ((0.0, 6.0), 0.1)], ids=["static", "dynamic"])
+def test_ksum_backward_matches_oracle(g, omegas, delta):
+    q = (0.5, 0.0, 0.0)
+    kp, b, gc, probs, geoms = ksum_case(g, 2, q, 59)
+    om = np.asarray(omegas) / EV
+    r = np.random.default_rng(8)
+    gbar = r.standard_normal((len(om), len(gc), len(gc))) + 1j * r.standard_normal((len(om), len(gc), len(gc)))
+    gev, gec, _ = g.p.gw_chi0_backward(g.ctx, probs, om, delta / EV, g.p.GW_FP64,
+                                       g.torch.from_numpy(gbar).to(g.dev), ksum=True)
+    g.torch.cuda.synchronize()
+    gv, gcl = oracle.grad_chi0_ksum_energies(b.coef_v, b.e_v, b.coef_c, b.e_c, b.gw, kp, q, gc, gbar, om, delta / EV)
+    want_v, want_c = np.concatenate(gv), np.concatenate(gcl)
+    got_v, got_c = gev.cpu().numpy(), gec.cpu().numpy()
+    assert np.abs(got_v - want_v).max() <= 1e-10 * np.abs(want_v).max()
+    assert np.abs(got_c - want_c).max() <= 1e-10 * np.abs(want_c).max()
+    for gm in geoms.values():
+        g.p.gw_geom_destroy(gm)
