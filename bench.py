@@ -90,13 +90,14 @@ def main():
     ap.add_argument("--inputs-cache", default=None,
                     help="npz file for the generated inputs: loaded if present, written otherwise")
     ap.add_argument("--workload", default="static",
-                    choices=["static", "batched", "grouped", "adjoint", "grouping-study"],
+                    choices=["static", "batched", "grouped", "adjoint", "grouping-study", "extensions"],
                     help="static: the 72^3 / 128x4000 / NG 2000 build (default); batched: 8 q-points x 16 "
                          "frequencies, 128x6000 bands, NG 800..3000, one persistent launch per chunk; grouped: "
                          "96^3, 256 x 16000 bands grouped above 30 eV into 1 eV windows, NG 4000, with eps^-1; "
                          "adjoint: 128^3, 512 x 25000 bands grouped the same way, NG 8000, build + eps^-1 + "
                          "their adjoints down to the energy gradients; grouping-study: the 96^3 spectrum summed "
-                         "exactly and grouped on several energy grids (accuracy and time against the exact sum)")
+                         "exactly and grouped on several energy grids (accuracy and time against the exact sum); "
+                         "extensions: the k-point sum, the static COH self-energy and the plasmon-pole eps^-1(w)")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run every conduction chunk's contraction on the context's stream (no second stream)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -121,6 +122,9 @@ def main():
         return
     if args.workload == "grouping-study":
         run_grouping_study(args, torch, synth, p, dev)
+        return
+    if args.workload == "extensions":
+        run_extensions(args, torch, synth, p, dev)
         return
     cfg = synth.config(1)
     nd = cfg.nd
@@ -599,6 +603,111 @@ def run_grouping_study(args, torch, synth, p, dev):
     print(json.dumps({"metric": METRIC, "workload": "grouping-study-" + cfg.name, "dtype": mode,
                       "data": "synthetic", "grid": nd, "nv": cfg.nv, "nc": cfg.nc, "ng": ng, "e0_ev": cfg.e0_ev,
                       "rows": rows}))
+
+
+def run_extensions(args, torch, synth, p, dev):
+    """Throughput of the paths beside the band sum, each on inputs shaped like the 72^3 /
+    NG 2000 workload: (1) the k-point sum of Eq. (chi0) on a 2x2x2 grid (q = (1/2, 0, 0), 128
+    valence x 500 conduction bands per k: 512,000 pairs as in the static workload), (2) the
+    static COH self-energy of 8 band-edge states over 128 + 4,000 bands, (3) the plasmon-pole
+    eps^-1(w) at NG 8000 for 16 frequencies (reads eps^-1(0) once, writes every frequency)."""
+    ctx = p.gw_ctx_create(0)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    mode = [m for m in args.modes.split(",") if m][0]
+    prec = p.PRECISIONS[mode]
+    out = {}
+
+    def timed(fn, reps=None):
+        reps = reps or max(1, args.steps)
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - a) / reps, r
+
+    # (1) k-point sum
+    cfg = synth.config(1)
+    kp = synth.kpoint_grid(2)
+    q = (0.5, 0.0, 0.0)
+    t0 = time.time()
+    kb = synth.make_kbands(11, kp, cfg.nd / 4.0, 128, 500)
+    gc = synth.chi_sphere(cfg.ng[0], q, cfg.cell)
+    idx, g0 = p.gw_kq_map(kp, q)
+    # valence rows relabelled to k + q (entry g holds c_{v,k''}(g + G0)): one geometry and
+    # the dielectric sphere's own width
+    u = np.unique(np.concatenate(list(kb.gw) + [kb.gw[idx[k]] - g0[k] for k in range(len(kp))]), axis=0)
+    u = np.ascontiguousarray(u[np.lexsort((u[:, 2], u[:, 1], u[:, 0], (u * u).sum(1)))].astype(np.int32))
+    pos = {tuple(x): i for i, x in enumerate(u.tolist())}
+
+    def embed(rows, gw):
+        e = np.zeros((rows.shape[0], len(u)), dtype=np.complex128)
+        e[:, [pos[tuple(x)] for x in gw.tolist()]] = rows
+        return e
+    geoms = {(): p.gw_geom_create(ctx, (cfg.nd,) * 3, u, gc)}
+    probs = []
+    for k in range(len(kp)):
+        kk = idx[k]
+        probs.append(p.make_problem(geoms[()], t(embed(kb.coef_v[kk], kb.gw[kk] - g0[k])), t(kb.e_v[kk]),
+                                    t(embed(kb.coef_c[k], kb.gw[k])), t(kb.e_c[k])))
+    log(f"k-point inputs: {len(kp)} k, union sphere {len(u)}, NG {len(gc)}, ready in {time.time() - t0:.1f}s")
+    ws = torch.empty(p.gw_chi0_workspace_size(ctx, probs, 1, prec), dtype=torch.uint8, device=dev)
+    chi = torch.empty((1, len(gc), len(gc)), dtype=torch.complex128, device=dev)
+    dt, _ = timed(lambda: p.gw_chi0_build_ksum(ctx, probs, len(gc), [0.0], 0.0, prec, workspace=ws, out=chi))
+    k = 2 * int(np.abs(gc).max()) + 1
+    npair = 128 * 500 * len(kp)
+    fl = flops_model(cfg.nd, k, len(gc), npair, len(kp) * 628, with_inverse=False)
+    out["ksum"] = {"k_points": len(kp), "pairs": npair, "ng": len(gc), "seconds": dt,
+                   "tflops": fl["total"] / dt / 1e12, "band_pairs_per_s": npair / dt}
+    log(f"k-point sum: {dt * 1e3:.1f} ms, {out['ksum']['tflops']:.2f} TFLOP/s")
+    del ws, chi, probs
+    for gm in geoms.values():
+        p.gw_geom_destroy(gm)
+
+    # (2) static COH of 8 band-edge states over every band of the static workload
+    gw = synth.wf_sphere(cfg.nd)
+    gc0 = synth.chi_sphere(cfg.ng[0], cfg.qs[0], cfg.cell)
+    bands = synth.make_bands(cfg, gvec_wf=gw, device="cuda")
+    geom = p.gw_geom_create(ctx, (cfg.nd,) * 3, gw, gc0)
+    cv, cc = t(bands.coef_v), t(bands.coef_c)
+    ng = len(gc0)
+    prob = p.make_problem(geom, cv, t(bands.e_v), cc, t(bands.e_c))
+    chi0 = p.gw_chi0_build(ctx, [prob], [ng], [0.0], 0.0, p.GW_FP64)[0][0]
+    vc = t(synth.coulomb(gc0, cfg.qs[0], cfg.cell))
+    z = p.gw_eps_inv(ctx, vc, chi0)
+    call = torch.cat([cv, cc])
+    states = torch.cat([cv[-4:], cc[:4]]).contiguous()
+    ncols = cfg.nv + cfg.nc
+    sprob = p.make_problem(geom, states, t(np.zeros(8)), call, t(np.zeros(ncols)))
+    sws = torch.empty(p.gw_sigma_coh_workspace_size(ctx, sprob), dtype=torch.uint8, device=dev)
+    dt, _ = timed(lambda: p.gw_sigma_coh_static(ctx, sprob, vc, z, workspace=sws))
+    ngp = (ng + 127) // 128 * 128
+    gemm = 8.0 * ngp * ngp * 8 * ncols
+    out["sigma_coh_static"] = {"states": 8, "columns": ncols, "ng": ng, "seconds": dt,
+                               "gemm_tflops": gemm / dt / 1e12}
+    log(f"static COH: {dt * 1e3:.1f} ms for 8 states x {ncols} columns ({gemm / dt / 1e12:.1f} TFLOP/s of GEMM)")
+    del sws, call, cv, cc, bands
+
+    # (3) plasmon-pole eps^-1(w) at NG 8000
+    c5 = synth.config(4)
+    gc5 = synth.chi_sphere(c5.ng[0], c5.qs[0], c5.cell)
+    n5 = len(gc5)
+    rz = np.random.default_rng(5)
+    z5 = torch.eye(n5, dtype=torch.complex128, device=dev) * 0.8
+    z5 += 0.01 * torch.from_numpy(rz.standard_normal((n5, n5))).to(dev)
+    half = int((gc5.max(0) - gc5.min(0)).max())
+    box = t(synth.density_box(half, c5.cell, 2.0 * c5.nv))
+    om = np.linspace(0.0, 40.0, 16) / synth.HARTREE_EV
+    b5 = synth.recip(c5.cell)
+    dt, _ = timed(lambda: p.gw_gpp_eps_inv(ctx, gc5, c5.qs[0], b5, box, z5, om, 0.1 / synth.HARTREE_EV))
+    nbytes = 16.0 * n5 * n5 * (1 + len(om))
+    out["plasmon_pole"] = {"ng": n5, "frequencies": len(om), "seconds": dt, "bytes": nbytes,
+                           "gb_per_s": nbytes / dt / 1e9, "hbm_frac": nbytes / dt / 8e12}
+    log(f"plasmon pole: {dt * 1e3:.1f} ms at NG {n5} x {len(om)} frequencies, {nbytes / dt / 1e9:.0f} GB/s")
+    print(json.dumps({"metric": METRIC, "workload": "extensions", "dtype": mode, "data": "synthetic",
+                      "results": out}))
 
 
 if __name__ == "__main__":

@@ -166,13 +166,16 @@ gw_status gw_chi0_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, in
 /* The k-point sum of Eq. (chi0) for one q: chi0 = sum over the nk problems, one per k, all
  * with the same dielectric-sphere size; the output is one set of nomega ng x ng blocks
  * (gw_chi0_build's layout for a single problem), the problems added in order.  Problem k
- * holds, on a wavefunction sphere that contains the spheres of k and of k'' (gw_kq_map:
- * k + q = k'' + G0; coefficients outside a k-point's own sphere are zero):
- *   coef_v, e_v   the valence rows and energies at k'' (the states at k + q),
- *   coef_c, e_col the conduction columns at k,
- *   geometry      dielectric sphere entered as G + G0 (Miller indices, same order for every
- *                 k): the matrix element <v,k+q| e^{i(q+G).r} |c,k> is the pair density of
- *                 the two rows at G + G0.
+ * holds the conduction columns and energies at k (coef_c, e_col) and the valence states at
+ * k + q = k'' + G0 (gw_kq_map) with their energies E_{v,k''} (coef_v, e_v), in either form
+ * (coefficients outside a state's own sphere are zero):
+ *   relabelled   the valence row entry at Miller index g holds c_{v,k''}(g + G0), and the
+ *                dielectric sphere is G as usual: one geometry, whose wavefunction sphere
+ *                contains the spheres of every k and every k'' shifted by -G0, serves all k
+ *                and the sphere's width (and so the pair kernel's work) is unchanged;
+ *   shifted      the valence rows as stored at k'', and the problem's dielectric sphere entered
+ *                as G + G0: <v,k+q| e^{i(q+G).r} |c,k> is the pair density of the two rows at
+ *                G + G0 (a geometry per distinct G0, spheres up to one shell wider).
  * Arguments, workspace (gw_chi0_workspace_size over the nk problems), modes and errors as
  * for gw_chi0_build; GW_EINVAL if the sphere sizes differ. */
 gw_status gw_chi0_build_ksum(gw_ctx* ctx, const gw_chi0_problem* probs, int nk, int nomega, const double* omega,

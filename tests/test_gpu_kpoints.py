@@ -29,30 +29,37 @@ def embed(rows, gw, u):
     return out
 
 
-def ksum_case(g, n, q, ng, radius=5.0, nv=4, nc=12, seed=7):
+def ksum_case(g, n, q, ng, radius=5.0, nv=4, nc=12, seed=7, relabel=False):
+    """One problem per k: valence rows of k'' = k + q - G0 either relabelled to k + q (one
+    geometry, dielectric sphere G) or as stored (dielectric sphere shifted to G + G0)."""
     kp = synth.kpoint_grid(n)
     b = synth.make_kbands(seed, kp, radius, nv, nc)
     gc = synth.chi_sphere(ng, q, np.eye(3) * 8.4)
-    u = union_sphere(b.gw)
     idx, g0 = g.p.gw_kq_map(kp, q)
+    vsph = [b.gw[idx[k]] - g0[k] if relabel else b.gw[idx[k]] for k in range(len(kp))]
+    u = union_sphere(list(b.gw) + vsph)
     geoms = {}
     probs = []
     for k in range(len(kp)):
-        key = tuple(g0[k])
+        key = () if relabel else tuple(g0[k])
         if key not in geoms:
-            geoms[key] = g.p.gw_geom_create(g.ctx, (24, 24, 24), u, (gc + g0[k]).astype(np.int32))
+            sphere = gc if relabel else gc + g0[k]
+            geoms[key] = g.p.gw_geom_create(g.ctx, (24, 24, 24), u, sphere.astype(np.int32))
         kk = idx[k]
-        probs.append(g.p.make_problem(geoms[key], g.t(embed(b.coef_v[kk], b.gw[kk], u)), g.t(b.e_v[kk]),
+        probs.append(g.p.make_problem(geoms[key], g.t(embed(b.coef_v[kk], vsph[k], u)), g.t(b.e_v[kk]),
                                       g.t(embed(b.coef_c[k], b.gw[k], u)), g.t(b.e_c[k])))
     return kp, b, gc, probs, geoms
 
 
-@pytest.mark.parametrize("n,q,omegas,delta", [(2, (0.5, 0.0, 0.0), (0.0,), 0.0),
-                                              (2, (0.5, 0.5, 0.0), (0.0, 6.0), 0.1),
-                                              (3, (1 / 3, 0.0, 0.0), (0.0,), 0.0)],
-                         ids=["2cube-static", "2cube-dynamic", "3cube-27k-two-batches"])
-def test_ksum_matches_oracle(g, n, q, omegas, delta):
-    kp, b, gc, probs, geoms = ksum_case(g, n, q, 59)
+@pytest.mark.parametrize("n,q,omegas,delta,relabel", [(2, (0.5, 0.0, 0.0), (0.0,), 0.0, False),
+                                                      (2, (0.5, 0.5, 0.0), (0.0, 6.0), 0.1, False),
+                                                      (3, (1 / 3, 0.0, 0.0), (0.0,), 0.0, False),
+                                                      (2, (0.5, 0.5, 0.0), (0.0, 6.0), 0.1, True),
+                                                      (3, (1 / 3, 2 / 3, 0.0), (0.0,), 0.0, True)],
+                         ids=["2cube-static", "2cube-dynamic", "3cube-27k-two-batches", "2cube-dynamic-relabelled",
+                              "3cube-relabelled"])
+def test_ksum_matches_oracle(g, n, q, omegas, delta, relabel):
+    kp, b, gc, probs, geoms = ksum_case(g, n, q, 59, relabel=relabel)
     om = np.asarray(omegas) / EV
     got = g.p.gw_chi0_build_ksum(g.ctx, probs, len(gc), om, delta / EV, g.p.GW_FP64)
     g.torch.cuda.synchronize()
