@@ -256,15 +256,18 @@ __global__ __launch_bounds__(256) void k_zgemm(int m, int n, int kd, double2 alp
 #pragma unroll
     for (int r = 0; r < (ZK * ZT) / 256; ++r) {
       const int e = tid + 256 * r;
-      // A tile: rows r0 + (e % ZT), k = k0 + e / ZT
+      // consecutive threads walk the operand's contiguous index: k for A stored by rows (N,
+      // conj) and for B stored transposed (T, C), the row / column index otherwise
       {
-        const int kk = e / ZT, rr = e % ZT;
+        const bool along_k = opa == kOpN || opa == kOpConj;
+        const int kk = along_k ? e % ZK : e / ZT, rr = along_k ? e / ZK : e % ZT;
         double2 x{0.0, 0.0};
         if (r0 + rr < m && k0 + kk < kd) x = opget(A, lda, r0 + rr, k0 + kk, opa);
         sA[kk][rr] = x;
       }
       {
-        const int kk = e / ZT, cc = e % ZT;
+        const bool along_k = opb == kOpT || opb == kOpC;
+        const int kk = along_k ? e % ZK : e / ZT, cc = along_k ? e / ZK : e % ZT;
         double2 x{0.0, 0.0};
         if (c0 + cc < n && k0 + kk < kd) x = opget(B, ldb, k0 + kk, c0 + cc, opb);
         sB[kk][cc] = x;
