@@ -224,7 +224,7 @@ gw_status gw_chi0_backward_ksum(gw_ctx* ctx, const gw_chi0_problem* probs, int n
  * Needs a context on a non-null stream.  Disabling drops the cached graphs. */
 gw_status gw_ctx_set_graph(gw_ctx* ctx, int enable);
 
-/* Launch-shape tuner: on the first conduction chunk of each problem, times the three
+/* Launch-shape tuner: on the first conduction chunk of each problem, times the five
  * forms of the pair kernel and the contraction with
  * 1..32 pair-range splits, and keeps the fastest per problem shape in the context.
  * Later gw_chi0_workspace_size / gw_chi0_build calls use the tuned shapes (query the
@@ -234,11 +234,14 @@ gw_status gw_tune(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nome
                   void* workspace, size_t ws_bytes);
 /* The tuned shapes for prob's problem shape: pair-kernel form (1, 2 = 256 threads with
  * one or two resident workgroups per CU, 3 / 4 = split-line form with 4 / 2 valence bands
- * per workgroup) and the number of pair-range splits of the contraction; both 0 if the
- * shape was not tuned. */
+ * per workgroup, 5 = lean split-line form with 2 valence bands, which keeps the stage-2
+ * items beyond one per thread in LDS; it exists where the dielectric sphere spans 17 or 19
+ * frequencies along x3 on the 72^3 grid, and in float32 also on the 96^3 grid; elsewhere
+ * form 5 runs form 1) and the number of pair-range splits of the contraction; both 0 if
+ * the shape was not tuned. */
 gw_status gw_tune_get(gw_ctx* ctx, const gw_chi0_problem* prob, gw_precision prec, int* pair_variant, int* ksplit);
 /* Sets the shapes for prob's problem shape, e.g. to restore what gw_tune_get reported in
- * an earlier process: pair_variant 0..4 (0 = automatic), ksplit 0..32 (0 = automatic);
+ * an earlier process: pair_variant 0..5 (0 = automatic), ksplit 0..32 (0 = automatic);
  * both 0 forgets the shape.  GW_EINVAL outside those ranges. */
 gw_status gw_tune_set(gw_ctx* ctx, const gw_chi0_problem* prob, gw_precision prec, int pair_variant, int ksplit);
 

@@ -782,7 +782,7 @@ gw_status gw_tune(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nome
     if (result == GW_OK)
       result = band_to_real(ctx, L, p.geom->g, (const double2*)p.coef_c, p.nband, p.col_band, 0, p.ncol, q.cc, ws,
                             ws + L.off_psic);
-    for (int minb = 1; minb <= 4 && result == GW_OK; ++minb) {
+    for (int minb = 1; minb <= gw::kPairVariants && result == GW_OK; ++minb) {
       q.minb = minb;
       float t0 = 0, t1 = 0;
       result = timed([&] { return pair_block(ctx, L, q, ws); }, &t0);   // warm-up

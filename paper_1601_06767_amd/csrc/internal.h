@@ -136,7 +136,7 @@ hipError_t launch_coh_reduce(const void* m, const void* z, int ns, int cc, int n
 // plasmon-pole extension (gpp.hip)
 hipError_t launch_gpp(const void* eps0, int ng, const double* kvec, const int32_t* gvec, const void* rho, int half,
                       const double* omega, int nomega, double eta, void* modes, void* out, hipStream_t st);
-constexpr int kPairVariants = 4;   // forms of the pair kernel a tuned shape may name
+constexpr int kPairVariants = 5;   // forms of the pair kernel a tuned shape may name
 // minb: 0 = automatic, 1 or 2 = 256-thread kernel with that many resident workgroups per CU,
 // 3 / 4 = split-line kernel with 4 / 2 valence bands per workgroup (falls back to the
 // 256-thread kernel where its LDS does not fit).

@@ -186,12 +186,21 @@ __global__ __launch_bounds__(256, MINB) void k_pair_planes(const cx<T>* __restri
 // one stage-2 item; the two partial Z halves are added in LDS.  It halves the per-lane
 // register state of the 256-thread kernel (no spills in float64); TV = 2 also halves the
 // LDS, so that two workgroups share a CU.
-template <typename T, int R, int K, int TV>
+//
+// From K = 17 on a workgroup has more stage-2 items (8 TV K) than threads (128 TV); the
+// lean form (LEAN) keeps one item per lane in registers and the accumulators of the
+// remaining items in LDS, and stages the chunks through one LDS buffer instead of two
+// (one more barrier per step), so that registers and LDS both fit two workgroups per CU.
+template <typename T, int R, int K, int TV, bool LEAN = false>
 struct SplitLds {
   static constexpr int rp = R + 1;
+  static constexpr int nbuf = LEAN ? 1 : 2;
+  static constexpr int nitem = TV * kTC * K;
+  static constexpr int nover = LEAN && nitem > 128 * TV ? nitem - 128 * TV : 0;   // items kept in LDS
   static constexpr size_t chunk = (size_t)kTC * kRows * rp;   // one radix-R chunk of the 64 conduction rows
   static constexpr size_t vchunk = (size_t)TV * kRows * rp;   // and of the 8 TV valence rows
-  static constexpr size_t bytes = (2 * 2 * (chunk + vchunk) + (size_t)TV * kTC * kRows * K) * sizeof(cx<T>);
+  static constexpr size_t bytes =
+      (nbuf * 2 * (chunk + vchunk) + (size_t)TV * kTC * kRows * K + (size_t)nover * K) * sizeof(cx<T>);
 };
 
 template <typename T, int R, int K, int TV = kTV>
@@ -199,15 +208,27 @@ constexpr bool split_fits() {
   return SplitLds<T, R, K, TV>::bytes <= 160 * 1024;
 }
 
-// Automatic form (measured per 32k-pair launch on one MI355X).  float64: the two-valence
-// split-line kernel wherever it fits (72^3 K 15: 18.7 against 31.7 ms; 96^3 K 19: 66 against
-// 102 ms; 128^3 K 25: 211 against 433 ms), since it halves the per-lane state that
-// otherwise costs the 256-thread kernel its second resident workgroup or spills.  float32:
-// the 256-thread kernel up to K = 21 (72^3: 9.0 ms, 96^3: 24.5 ms, both ahead of the split
-// forms), the four-valence split-line kernel from K = 23 on (128^3 K 25: 92 against 115 ms).
+// The lean form is built where it has items beyond one per lane, those items fit one
+// wave, and two workgroups share the LDS.
+template <typename T, int R, int K>
+constexpr bool lean_fits() {
+  using L = SplitLds<T, R, K, 2, true>;
+  return L::nover > 0 && L::nover <= 64 && 2 * L::bytes <= 160 * 1024;
+}
+
+// Automatic form (measured per 32k-pair launch on one MI355X).  float64: the lean
+// two-valence kernel where it is built (72^3 K 17: 21.0 against 35.8 ms for the plain
+// two-valence form; K 19: 23.2 against 39.7 ms), else the two-valence split-line kernel
+// wherever it fits (72^3 K 15: 18.7 against 31.7 ms; 96^3 K 19: 66 against 102 ms; 128^3
+// K 25: 211 against 433 ms), since it halves the per-lane state that otherwise costs the
+// 256-thread kernel its second resident workgroup or spills.  float32: the 256-thread
+// kernel up to K = 21 (72^3: 9.0 ms at K 15, 12.9 ms at K 17, against 14.1 for the lean
+// form; 96^3: 24.5 ms), the four-valence split-line kernel from K = 23 on (128^3 K 25: 92
+// against 115 ms).
 template <typename T, int R, int K>
 constexpr int auto_variant() {
   if constexpr (std::is_same<T, double>::value) {
+    if constexpr (lean_fits<T, R, K>()) return 5;
     if constexpr (split_fits<T, R, K, 2>()) return 4;
   } else {
     if constexpr (K >= 23 && split_fits<T, R, K, 4>()) return 3;
@@ -215,12 +236,13 @@ constexpr int auto_variant() {
   return planes_min_blocks<T, R, K>();
 }
 
-template <typename T, int ND, int R, int K, int TV>
-__global__ __launch_bounds__(128 * TV, 1) void k_pair_planes_split(const cx<T>* __restrict__ psi_v,
-                                                              const cx<T>* __restrict__ psi_c, int nvs, int ncs,
-                                                              const cx<T>* __restrict__ twk, cx<T>* __restrict__ q) {
+template <typename T, int ND, int R, int K, int TV, bool LEAN = false>
+__global__ __launch_bounds__(128 * TV, LEAN ? 2 : 1) void k_pair_planes_split(const cx<T>* __restrict__ psi_v,
+                                                                         const cx<T>* __restrict__ psi_c, int nvs,
+                                                                         int ncs, const cx<T>* __restrict__ twk,
+                                                                         cx<T>* __restrict__ q) {
   using V = cx<T>;
-  using L = SplitLds<T, R, K, TV>;
+  using L = SplitLds<T, R, K, TV, LEAN>;
   constexpr int NT = 128 * TV;           // threads
   constexpr int S = ND / R;
   constexpr int SL = (S + 1) / 2;        // chunks of the first half
@@ -230,15 +252,18 @@ __global__ __launch_bounds__(128 * TV, 1) void k_pair_planes_split(const cx<T>* 
   constexpr int RCH = (K - 1) / 2;
   constexpr int NPAIR = TV * kTC;
   constexpr int NITEM = NPAIR * K;
-  constexpr int IPL = (NITEM + NT - 1) / NT;
+  constexpr int NOV = L::nover;          // items whose accumulators live in LDS (lanes 0..NOV-1)
+  constexpr int IPL = LEAN ? 1 : (NITEM + NT - 1) / NT;   // items in registers per lane
+  static_assert(!LEAN || (NOV > 0 && NOV <= 64), "lean form: overflow items must fit the first wave");
   constexpr int CH = kTC * kRows * R;    // conduction elements of one chunk
   constexpr int CV = TV * kRows * R;     // valence elements of one chunk
   constexpr int PER = 2 * (CH + CV) / NT;
   static_assert(PER * NT == 2 * (CH + CV), "chunk elements must divide evenly");
   constexpr size_t NPL = (size_t)ND * ND;
-  __shared__ V s_c[2 * 2 * L::chunk];   // [buffer][half][row][rp]
-  __shared__ V s_v[2 * 2 * L::vchunk];
+  __shared__ V s_c[L::nbuf * 2 * L::chunk];   // [buffer][half][row][rp]
+  __shared__ V s_v[L::nbuf * 2 * L::vchunk];
   __shared__ V s_z[NPAIR * kRows * K];
+  __shared__ V s_q[NOV > 0 ? NOV * K : 1];    // [item - NT][j]
 
   const int nbc = ncs / kTC;
   const int nbv = nvs / TV;
@@ -292,6 +317,10 @@ __global__ __launch_bounds__(128 * TV, 1) void k_pair_planes_split(const cx<T>* 
   for (int r = 0; r < IPL; ++r)
 #pragma unroll
     for (int j = 0; j < K; ++j) qacc[r][j] = V{T(0), T(0)};
+  if (NOV > 0 && tid < NOV) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) s_q[tid * K + j] = V{T(0), T(0)};
+  }
 
   fetch(0);
   stash(0);
@@ -306,9 +335,10 @@ __global__ __launch_bounds__(128 * TV, 1) void k_pair_planes_split(const cx<T>* 
       const int st = b2 * SL + t;
       if (st + 1 < NSTEP) fetch(st + 1);
       const int b = hf ? SL + t : t;
+      const int buf = LEAN ? 0 : (st & 1);
       if (hf == 0 || t < SH) {
-        const V* rc = s_c + ((st & 1) * 2 + hf) * L::chunk + (cl * kRows + a2) * L::rp;
-        const V* rv = s_v + ((st & 1) * 2 + hf) * L::vchunk + (wv * kRows + a2) * L::rp;
+        const V* rc = s_c + (buf * 2 + hf) * L::chunk + (cl * kRows + a2) * L::rp;
+        const V* rv = s_v + (buf * 2 + hf) * L::vchunk + (wv * kRows + a2) * L::rp;
         V x[R];
 #pragma unroll
         for (int a = 0; a < R; ++a) x[a] = cmulc(rv[a], rc[a]);
@@ -320,7 +350,15 @@ __global__ __launch_bounds__(128 * TV, 1) void k_pair_planes_split(const cx<T>* 
           cmac(acc[j], tv, x[((n % R) + R) % R]);
         }
       }
-      if (st + 1 < NSTEP) stash((st + 1) & 1);
+      if (LEAN) {
+        // one buffer: every wave is done with it before the next chunk overwrites it
+        if (st + 1 < NSTEP) {
+          __syncthreads();
+          stash(0);
+        }
+      } else if (st + 1 < NSTEP) {
+        stash((st + 1) & 1);
+      }
       __syncthreads();
     }
     V* z = s_z + ((wv * kTC + cl) * kRows + a2) * K;
@@ -351,6 +389,23 @@ __global__ __launch_bounds__(128 * TV, 1) void k_pair_planes_split(const cx<T>* 
         }
       }
     }
+    if (NOV > 0 && tid < NOV) {
+      // the items beyond one per lane, accumulated in LDS by the lanes of the first wave
+      const int it = NT + tid;
+      const int pair = it / K, j3 = it % K;
+      V y[kRows];
+#pragma unroll
+      for (int a = 0; a < kRows; ++a) y[a] = s_z[(pair * kRows + a) * K + j3];
+      dft<kRows>(y);
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const int n = j - RCH;
+        const V tv = twk[b2 * K + j];
+        V acc = s_q[tid * K + j];
+        cmac(acc, tv, y[((n % kRows) + kRows) % kRows]);
+        s_q[tid * K + j] = acc;
+      }
+    }
     // s_z is rewritten only after the SL barriers of the next group's stage 1
   }
   const int p1 = (x1 % S) * R + x1 / S;
@@ -365,6 +420,15 @@ __global__ __launch_bounds__(128 * TV, 1) void k_pair_planes_split(const cx<T>* 
 #pragma unroll
       for (int j = 0; j < K; ++j) dst[j * K] = qacc[r][j];
     }
+  }
+  if (NOV > 0 && tid < NOV) {
+    const int it = NT + tid;
+    const int pair = it / K, j3 = it % K;
+    const int pv = pair / kTC, pc = pair % kTC;
+    const size_t pg = (size_t)(v0 + pv) * ncs + (c0 + pc);
+    V* dst = q + (pg * ND + p1) * (K * K) + j3;
+#pragma unroll
+    for (int j = 0; j < K; ++j) dst[j * K] = s_q[tid * K + j];
   }
 }
 
@@ -416,9 +480,17 @@ hipError_t run_planes(const Geom& g, const void* psi_v, const void* psi_c, int n
   const cx<T>* pv = (const cx<T>*)psi_v;
   const cx<T>* pc = (const cx<T>*)psi_c;
   // variant: 1 / 2 = 256-thread kernel with one / two resident workgroups per CU,
-  // 3 / 4 = split-line kernel with 4 / 2 valence bands per workgroup, 0 = automatic
+  // 3 / 4 = split-line kernel with 4 / 2 valence bands per workgroup, 5 = lean split-line
+  // kernel with 2 valence bands, 0 = automatic
   int variant = minb;
   if (variant == 0) variant = auto_variant<T, R, K>();
+  if constexpr (lean_fits<T, R, K>()) {
+    if (variant == 5) {
+      const int nblk = ND * (nvs / 2) * (ncs / kTC);
+      k_pair_planes_split<T, ND, R, K, 2, true><<<nblk, 256, 0, st>>>(pv, pc, nvs, ncs, tw, (cx<T>*)q);
+      return hipGetLastError();
+    }
+  }
   if constexpr (split_fits<T, R, K, 4>()) {
     if (variant == 3) {
       const int nblk = ND * (nvs / 4) * (ncs / kTC);

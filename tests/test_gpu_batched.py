@@ -99,8 +99,9 @@ def test_tuner_choices_keep_parity(g):
         assert fro <= tol and mx <= tol, (prec, fro, mx)
 
 
-@pytest.mark.parametrize("cfg,ng", [(0, None), (1, 300), (2, 2600), (4, 6500)], ids=["24cube", "72cube", "96cube",
-                                                                                  "128cube"])
+# 72^3 with NG 2600 / 3600 gives K = 17 / 19, where the lean split-line form (5) is built
+@pytest.mark.parametrize("cfg,ng", [(0, None), (1, 300), (1, 2600), (1, 3600), (2, 2600), (4, 6500)],
+                         ids=["24cube", "72cube", "72cube-K17", "72cube-K19", "96cube", "128cube"])
 def test_every_pair_kernel_form_matches_oracle(g, cfg, ng):
     # each form of the pair kernel forced through gw_tune_set, float64 and float32, on a
     # conduction count that is not a multiple of the workgroup's 8 columns
@@ -109,7 +110,7 @@ def test_every_pair_kernel_form_matches_oracle(g, cfg, ng):
     prob = g.problem(case)
     ref = ref_chi0(case, [0.0], 0.0)[0]
     for prec, tol in (("fp64", 1e-10), ("fp32", 2e-5)):
-        for form in (1, 2, 3, 4):
+        for form in (1, 2, 3, 4, 5):
             p.gw_tune_set(g.ctx, prob, p.PRECISIONS[prec], form, 0)
             assert p.gw_tune_get(g.ctx, prob, p.PRECISIONS[prec]) == (form, 0)
             chi = g.chi0(case, prec=prec)[0]
@@ -118,7 +119,7 @@ def test_every_pair_kernel_form_matches_oracle(g, cfg, ng):
         p.gw_tune_set(g.ctx, prob, p.PRECISIONS[prec], 0, 0)
         assert p.gw_tune_get(g.ctx, prob, p.PRECISIONS[prec]) == (0, 0)
     with pytest.raises(p.GwError):
-        p.gw_tune_set(g.ctx, prob, p.GW_FP64, 5, 0)
+        p.gw_tune_set(g.ctx, prob, p.GW_FP64, 6, 0)
     with pytest.raises(p.GwError):
         p.gw_tune_set(g.ctx, prob, p.GW_FP64, 1, 33)
 
