@@ -89,9 +89,11 @@ gw_status gw_ctx_stage_times(gw_ctx* ctx, double* ms, long long* counts, int res
  * stream of the context while the band and pair transforms of the next chunk run on the
  * context's stream, with events between the two and a join before the call's last
  * launches, so the call stays ordered on the context's stream.
- *   mode 0  off;  1  where it pays (default): the split-BF16x3 mode, whose contraction
- *   leaves room on each CU for a pair-transform workgroup;  2  in every mode.
- * The results do not depend on the mode (same kernels, same summation order).  With
+ *   mode 0  off;  1  where it pays (default): the split-BF16x3 mode with dielectric
+ *   spheres of at most 2048 (padded) G-vectors, whose contraction then leaves room on each
+ *   CU for a pair-transform workgroup (without overlap that contraction holds two
+ *   workgroups per CU instead, which is faster for larger spheres);  2  in every mode.
+ * The results do not depend on the mode (same arithmetic, same summation order).  With
  * timing on, the contraction's stage time is measured on the second stream and overlaps
  * the others.  GW_EINVAL for another mode. */
 gw_status gw_ctx_set_overlap(gw_ctx* ctx, int mode);

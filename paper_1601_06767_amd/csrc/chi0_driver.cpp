@@ -250,11 +250,18 @@ gw_status enqueue_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, in
   // ev_ready[b] (main) -> contraction j (side) -> ev_free[b] (side) -> transforms of
   // chunk j + 2 (main), and ev_join before the finalisation.
   // Overlap pays where the contraction leaves registers for a pair-kernel workgroup on the
-  // same CU: the split-BF16x3 form (160 VGPRs, one 512-thread workgroup per CU; measured
-  // 256 -> 229 ms per 72^3 / 512k-pair step).  The float64 and float32 contractions fill
-  // the register file, so the next chunk's transforms queue behind them (no gain measured;
-  // capping the contraction at one workgroup per CU made float64 slower, 519 -> 558 ms).
-  const bool ovl = nchunk > 1 && (ctx->overlap == 2 || (ctx->overlap == 1 && L.mode == 2));
+  // same CU and is small beside the transforms: the split-BF16x3 form at one 512-thread
+  // workgroup per CU (146 VGPRs) with dielectric spheres up to 2048 (measured 214.7 ms per
+  // 72^3 / 512k-pair / NG 2000 step, against 221.4 ms without overlap, where the contraction
+  // alone runs two workgroups per CU at 128 VGPRs).  With larger spheres the contraction
+  // alone is the faster choice (96^3 / NG 4000 grouped step: 1.599 s alone, 1.632 s
+  // overlapped).  The float64 and float32 contractions fill the register file, so the next
+  // chunk's transforms queue behind them (no gain measured; capping the contraction at one
+  // workgroup per CU made float64 slower, 519 -> 558 ms).
+  int max_ngp = 0;
+  for (const ProbPlan& q : L.pp) max_ngp = std::max(max_ngp, q.p->geom->g.ngp);
+  const bool ovl =
+      nchunk > 1 && (ctx->overlap == 2 || (ctx->overlap == 1 && L.mode == 2 && max_ngp <= 2048));
   hipStream_t cs = ovl ? ctx->side : ctx->stream;
   auto chunk = [&](int j) -> gw_status {
     const int buf = j & 1;
@@ -308,7 +315,7 @@ gw_status enqueue_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, in
     const int grid = (int)std::min<long long>(item, 256LL * 8);
     {
       gw::StageScope sc(ctx, gw::kStageContract, cs);
-      GW_HIP(ctx, gw::launch_contract_batch(L.mode, bt, counter, grid, cs));
+      GW_HIP(ctx, gw::launch_contract_batch(L.mode, bt, counter, grid, !ovl, cs));
     }
     if (ovl) GW_HIP(ctx, hipEventRecord(ctx->ev_free[buf], cs));
     return GW_OK;
@@ -824,7 +831,7 @@ gw_status gw_tune(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nome
             [&]() -> gw_status {
               GW_HIP(ctx, gw::launch_zero(ws + qk.off_acc, qk.acc_one, ctx->stream));
               GW_HIP(ctx, gw::launch_zero(counter, 256, ctx->stream));
-              GW_HIP(ctx, gw::launch_contract_batch(Lk.mode, bt, counter, grid, ctx->stream));
+              GW_HIP(ctx, gw::launch_contract_batch(Lk.mode, bt, counter, grid, true, ctx->stream));
               return GW_OK;
             },
             &t);

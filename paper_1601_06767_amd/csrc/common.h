@@ -32,12 +32,9 @@ template <typename V> __device__ __forceinline__ void cmac(V& acc, V a, V b) {
   acc.y = fma(a.y, b.x, acc.y);
 }
 
-// bfloat16 as the upper half of a float, rounded to nearest even (finite inputs)
-__device__ __forceinline__ unsigned short bf16_rne(float x) {
-  unsigned u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
+// bfloat16 as the upper half of a float: float -> bf16 bits rounded to nearest even
+// (v_cvt_pk_bf16_f32 on gfx950), and back
+__device__ __forceinline__ unsigned short bf16_rne(float x) { return __builtin_bit_cast(unsigned short, (__bf16)x); }
 __device__ __forceinline__ float bf16_val(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
 // ---------------------------------------------------------------- unit roots

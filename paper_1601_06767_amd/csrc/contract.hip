@@ -111,6 +111,13 @@ __device__ __forceinline__ void store_tile(double2* out, int ngp, int r0, int c0
 
 constexpr int KC = 16;   // pairs per LDS stage
 
+// Length of each of the ksplit pair ranges: a multiple of the 16-pair stage, so that only
+// a range's last stage can be partial and every stage starts on a multiple of 16.
+__device__ __forceinline__ int range_len(int nk, int ksplit) {
+  const int per = (nk + ksplit - 1) / ksplit;
+  return (per + 15) / 16 * 16;
+}
+
 // ---------------------------------------------------------------- f64 / f32 MFMA tile
 template <typename T, int TILE>
 __device__ void tile_mfma(const cx<T>* __restrict__ m, const double* __restrict__ w, int nk, int ngp, int ksplit,
@@ -125,7 +132,7 @@ __device__ void tile_mfma(const cx<T>* __restrict__ m, const double* __restrict_
   int ti, tj;
   tile_coords(t, &ti, &tj);
   const int g0 = ti * TILE, h0 = tj * TILE;
-  const int per = (nk + ksplit - 1) / ksplit;
+  const int per = range_len(nk, ksplit);
   const int k0 = ks * per;
   const int k1 = min(nk, k0 + per);
   const int tid = threadIdx.x;
@@ -144,12 +151,13 @@ __device__ void tile_mfma(const cx<T>* __restrict__ m, const double* __restrict_
     }
   V pa[NR], pb[NR];
   auto fetch = [&](int kk) {
+    const bool full = kk + KC <= k1;   // every stage but the last of a range
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const int e = tid + NT * r;
       const int k = e / TILE, g = e % TILE;
       V a{T(0), T(0)}, b{T(0), T(0)};
-      if (kk + k < k1) {
+      if (full || kk + k < k1) {
         const size_t row = (size_t)(kk + k) * ngp;
         a = m[row + g0 + g];
         const V bb = m[row + h0 + g];
@@ -199,7 +207,8 @@ __device__ void tile_mfma(const cx<T>* __restrict__ m, const double* __restrict_
 // even); products use hi*hi + hi*lo + lo*hi on MFMA 16x16x32 bf16 with float32
 // accumulation.  The complex Hermitian update is two real products over a doubled
 // inner index k' = [re of 16 pairs | im of 16 pairs]:
-//   Re C = [ar | ai] [br | bi]^T,   Im C = [ai | -ar] [br | bi]^T,   b = w M(G').
+//   Re C = [ar | ai] [br | bi]^T,   Im C = [ar | ai] [-bi | br]^T,   b = w M(G'),
+// so both products share the A fragments; the B rows carry a negated copy of bi.
 // MFMA 16x16x32 bf16 operands: lane l holds row l % 16, inner indices 8 (l / 16) + 0..7;
 // result rows 4 (l / 16) + r, column l % 16.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -207,7 +216,10 @@ typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 
 constexpr int BK = 16;          // pairs per MFMA step
-constexpr int BROW = 40;        // bf16 per LDS row (32 used, padded so 8 rows read together hit distinct banks)
+static_assert(BK == KC && KC == 16, "pair ranges are aligned to 16-pair stages");
+// bf16 per LDS row: [re | im] of the 16 pairs, then -im (B rows only), then padding so
+// that 8 rows read together hit distinct banks
+constexpr int BROW = 56;
 
 template <int TILE>
 __device__ void tile_bf16x3(const void* __restrict__ mv, const double* __restrict__ w, int nk, int ngp, int ksplit,
@@ -220,7 +232,7 @@ __device__ void tile_bf16x3(const void* __restrict__ mv, const double* __restric
   int ti, tj;
   tile_coords(t, &ti, &tj);
   const int g0 = ti * TILE, h0 = tj * TILE;
-  const int per = (nk + ksplit - 1) / ksplit;
+  const int per = range_len(nk, ksplit);
   const int k0 = ks * per;
   const int k1 = min(nk, k0 + per);
   const int tid = threadIdx.x;
@@ -228,7 +240,7 @@ __device__ void tile_bf16x3(const void* __restrict__ mv, const double* __restric
   const int wr = wave / G::WC, wc = wave % G::WC;
   const int li = lane & 15, lg = lane >> 4;
   // staging role: operand (A or B), row, half of the 16 pairs
-  const int op = tid / (2 * TILE);           // 0: A rows (G), 1: B rows (G')
+  const int op = __builtin_amdgcn_readfirstlane(tid / (2 * TILE));   // 0: A rows (G), 1: B rows (G'); wave-uniform
   const int srow = tid % TILE;
   const int shalf = (tid / TILE) % 2;        // pairs [8 shalf, 8 shalf + 8)
   const int gcol = (op ? h0 : g0) + srow;
@@ -243,9 +255,33 @@ __device__ void tile_bf16x3(const void* __restrict__ mv, const double* __restric
     }
   float2 pf[8];
   auto fetch = [&](int kk) {
+    const int kb = kk + 8 * shalf;
+    if (kk + BK <= k1) {   // every stage but the last of a range: no masks
+      double wk[8];
+      if (op) {
+        // kb is a multiple of 8 (stage-aligned ranges), so 16-byte loads of the weights
+#pragma unroll
+        for (int e = 0; e < 8; e += 2) {
+          const double2 w2 = *(const double2*)(w + kb + e);
+          wk[e] = w2.x;
+          wk[e + 1] = w2.y;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        float2 x = m[(size_t)(kb + e) * ngp + gcol];
+        if (op) {
+          const float sw = (float)wk[e];
+          x.x *= sw;
+          x.y *= sw;
+        }
+        pf[e] = x;
+      }
+      return;
+    }
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const int k = kk + 8 * shalf + e;
+      const int k = kb + e;
       float2 x{0.f, 0.f};
       if (k < k1) {
         x = m[(size_t)k * ngp + gcol];
@@ -259,8 +295,9 @@ __device__ void tile_bf16x3(const void* __restrict__ mv, const double* __restric
     }
   };
   if (k0 < k1) fetch(k0);
-  const int yg = (lg + 2) & 3;
-  const unsigned short neg = lg >= 2 ? 0x8000 : 0;
+  // the imaginary product's right operand [-bi | br]: lanes of groups 0, 1 read the
+  // negated copy of bi, those of groups 2, 3 read br
+  const int boff = lg < 2 ? 32 + 8 * lg : 8 * (lg - 2);
   for (int kk = k0; kk < k1; kk += BK) {
     __syncthreads();
     {
@@ -277,27 +314,30 @@ __device__ void tile_bf16x3(const void* __restrict__ mv, const double* __restric
       *(u16x8*)&s[op][0][srow][16 + 8 * shalf] = ih;
       *(u16x8*)&s[op][1][srow][8 * shalf] = rl;
       *(u16x8*)&s[op][1][srow][16 + 8 * shalf] = il;
+      if (op == 1) {
+        // bf16 negation flips the sign bit, so -hi and -lo split -bi exactly
+        typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+        const u32x4 sign = {0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+        *(u32x4*)&s[1][0][srow][32 + 8 * shalf] = __builtin_bit_cast(u32x4, ih) ^ sign;
+        *(u32x4*)&s[1][1][srow][32 + 8 * shalf] = __builtin_bit_cast(u32x4, il) ^ sign;
+      }
     }
     __syncthreads();
     if (kk + BK < k1) fetch(kk + BK);
-    bf16x8 xh[MI], xl[MI], yh[MI], yl[MI], bh[NJ], bl[NJ];
+    bf16x8 xh[MI], xl[MI], bh[NJ], bl[NJ], ch[NJ], cl[NJ];
 #pragma unroll
     for (int i = 0; i < MI; ++i) {
       const int r = 16 * MI * wr + 16 * i + li;
       xh[i] = *(const bf16x8*)&s[0][0][r][8 * lg];
       xl[i] = *(const bf16x8*)&s[0][1][r][8 * lg];
-      u16x8 uh = *(const u16x8*)&s[0][0][r][8 * yg];
-      u16x8 ul = *(const u16x8*)&s[0][1][r][8 * yg];
-      uh ^= neg;
-      ul ^= neg;
-      yh[i] = __builtin_bit_cast(bf16x8, uh);
-      yl[i] = __builtin_bit_cast(bf16x8, ul);
     }
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       const int r = 16 * NJ * wc + 16 * j + li;
       bh[j] = *(const bf16x8*)&s[1][0][r][8 * lg];
       bl[j] = *(const bf16x8*)&s[1][1][r][8 * lg];
+      ch[j] = *(const bf16x8*)&s[1][0][r][boff];
+      cl[j] = *(const bf16x8*)&s[1][1][r][boff];
     }
 #pragma unroll
     for (int i = 0; i < MI; ++i)
@@ -306,9 +346,9 @@ __device__ void tile_bf16x3(const void* __restrict__ mv, const double* __restric
         cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[i], bh[j], cre[i][j], 0, 0, 0);
         cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[i], bl[j], cre[i][j], 0, 0, 0);
         cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl[i], bh[j], cre[i][j], 0, 0, 0);
-        cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yh[i], bh[j], cim[i][j], 0, 0, 0);
-        cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yh[i], bl[j], cim[i][j], 0, 0, 0);
-        cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yl[i], bh[j], cim[i][j], 0, 0, 0);
+        cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[i], ch[j], cim[i][j], 0, 0, 0);
+        cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[i], cl[j], cim[i][j], 0, 0, 0);
+        cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl[i], ch[j], cim[i][j], 0, 0, 0);
       }
   }
   store_tile<MI, NJ>(acc + (size_t)ks * ngp * ngp, ngp, g0 + 16 * MI * wr, h0 + 16 * NJ * wc, cre, cim, li, lg, false);
@@ -337,10 +377,13 @@ __global__ __launch_bounds__(64 * TileGeo<TILE>::NW) void k_contract(const void*
 
 // Persistent grid over all items of a batch; items of problem b occupy
 // [item0[b], item0[b+1]) and decode as (job, split, tile), job = w_index * nparts + part,
-// tile fastest (pair-range major, as above).
-template <int MODE, int TILE>
-__global__ __launch_bounds__(64 * TileGeo<TILE>::NW) void k_contract_batch(ContractBatch bt,
-                                                                           int* __restrict__ counter) {
+// tile fastest (pair-range major, as above).  MINW = waves per SIMD the registers must
+// allow: 4 holds two 512-thread split-bf16 workgroups per CU (128 registers), used when
+// the contraction has the CUs to itself; 1 leaves registers for the pair kernels that run
+// beside it on the other stream.
+template <int MODE, int TILE, int MINW = 1>
+__global__ __launch_bounds__(64 * TileGeo<TILE>::NW, MINW) void k_contract_batch(ContractBatch bt,
+                                                                                 int* __restrict__ counter) {
   __shared__ int s_item;
   for (;;) {
     __syncthreads();
@@ -444,12 +487,14 @@ hipError_t contract_grid(int mode, const void* m, const double* w, int nk, int n
 }
 
 template <int TILE>
-hipError_t contract_batch(int mode, const ContractBatch& bt, int* counter, int grid, hipStream_t st) {
+hipError_t contract_batch(int mode, const ContractBatch& bt, int* counter, int grid, bool alone, hipStream_t st) {
   constexpr int NT = 64 * TileGeo<TILE>::NW;
   if (mode == 0)
     k_contract_batch<0, TILE><<<grid, NT, 0, st>>>(bt, counter);
   else if (mode == 1)
     k_contract_batch<1, TILE><<<grid, NT, 0, st>>>(bt, counter);
+  else if (alone)
+    k_contract_batch<2, TILE, 4><<<grid, NT, 0, st>>>(bt, counter);
   else
     k_contract_batch<2, TILE><<<grid, NT, 0, st>>>(bt, counter);
   return hipGetLastError();
@@ -463,11 +508,12 @@ hipError_t launch_contract(int mode, const void* m, const double* w, int nk, int
                                    : contract_grid<128>(mode, m, w, nk, ngp, ksplit, acc, st);
 }
 
-hipError_t launch_contract_batch(int mode, const ContractBatch& bt, int* counter, int grid, hipStream_t st) {
+hipError_t launch_contract_batch(int mode, const ContractBatch& bt, int* counter, int grid, bool alone,
+                                 hipStream_t st) {
   for (int b = 0; b < bt.nprob; ++b)
     if (bt.p[b].ngp % contract_tile(mode) != 0) return hipErrorInvalidValue;
-  return contract_tile(mode) == 64 ? contract_batch<64>(mode, bt, counter, grid, st)
-                                   : contract_batch<128>(mode, bt, counter, grid, st);
+  return contract_tile(mode) == 64 ? contract_batch<64>(mode, bt, counter, grid, alone, st)
+                                   : contract_batch<128>(mode, bt, counter, grid, alone, st);
 }
 
 hipError_t launch_finalize(const double2* accA, const double2* accB, int ksplit, int ng, int ngp, double2* chi,

@@ -192,7 +192,10 @@ struct ContractBatch {
   long long item0[kMaxBatch + 1];
   ContractProb p[kMaxBatch];
 };
-hipError_t launch_contract_batch(int mode, const ContractBatch& bt, int* counter, int grid, hipStream_t st);
+// alone: no other kernel shares the CUs (no chunk overlap): the split-bf16 form then holds
+// two workgroups per CU.
+hipError_t launch_contract_batch(int mode, const ContractBatch& bt, int* counter, int grid, bool alone,
+                                 hipStream_t st);
 // chi[G][G'] = sum_ks accA + i sum_ks accB (Hermitian parts mirrored), for G, G' < ng.
 hipError_t launch_finalize(const double2* accA, const double2* accB, int ksplit, int ng, int ngp, double2* chi,
                            bool accumulate, hipStream_t st);

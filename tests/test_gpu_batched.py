@@ -124,6 +124,25 @@ def test_every_pair_kernel_form_matches_oracle(g, cfg, ng):
         p.gw_tune_set(g.ctx, prob, p.GW_FP64, 1, 33)
 
 
+@pytest.mark.parametrize("om,d", [((0.0,), 0.0), ((0.0, 7.0), 0.1)], ids=["static", "dynamic"])
+def test_contraction_splits_keep_parity(g, om, d):
+    # the pair range of each contraction tile split 1..32 ways (ranges are whole 16-pair
+    # stages, so the larger splits leave empty ranges), in every precision
+    p = g.p
+    case = make_case(0, nv=6, nc=21)
+    prob = g.problem(case)
+    om = np.asarray(om) / EV
+    ref = ref_chi0(case, om, d / EV)
+    for prec, tol in (("fp64", 1e-10), ("fp32", 2e-5), ("bf16x3", 1e-4)):
+        for ks in (1, 3, 7, 32):
+            p.gw_tune_set(g.ctx, prob, p.PRECISIONS[prec], 0, ks)
+            chi = g.chi0(case, om, d / EV, prec)
+            for i in range(len(om)):
+                fro, mx = rel_err(chi[i], ref[i])
+                assert fro <= tol and mx <= tol, (prec, ks, i, fro, mx)
+        p.gw_tune_set(g.ctx, prob, p.PRECISIONS[prec], 0, 0)
+
+
 def _build(g, ctx, probs, ngs, om, d, prec, ws):
     p = g.p
     out = p.gw_chi0_build(ctx, probs, ngs, om, d, p.PRECISIONS[prec], workspace=ws)
