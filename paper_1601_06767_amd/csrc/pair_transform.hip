@@ -208,12 +208,12 @@ constexpr bool split_fits() {
   return SplitLds<T, R, K, TV>::bytes <= 160 * 1024;
 }
 
-// The lean form is built where it has items beyond one per lane, those items fit one
-// wave, and two workgroups share the LDS.
+// The lean form is built where it has items beyond one per lane (at most one more per
+// lane) and two workgroups share the LDS.
 template <typename T, int R, int K>
 constexpr bool lean_fits() {
   using L = SplitLds<T, R, K, 2, true>;
-  return L::nover > 0 && L::nover <= 64 && 2 * L::bytes <= 160 * 1024;
+  return L::nover > 0 && L::nover <= 256 && 2 * L::bytes <= 160 * 1024;
 }
 
 // Automatic form (measured per 32k-pair launch on one MI355X).  float64: the lean
@@ -223,14 +223,16 @@ constexpr bool lean_fits() {
 // K 25: 211 against 433 ms), since it halves the per-lane state that otherwise costs the
 // 256-thread kernel its second resident workgroup or spills.  float32: the 256-thread
 // kernel up to K = 21 (72^3: 9.0 ms at K 15, 12.9 ms at K 17, against 14.1 for the lean
-// form; 96^3: 24.5 ms), the four-valence split-line kernel from K = 23 on (128^3 K 25: 92
-// against 115 ms).
+// form; 96^3: 24.5 ms), from K = 23 on the lean kernel (128^3 K 25: 79.1 ms, against 92.2
+// for the four-valence split-line kernel and 113.6 for the 256-thread one), else the
+// four-valence split-line kernel.
 template <typename T, int R, int K>
 constexpr int auto_variant() {
   if constexpr (std::is_same<T, double>::value) {
     if constexpr (lean_fits<T, R, K>()) return 5;
     if constexpr (split_fits<T, R, K, 2>()) return 4;
   } else {
+    if constexpr (K >= 23 && lean_fits<T, R, K>()) return 5;
     if constexpr (K >= 23 && split_fits<T, R, K, 4>()) return 3;
   }
   return planes_min_blocks<T, R, K>();
@@ -254,7 +256,7 @@ __global__ __launch_bounds__(128 * TV, LEAN ? 2 : 1) void k_pair_planes_split(co
   constexpr int NITEM = NPAIR * K;
   constexpr int NOV = L::nover;          // items whose accumulators live in LDS (lanes 0..NOV-1)
   constexpr int IPL = LEAN ? 1 : (NITEM + NT - 1) / NT;   // items in registers per lane
-  static_assert(!LEAN || (NOV > 0 && NOV <= 64), "lean form: overflow items must fit the first wave");
+  static_assert(!LEAN || (NOV > 0 && NOV <= NT), "lean form: at most one item per lane beyond the first");
   constexpr int CH = kTC * kRows * R;    // conduction elements of one chunk
   constexpr int CV = TV * kRows * R;     // valence elements of one chunk
   constexpr int PER = 2 * (CH + CV) / NT;
@@ -390,7 +392,7 @@ __global__ __launch_bounds__(128 * TV, LEAN ? 2 : 1) void k_pair_planes_split(co
       }
     }
     if (NOV > 0 && tid < NOV) {
-      // the items beyond one per lane, accumulated in LDS by the lanes of the first wave
+      // the items beyond one per lane, accumulated in LDS by the first NOV lanes
       const int it = NT + tid;
       const int pair = it / K, j3 = it % K;
       V y[kRows];
