@@ -85,7 +85,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--modes", default="fp64,fp32")
     ap.add_argument("--cpu-sample", type=int, default=16, help="valence bands in the oracle sample (0 = skip)")
-    ap.add_argument("--cpu-cols", type=int, default=320)
+    ap.add_argument("--cpu-cols", type=int, default=800)
     ap.add_argument("--tune", action="store_true", help="run the launch-shape tuner before timing each mode")
     ap.add_argument("--inputs-cache", default=None,
                     help="npz file for the generated inputs: loaded if present, written otherwise")
