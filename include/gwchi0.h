@@ -204,7 +204,9 @@ gw_status gw_chi0_build_ksum(gw_ctx* ctx, const gw_chi0_problem* probs, int nk, 
  * element: mbar_p = sum_w [conj(w_p) chibar m_p + w_p chibar^H m_p], h_p = F^H mbar_p on
  * the grid (F the transform of Eq. (chi0) including 1/N), dL/du_c = sum_v h_vc u_v,
  * dL/du_v = sum_c conj(h_vc) u_c, then the transpose of the band transform.  Every
- * reduction is float64 in a fixed order. */
+ * reduction is float64 in a fixed order.  The product chibar m_p runs in the precision's
+ * arithmetic: float64, float32, or split-bf16 x3 with float32 accumulation (chibar rounded
+ * to float32 first). */
 gw_status gw_chi0_backward(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, const double* omega,
                            double delta, gw_precision prec, void* workspace, size_t ws_bytes, const void* grad_chi0,
                            double* grad_e_v, double* grad_e_col, double* grad_n_col, void* grad_coef_v,

@@ -9,6 +9,7 @@
 // k_adjoint: Y = M chibar^T on MFMA (64 pairs x 64 G per workgroup, inner G'), fused
 // with the row dot sum_G conj(M[p][G]) Y[p][G] over the tile's 64 G; the per-tile
 // partial sums are reduced in float64 in fixed order by k_adjoint_pairs.
+// k_adjoint_bf16x3: the same product for the split-bf16 mode on bf16 MFMA, 128 x 128 tiles.
 #include <algorithm>
 #include <type_traits>
 
@@ -143,6 +144,186 @@ __global__ __launch_bounds__(256) void k_adjoint(const cx<T>* __restrict__ m, in
   }
 }
 
+// ---------------------------------------------------------------- split-bf16 x3 form
+// M (float) and chibar (rounded to float) are each split into hi = bf16(x) and
+// lo = bf16(x - hi); products hi*hi + hi*lo + lo*hi on MFMA 16x16x32 bf16 with float32
+// accumulation.  Over the doubled inner index k' = [re of 16 G' | im of 16 G']:
+//   Re Y = [mr | mi] [br | -bi]^T,   Im Y = [mr | mi] [bi | br]^T,   b = chibar[G][G'],
+// so both products share the M fragments; the chibar rows in LDS hold [br | bi | -bi].
+// 128 pairs x 128 G per workgroup, 8 waves on a 2 x 4 grid, each 64 pairs x 32 G.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int BT = 128;     // pairs and G per tile
+constexpr int BKS = 16;     // G' per stage
+constexpr int BROWA = 56;   // bf16 per LDS row: 48 used, padded so 8 rows read together hit distinct banks
+constexpr int BMI = 4, BNJ = 2;
+
+// One workgroup per CU (162 registers): capped at 128 registers for a second one, it
+// spills and runs slower (measured 9.4 against 5.4 ms per 32k-pair launch at NG 2000; the
+// float32 kernel takes 9.2 ms).
+__global__ __launch_bounds__(512) void k_adjoint_bf16x3(const float2* __restrict__ m, int npair, int ng, int ngp,
+                                                           const double2* __restrict__ gbar,
+                                                           double2* __restrict__ part) {
+  __shared__ __align__(16) unsigned short s[2][2][BT][BROWA];   // [M | chibar][hi | lo][row][k']
+  __shared__ double2 sred[4][BT];
+  const int ntg = ngp / BT;
+  const int p0 = (blockIdx.x / ntg) * BT;
+  const int tg = blockIdx.x % ntg;
+  const int q0 = tg * BT;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = wave / 4, wc = wave % 4;
+  const int li = lane & 15, lg = lane >> 4;
+  // staging role: operand (M rows or chibar rows, wave-uniform); each thread takes the two
+  // G' 2 kp, 2 kp + 1 of rows rg + 32 rr (rr = 0..3), so that 8 lanes read 16 consecutive G'
+  // of a row (16-byte loads along the contiguous index)
+  const int op = __builtin_amdgcn_readfirstlane(tid / (2 * BT));
+  const int kp = tid % 8;
+  const int rg = (tid % (2 * BT)) / 8;
+  const int nrow = op == 0 ? npair - p0 : ng - q0;   // valid rows of this operand's tile
+  const size_t ld = op == 0 ? (size_t)ngp : (size_t)ng;
+  const size_t base0 = op == 0 ? (size_t)p0 * ngp : (size_t)q0 * ng;
+
+  f32x4 cre[BMI][BNJ], cim[BMI][BNJ];
+#pragma unroll
+  for (int i = 0; i < BMI; ++i)
+#pragma unroll
+    for (int j = 0; j < BNJ; ++j) {
+      cre[i][j] = f32x4{0, 0, 0, 0};
+      cim[i][j] = f32x4{0, 0, 0, 0};
+    }
+  float2 pf[4][2];
+  auto fetch = [&](int k0) {
+    const int k = k0 + 2 * kp;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int row = rg + 32 * rr;
+      float2 x0{0.f, 0.f}, x1{0.f, 0.f};
+      if (row < nrow && k < ng) {
+        const size_t at = base0 + (size_t)row * ld + k;
+        if (op == 0) {
+          if (k + 1 < ng) {
+            // k even and ngp even: 16-byte aligned
+            const float4 v = *(const float4*)(m + at);
+            x0 = float2{v.x, v.y};
+            x1 = float2{v.z, v.w};
+          } else {
+            x0 = m[at];
+          }
+        } else {
+          const double2 d0 = gbar[at];
+          x0 = float2{(float)d0.x, (float)d0.y};
+          if (k + 1 < ng) {
+            const double2 d1 = gbar[at + 1];
+            x1 = float2{(float)d1.x, (float)d1.y};
+          }
+        }
+      }
+      pf[rr][0] = x0;
+      pf[rr][1] = x1;
+    }
+  };
+  fetch(0);
+  const int re_off = lg < 2 ? 8 * lg : 32 + 8 * (lg - 2);   // [br | -bi]
+  const int im_off = lg < 2 ? 16 + 8 * lg : 8 * (lg - 2);   // [bi | br]
+  for (int k0 = 0; k0 < ng; k0 += BKS) {
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      // two consecutive G' as one 32-bit word (the lower G' in the low half)
+      unsigned rh = 0, rl = 0, ih = 0, il = 0;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const unsigned short a = bf16_rne(pf[rr][e].x), b = bf16_rne(pf[rr][e].y);
+        rh |= (unsigned)a << (16 * e);
+        ih |= (unsigned)b << (16 * e);
+        rl |= (unsigned)bf16_rne(pf[rr][e].x - bf16_val(a)) << (16 * e);
+        il |= (unsigned)bf16_rne(pf[rr][e].y - bf16_val(b)) << (16 * e);
+      }
+      const int row = rg + 32 * rr;
+      *(unsigned*)&s[op][0][row][2 * kp] = rh;
+      *(unsigned*)&s[op][0][row][16 + 2 * kp] = ih;
+      *(unsigned*)&s[op][1][row][2 * kp] = rl;
+      *(unsigned*)&s[op][1][row][16 + 2 * kp] = il;
+      if (op == 1) {
+        // flipping the sign bits of hi and lo splits -bi exactly
+        *(unsigned*)&s[1][0][row][32 + 2 * kp] = ih ^ 0x80008000u;
+        *(unsigned*)&s[1][1][row][32 + 2 * kp] = il ^ 0x80008000u;
+      }
+    }
+    __syncthreads();
+    if (k0 + BKS < ng) fetch(k0 + BKS);
+    bf16x8 xh[BMI], xl[BMI], reh[BNJ], rel[BNJ], imh[BNJ], iml[BNJ];
+#pragma unroll
+    for (int i = 0; i < BMI; ++i) {
+      const int r = 16 * BMI * wr + 16 * i + li;
+      xh[i] = *(const bf16x8*)&s[0][0][r][8 * lg];
+      xl[i] = *(const bf16x8*)&s[0][1][r][8 * lg];
+    }
+#pragma unroll
+    for (int j = 0; j < BNJ; ++j) {
+      const int r = 16 * BNJ * wc + 16 * j + li;
+      reh[j] = *(const bf16x8*)&s[1][0][r][re_off];
+      rel[j] = *(const bf16x8*)&s[1][1][r][re_off];
+      imh[j] = *(const bf16x8*)&s[1][0][r][im_off];
+      iml[j] = *(const bf16x8*)&s[1][1][r][im_off];
+    }
+#pragma unroll
+    for (int i = 0; i < BMI; ++i)
+#pragma unroll
+      for (int j = 0; j < BNJ; ++j) {
+        cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[i], reh[j], cre[i][j], 0, 0, 0);
+        cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[i], rel[j], cre[i][j], 0, 0, 0);
+        cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl[i], reh[j], cre[i][j], 0, 0, 0);
+        cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[i], imh[j], cim[i][j], 0, 0, 0);
+        cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[i], iml[j], cim[i][j], 0, 0, 0);
+        cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl[i], imh[j], cim[i][j], 0, 0, 0);
+      }
+  }
+  // epilogue: per pair row, sum over this tile's G of conj(M[p][G]) Y[p][G]; result rows of
+  // the bf16 16x16x32 MFMA are 4 (lane / 16) + r, columns lane % 16
+  // (one block row i at a time, to keep few registers live beside the accumulators)
+#pragma unroll
+  for (int i = 0; i < BMI; ++i) {
+    double2 rs[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) rs[r] = double2{0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < BNJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int pr = 16 * BMI * wr + 16 * i + 4 * lg + r;
+        const int gc = q0 + 16 * BNJ * wc + 16 * j + li;
+        if (p0 + pr < npair && gc < ng) {
+          const float2 mv = m[(size_t)(p0 + pr) * ngp + gc];
+          const double yr = (double)cre[i][j][r], yi = (double)cim[i][j][r];
+          rs[r].x += (double)mv.x * yr + (double)mv.y * yi;
+          rs[r].y += (double)mv.x * yi - (double)mv.y * yr;
+        }
+      }
+    // sum over the 16 lanes li of a row (xor shuffles within the 16-lane group)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int o = 8; o >= 1; o >>= 1) {
+        rs[r].x += __shfl_xor(rs[r].x, o, 64);
+        rs[r].y += __shfl_xor(rs[r].y, o, 64);
+      }
+    if (li == 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sred[wc][16 * BMI * wr + 16 * i + 4 * lg + r] = rs[r];
+    }
+  }
+  __syncthreads();
+  if (tid < BT && p0 + tid < npair) {
+    double2 a = sred[0][tid];
+#pragma unroll
+    for (int c = 1; c < 4; ++c) {
+      a.x += sred[c][tid].x;
+      a.y += sred[c][tid].y;
+    }
+    part[(size_t)(p0 + tid) * ntg + tg] = a;
+  }
+}
+
 // Per pair: s = sum over G tiles (fixed order), then dL/dx and dL/dn accumulated over w.
 __global__ void k_adjoint_pairs(const double2* __restrict__ part, int ntg, const double* __restrict__ e_v, int nv,
                                 int nvs, const double* __restrict__ e_col, const double* __restrict__ n_col, int c0,
@@ -210,6 +391,17 @@ hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t st) {
 
 size_t adjoint_partial_bytes(int npair, int ngp) { return (size_t)npair * (ngp / AT) * sizeof(double2); }
 
+int adjoint_tile(int mode) { return mode == 2 ? BT : AT; }
+
+hipError_t launch_adjoint_bf16x3(const void* m, int npair, int ng, int ngp, const double2* gbar, double2* part,
+                                 hipStream_t st) {
+  if (ngp % BT != 0) return hipErrorInvalidValue;
+  const int ntg = ngp / BT;
+  const int nb = ((npair + BT - 1) / BT) * ntg;
+  k_adjoint_bf16x3<<<nb, 512, 0, st>>>((const float2*)m, npair, ng, ngp, gbar, part);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_adjoint(const void* m, int npair, int ng, int ngp, const double2* gbar, double2* part,
                           hipStream_t st) {
@@ -221,12 +413,12 @@ hipError_t launch_adjoint(const void* m, int npair, int ng, int ngp, const doubl
 template hipError_t launch_adjoint<double>(const void*, int, int, int, const double2*, double2*, hipStream_t);
 template hipError_t launch_adjoint<float>(const void*, int, int, int, const double2*, double2*, hipStream_t);
 
-hipError_t launch_adjoint_pairs(const double2* part, int ngp, const double* e_v, int nv, int nvs, const double* e_col,
+hipError_t launch_adjoint_pairs(const double2* part, int ntg, const double* e_v, int nv, int nvs, const double* e_col,
                                 const double* n_col, int c0, int ncol, int cc, double omega, double delta, double* dx,
                                 double* dn, hipStream_t st) {
   const int np = nvs * cc;
-  k_adjoint_pairs<<<(np + 255) / 256, 256, 0, st>>>(part, ngp / AT, e_v, nv, nvs, e_col, n_col, c0, ncol, cc, omega,
-                                                     delta, dx, dn);
+  k_adjoint_pairs<<<(np + 255) / 256, 256, 0, st>>>(part, ntg, e_v, nv, nvs, e_col, n_col, c0, ncol, cc, omega, delta,
+                                                     dx, dn);
   return hipGetLastError();
 }
 

@@ -571,11 +571,13 @@ gw_status backward_entry(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, i
       GW_HIP(ctx, gw::launch_fill_f64(dn, q.npair, 0.0, ctx->stream));
       for (int iw = 0; iw < nomega; ++iw) {
         const double2* gb = (const double2*)gin + (size_t)iw * g.ng * g.ng;
-        hipError_t e = L.fp64 ? gw::launch_adjoint<double>(ws + q.off_m, q.npair, g.ng, g.ngp, gb, part, ctx->stream)
-                              : gw::launch_adjoint<float>(ws + q.off_m, q.npair, g.ng, g.ngp, gb, part, ctx->stream);
+        hipError_t e =
+            L.fp64        ? gw::launch_adjoint<double>(ws + q.off_m, q.npair, g.ng, g.ngp, gb, part, ctx->stream)
+            : L.mode == 2 ? gw::launch_adjoint_bf16x3(ws + q.off_m, q.npair, g.ng, g.ngp, gb, part, ctx->stream)
+                          : gw::launch_adjoint<float>(ws + q.off_m, q.npair, g.ng, g.ngp, gb, part, ctx->stream);
         GW_HIP(ctx, e);
-        GW_HIP(ctx, gw::launch_adjoint_pairs(part, g.ngp, p.e_v, p.nv, q.nvs, p.e_col, p.n_col, c0, p.ncol, q.cc,
-                                             omega[iw], delta, dx, dn, ctx->stream));
+        GW_HIP(ctx, gw::launch_adjoint_pairs(part, g.ngp / gw::adjoint_tile(L.mode), p.e_v, p.nv, q.nvs, p.e_col,
+                                             p.n_col, c0, p.ncol, q.cc, omega[iw], delta, dx, dn, ctx->stream));
       }
       GW_HIP(ctx, gw::launch_adjoint_reduce(dx, dn, p.nv, q.cc, c0, p.ncol, gev, gec, gn, ctx->stream));
       if (want_coef) {

@@ -241,11 +241,16 @@ hipError_t launch_eps_inv_backward(int n, const double* v, const double2* z, con
 hipError_t launch_flag_clear(int* flag, hipStream_t st);
 
 // ---------------------------------------------------------------- adjoint
-size_t adjoint_partial_bytes(int npair, int ngp);
+size_t adjoint_partial_bytes(int npair, int ngp);   // enough for every tile width
+int adjoint_tile(int mode);                          // G per partial sum in this mode (64 or 128)
 template <typename T>
 hipError_t launch_adjoint(const void* m, int npair, int ng, int ngp, const double2* gbar, double2* part,
                           hipStream_t st);
-hipError_t launch_adjoint_pairs(const double2* part, int ngp, const double* e_v, int nv, int nvs, const double* e_col,
+// split-bf16 x3 form over float pair densities (ngp a multiple of 128)
+hipError_t launch_adjoint_bf16x3(const void* m, int npair, int ng, int ngp, const double2* gbar, double2* part,
+                                 hipStream_t st);
+// ntg = ngp / adjoint_tile(mode) partial sums per pair
+hipError_t launch_adjoint_pairs(const double2* part, int ntg, const double* e_v, int nv, int nvs, const double* e_col,
                                 const double* n_col, int c0, int ncol, int cc, double omega, double delta, double* dx,
                                 double* dn, hipStream_t st);
 hipError_t launch_adjoint_reduce(const double* dx, const double* dn, int nv, int cc, int c0, int ncol, double* g_ev,

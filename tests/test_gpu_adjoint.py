@@ -64,6 +64,25 @@ def test_backward_fp32_and_bf16x3_modes(g):
             assert close(a, b, 1e-5), prec
 
 
+@pytest.mark.parametrize("cfg,nv,nc,ng", [(0, 6, 21, None), (1, 8, 40, 300)], ids=["24cube", "72cube"])
+def test_backward_mixed_modes_dynamic(g, cfg, nv, nc, ng):
+    # frequencies with broadening and grouped columns, in float32 and on the split-bf16
+    # adjoint kernel (128 x 128 tiles: the 72^3 sphere of 300 G spans three G tiles with a
+    # ragged last one)
+    case = make_case(cfg, nv=nv, nc=nc, ng=ng)
+    r = np.random.default_rng(8)
+    case.col_band = np.concatenate([np.arange(nc), r.integers(0, nc, nc // 3)]).astype(np.int32)
+    case.e_col = case.e_c[case.col_band] + r.uniform(0.0, 0.02, len(case.col_band))
+    case.n_col = r.uniform(1.0, 4.0, len(case.col_band))
+    om = np.array([0.0, 0.3, 9.0]) / EV
+    gbar = rand_gbar(len(case.gc), len(om), 9)
+    want = ref_backward(case, gbar, om, 0.1 / EV)
+    for prec in ("fp32", "bf16x3"):
+        got = gpu_backward(g, case, gbar, om, 0.1 / EV, prec)
+        for a, b in zip(got, want):
+            assert close(a, b, 1e-5), prec
+
+
 def _loss_gpu(g, geom, tensors, e_v, e_col, n_col, v, head, prec="fp64"):
     import paper_1601_06767_amd.autograd as A
     chi = A.chi0(g.ctx, geom, tensors[0], e_v, tensors[1], e_col, n_col, prec=prec)[0]
