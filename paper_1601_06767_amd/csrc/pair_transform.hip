@@ -80,29 +80,40 @@ __global__ __launch_bounds__(256, MINB) void k_pair_planes(const cx<T>* __restri
   const int a2 = lane % kRows;        // row within the x2 group
 
   // chunk staging: element e of step s (x2 group s / S, x3 group b = s % S); conduction
-  // rows first, then valence rows
+  // rows first, then valence rows.  Whether element i is a conduction or a valence one
+  // changes only at multiples of 64 (wave-uniform), so a step's source is a wave-uniform
+  // base plus this lane's fixed byte offset, and its LDS slot is fixed.
+  static_assert(CH % 64 == 0, "element kinds change at wave boundaries");
+  const int wave = __builtin_amdgcn_readfirstlane(wv);
   const V* pc_base = psi_c + ((size_t)c0 * ND + x1) * NPL;
   const V* pv_base = psi_v + ((size_t)v0 * ND + x1) * NPL;
+  unsigned voff[PER];   // bytes from the row set's base at g2 = 0, b = 0
+  int slot[PER];        // element of s_c / s_v in buffer 0
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + 256 * i;
+    const int e2 = e < CH ? e : e - CH;
+    const int row = e2 / R, a = e2 % R;
+    voff[i] = (unsigned)(((size_t)(row / kRows) * ND * NPL + (size_t)(row % kRows) * ND + a) * sizeof(V));
+    slot[i] = row * L::rp + a;
+  }
   V pf[PER];
   auto fetch = [&](int st) {
     const int g2 = st / S, b = st % S;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int e = tid + 256 * i;
-      const int e2 = e < CH ? e : e - CH;
-      const int row = e2 / R, a = e2 % R;
-      const V* base = e < CH ? pc_base : pv_base;
-      pf[i] = base[(size_t)(row / kRows) * ND * NPL + (size_t)(g2 * kRows + row % kRows) * ND + b * R + a];
+      const bool isc = wave * 64 + 256 * i < CH;
+      const char* sb = (const char*)(isc ? pc_base : pv_base) + ((size_t)g2 * kRows * ND + (size_t)b * R) * sizeof(V);
+      pf[i] = *(const V*)(sb + voff[i]);
     }
   };
   auto stash = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int e = tid + 256 * i;
-      if (e < CH)
-        s_c[buf * L::chunk + (e / R) * L::rp + e % R] = pf[i];
+      if (wave * 64 + 256 * i < CH)
+        s_c[buf * L::chunk + slot[i]] = pf[i];
       else
-        s_v[buf * L::vchunk + ((e - CH) / R) * L::rp + (e - CH) % R] = pf[i];
+        s_v[buf * L::vchunk + slot[i]] = pf[i];
     }
   };
 
@@ -219,20 +230,18 @@ constexpr bool lean_fits() {
 // Automatic form (measured per 32k-pair launch on one MI355X).  float64: the lean
 // two-valence kernel where it is built (72^3 K 17: 21.0 against 35.8 ms for the plain
 // two-valence form; K 19: 23.2 against 39.7 ms), else the two-valence split-line kernel
-// wherever it fits (72^3 K 15: 18.7 against 31.7 ms; 96^3 K 19: 66 against 102 ms; 128^3
-// K 25: 211 against 433 ms), since it halves the per-lane state that otherwise costs the
+// wherever it fits (72^3 K 15: 17.7 against 31.5 ms; 96^3 K 19: 68 against 101 ms; 128^3
+// K 25: 176 against 402 ms), since it halves the per-lane state that otherwise costs the
 // 256-thread kernel its second resident workgroup or spills.  float32: the 256-thread
-// kernel up to K = 21 (72^3: 9.0 ms at K 15, 12.9 ms at K 17, against 14.1 for the lean
-// form; 96^3: 24.5 ms), from K = 23 on the lean kernel (128^3 K 25: 79.1 ms, against 92.2
-// for the four-valence split-line kernel and 113.6 for the 256-thread one), else the
-// four-valence split-line kernel.
+// kernel up to K = 21 (72^3: 8.7 ms at K 15, 12.9 ms at K 17, against 14.1 for the lean
+// form; 96^3 K 19: 22.9 ms), the four-valence split-line kernel from K = 23 on (128^3 K
+// 25: 74.2 ms, against 77.1 for the lean form and 114 for the 256-thread one).
 template <typename T, int R, int K>
 constexpr int auto_variant() {
   if constexpr (std::is_same<T, double>::value) {
     if constexpr (lean_fits<T, R, K>()) return 5;
     if constexpr (split_fits<T, R, K, 2>()) return 4;
   } else {
-    if constexpr (K >= 23 && lean_fits<T, R, K>()) return 5;
     if constexpr (K >= 23 && split_fits<T, R, K, 4>()) return 3;
   }
   return planes_min_blocks<T, R, K>();
@@ -283,34 +292,49 @@ __global__ __launch_bounds__(128 * TV, LEAN ? 2 : 1) void k_pair_planes_split(co
   const int cl = lane / kRows;
   const int a2 = lane % kRows;
 
-  // element e of a step: half h = e / (CH + CV), then conduction rows, then valence rows
+  // element e of a step: half h = e / (CH + CV), then conduction rows, then valence rows.
+  // The kind of element i (half, conduction or valence) changes only at multiples of 64,
+  // so it is wave-uniform: a step's source is a wave-uniform base plus this lane's fixed
+  // byte offset (no per-step index arithmetic), and its LDS slot is fixed too.
+  static_assert(CH % 64 == 0 && CV % 64 == 0 && NT % 64 == 0, "element kinds change at wave boundaries");
   const V* pc_base = psi_c + ((size_t)c0 * ND + x1) * NPL;
   const V* pv_base = psi_v + ((size_t)v0 * ND + x1) * NPL;
+  unsigned voff[PER];   // bytes from the row set's base at g2 = 0, b = 0
+  int slot[PER];        // element of s_c / s_v in buffer 0
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + NT * i;
+    const int h = e / (CH + CV), e1 = e % (CH + CV);
+    const int e2 = e1 < CH ? e1 : e1 - CH;
+    const int row = e2 / R, a = e2 % R;
+    voff[i] = (unsigned)(((size_t)(row / kRows) * ND * NPL + (size_t)(row % kRows) * ND + a) * sizeof(V));
+    slot[i] = h * (e1 < CH ? (int)L::chunk : (int)L::vchunk) + row * L::rp + a;
+  }
   V pf[PER];
   auto fetch = [&](int st) {
     const int g2 = st / SL, t = st % SL;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int e = tid + NT * i;
-      const int h = e / (CH + CV), e1 = e % (CH + CV);
-      const int e2 = e1 < CH ? e1 : e1 - CH;
-      const int row = e2 / R, a = e2 % R;
+      const int ew = wave * 64 + NT * i;   // the wave's first element
+      const int h = ew / (CH + CV);
+      const bool isc = ew % (CH + CV) < CH;
       const int b = h ? SL + t : t;
-      const V* base = e1 < CH ? pc_base : pv_base;
       V x{T(0), T(0)};
-      if (b < S) x = base[(size_t)(row / kRows) * ND * NPL + (size_t)(g2 * kRows + row % kRows) * ND + b * R + a];
+      if (b < S) {
+        const char* sb = (const char*)(isc ? pc_base : pv_base) + ((size_t)g2 * kRows * ND + (size_t)b * R) * sizeof(V);
+        x = *(const V*)(sb + voff[i]);
+      }
       pf[i] = x;
     }
   };
   auto stash = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int e = tid + NT * i;
-      const int h = e / (CH + CV), e1 = e % (CH + CV);
-      if (e1 < CH)
-        s_c[(buf * 2 + h) * L::chunk + (e1 / R) * L::rp + e1 % R] = pf[i];
+      const int ew = wave * 64 + NT * i;
+      if (ew % (CH + CV) < CH)
+        s_c[buf * 2 * L::chunk + slot[i]] = pf[i];
       else
-        s_v[(buf * 2 + h) * L::vchunk + ((e1 - CH) / R) * L::rp + (e1 - CH) % R] = pf[i];
+        s_v[buf * 2 * L::vchunk + slot[i]] = pf[i];
     }
   };
 
