@@ -228,20 +228,23 @@ constexpr bool lean_fits() {
 }
 
 // Automatic form (measured per 32k-pair launch on one MI355X).  float64: the lean
-// two-valence kernel where it is built (72^3 K 17: 21.0 against 35.8 ms for the plain
-// two-valence form; K 19: 23.2 against 39.7 ms), else the two-valence split-line kernel
+// two-valence kernel where it is built (72^3 K 17: 19.9 against 34.3 ms for the plain
+// two-valence form; K 19: 21.2 against 36.5 ms), else the two-valence split-line kernel
 // wherever it fits (72^3 K 15: 17.7 against 31.5 ms; 96^3 K 19: 68 against 101 ms; 128^3
 // K 25: 176 against 402 ms), since it halves the per-lane state that otherwise costs the
-// 256-thread kernel its second resident workgroup or spills.  float32: the 256-thread
-// kernel up to K = 21 (72^3: 8.7 ms at K 15, 12.9 ms at K 17, against 14.1 for the lean
-// form; 96^3 K 19: 22.9 ms), the four-valence split-line kernel from K = 23 on (128^3 K
-// 25: 74.2 ms, against 77.1 for the lean form and 114 for the 256-thread one).
+// 256-thread kernel its second resident workgroup or spills.  float32: on radix-8 grids
+// the lean kernel where it is built (72^3 K 17: 10.7 against 12.9 ms for the 256-thread
+// one; K 19: 12.1 against 13.6 ms), else the 256-thread kernel up to K = 21 (72^3 K 15:
+// 8.7 ms; 96^3 K 17: 21.7 against 26.4 for the lean form; K 19: 22.9), and the
+// four-valence split-line kernel from K = 23 on (128^3 K 25: 74.2 ms, against 77.1 for
+// the lean form and 114 for the 256-thread one).
 template <typename T, int R, int K>
 constexpr int auto_variant() {
   if constexpr (std::is_same<T, double>::value) {
     if constexpr (lean_fits<T, R, K>()) return 5;
     if constexpr (split_fits<T, R, K, 2>()) return 4;
   } else {
+    if constexpr (R <= 8 && lean_fits<T, R, K>()) return 5;
     if constexpr (K >= 23 && split_fits<T, R, K, 4>()) return 3;
   }
   return planes_min_blocks<T, R, K>();
