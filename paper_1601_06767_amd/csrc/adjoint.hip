@@ -159,7 +159,8 @@ constexpr int BMI = 4, BNJ = 2;
 
 // One workgroup per CU (162 registers): capped at 128 registers for a second one, it
 // spills and runs slower (measured 9.4 against 5.4 ms per 32k-pair launch at NG 2000; the
-// float32 kernel takes 9.2 ms).
+// float32 kernel takes 9.2 ms).  Stages of 32 G' (two blocks of 16 between barriers) were
+// no faster (5.6 ms).
 __global__ __launch_bounds__(512) void k_adjoint_bf16x3(const float2* __restrict__ m, int npair, int ng, int ngp,
                                                            const double2* __restrict__ gbar,
                                                            double2* __restrict__ part) {

@@ -69,8 +69,8 @@ class Config:
 
 
 _Q0 = (0.01, 0.0, 0.0)
-_C4_QS = [_Q0, (0.5, 0, 0), (0, 0.5, 0), (0, 0, 0.5), (0.5, 0.5, 0), (0.5, 0, 0.5), (0, 0.5, 0.5), (0.5, 0.5, 0.5)]
-_C4_NG = [800, 1114, 1429, 1743, 2057, 2371, 2686, 3000]
+_BATCHED_QS = [_Q0, (0.5, 0, 0), (0, 0.5, 0), (0, 0, 0.5), (0.5, 0.5, 0), (0.5, 0, 0.5), (0, 0.5, 0.5), (0.5, 0.5, 0.5)]
+_BATCHED_NG = [800, 1114, 1429, 1743, 2057, 2371, 2686, 3000]
 
 
 def _a_for_atoms(atoms: int) -> float:
@@ -78,13 +78,13 @@ def _a_for_atoms(atoms: int) -> float:
     return 8.4 * (atoms / 8.0) ** (1.0 / 3.0)
 
 
-CONFIGS = [
+WORKLOADS = [
     Config(0, "static-24^3-16x240-ng259-fp64", 24, 16, 240, [259], 8.4, [_Q0], [0.0], 0.0, None, 1.0, 60.0, "fp64"),
     Config(1, "mgo64-static-72^3-128x4000-ng2000", 72, 128, 4000, [2000], _a_for_atoms(64), [_Q0], [0.0], 0.0,
            None, 1.0, 60.0, "fp64+fp32"),
     Config(2, "mgo128-grouped-96^3-256x16000-ng4000", 96, 256, 16000, [4000], _a_for_atoms(128), [_Q0], [0.0], 0.0,
            30.0, 1.0, 60.0, "bf16x3"),
-    Config(3, "batched-8q-16w-72^3-128x6000", 72, 128, 6000, list(_C4_NG), _a_for_atoms(64), list(_C4_QS),
+    Config(3, "batched-8q-16w-72^3-128x6000", 72, 128, 6000, list(_BATCHED_NG), _a_for_atoms(64), list(_BATCHED_QS),
            [40.0 * j / 15.0 for j in range(16)], 0.1, None, 1.0, 60.0, "fp32"),
     Config(4, "mgo256-grouped-128^3-512x25000-ng8000", 128, 512, 25000, [8000], _a_for_atoms(256), [_Q0], [0.0],
            0.0, 30.0, 1.0, 60.0, "bf16x3"),
@@ -92,7 +92,7 @@ CONFIGS = [
 
 
 def config(i: int) -> Config:
-    return dataclasses.replace(CONFIGS[i])
+    return dataclasses.replace(WORKLOADS[i])
 
 
 # --------------------------------------------------------------------------------------

@@ -133,7 +133,7 @@ def test_chi0_dynamic_fp64(g):
 
 
 def test_chi0_grouped_fp64(g):
-    # C1 spectrum [5, 60] eV grouped above E_0 = 30 eV in 1 eV windows (count weights)
+    # the 24^3 workload's spectrum [5, 60] eV grouped above E_0 = 30 eV in 1 eV windows (count weights)
     case = make_case(0, nv=16, nc=240)
     e0, de, nwin = 30.0 / EV, 1.0 / EV, 30
     col, e_col, n_col, n0 = g.p.gw_group_windows(case.e_c, e0, de, nwin)
