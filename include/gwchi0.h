@@ -111,7 +111,10 @@ gw_status gw_ctx_set_overlap(gw_ctx* ctx, int mode);
  * 2 max|n_wf,i| + max|n_chi,i| < N_i per axis, which makes the grid evaluation of
  * M_vc(G) equal to the plane-wave convolution sum_G' conj(c_v(G'+G)) c_c(G')
  * (reading of Eq. (chi0)'s matrix element, whose exponent is printed without ".r").
- * The geometry keeps its own device copies of the index tables. */
+ * Every grid that meets the bound gives the same chi0 up to rounding, so the smallest
+ * supported one is the cheapest (the 72^3 workload's spheres, 2 x 18 + 7 = 43, are exact on
+ * 48^3).  A sphere whose pair-kernel instance (grid, 2 max|n_chi| + 1) is not built gives
+ * GW_EUNSUPPORTED.  The geometry keeps its own device copies of the index tables. */
 gw_status gw_geom_create(gw_ctx* ctx, const int n_fft[3], int npw, const int32_t* gvec_wf, int ng,
                          const int32_t* gvec_chi, gw_geom** out);
 gw_status gw_geom_destroy(gw_geom* geom);

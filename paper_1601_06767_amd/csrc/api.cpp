@@ -31,7 +31,7 @@ bool line_split(int nd, LineSplit* out) {
   switch (nd) {
     case 24: *out = {8, 3}; return true;
     case 32: *out = {8, 4}; return true;
-    case 48: *out = {16, 3}; return true;
+    case 48: *out = {8, 6}; return true;
     case 64: *out = {16, 4}; return true;
     case 72: *out = {8, 9}; return true;
     case 96: *out = {16, 6}; return true;
@@ -164,6 +164,9 @@ gw_status gw_geom_create(gw_ctx* ctx, const int n_fft[3], int npw, const int32_t
   g.ngp = (int)round_up(ng, gw::kTile);
   g.line = ls;
   if (g.W > 2 * 64 + 1) return gw::fail(ctx, GW_EUNSUPPORTED, "wavefunction sphere too wide");
+  // the pair kernels read the planes in the band transform's split order: same radix
+  if (gw::pair_supported(nd, g.K) && gw::pair_radix(nd, g.K) != ls.R)
+    return gw::fail(ctx, GW_EUNSUPPORTED, "pair kernel radix differs from the band transform's split");
   if (!gw::pair_supported(nd, g.K))
     return gw::fail(ctx, GW_EUNSUPPORTED,
                 "no pair kernel for N = " + std::to_string(nd) + ", K = " + std::to_string(g.K) +

@@ -147,12 +147,14 @@ hipError_t launch_pair_planes(const Geom& g, const void* psi_v, const void* psi_
 template <typename T>
 hipError_t launch_pair_finish(const Geom& g, const void* q, int npair, void* m, hipStream_t st);
 bool pair_supported(int nd, int K);
+int pair_radix(int nd, int K);   // line radix R of the (nd, K) instance (0 if none); must equal Geom::line.R
 // (grid N, line radix R, pruned outputs K) of the compiled pair-transform instances
 #define GW_PAIR_CASES(X) \
   X(24, 8, 5)            \
   X(24, 8, 7)            \
   X(24, 8, 9)            \
   X(24, 8, 11)           \
+  X(48, 8, 15)           \
   X(72, 8, 9)            \
   X(72, 8, 11)           \
   X(72, 8, 13)           \

@@ -563,6 +563,14 @@ bool pair_supported(int nd, int K) {
   return false;
 }
 
+int pair_radix(int nd, int K) {
+#define X(nd_, r_, k_) \
+  if (nd == nd_ && K == k_) return r_;
+  GW_PAIR_CASES(X)
+#undef X
+  return 0;
+}
+
 template <typename T>
 hipError_t launch_pair_planes(const Geom& g, const void* psi_v, const void* psi_c, int nvs, int ncs, void* q, int minb,
                               hipStream_t st) {

@@ -612,3 +612,25 @@ def test_chi0_ksum_energy_gradients_match_finite_differences():
         minus[k][j] -= h
         fd = (loss(b.e_v, plus) - loss(b.e_v, minus)) / (2 * h)
         assert abs(fd - gcl[k][j]) <= 1e-6 * max(1.0, abs(gcl[k][j])), (k, j, fd, gcl[k][j])
+
+
+def test_chi0_is_the_same_on_every_alias_free_grid():
+    # Eq. (chi0)'s matrix element needs only the product's components on the chi sphere to
+    # be unaliased.  On the 24^3 workload (wavefunction radius 6, chi radius 4) every grid
+    # with N > 2*6 + 4 gives the same chi0 up to rounding; on N = 16 the components G +- 16
+    # of the product fold onto the sphere and M changes.
+    from oracle import chi0 as oc
+    cfg = synth.config(0)
+    gw = synth.wf_sphere(cfg.nd)
+    gc = synth.chi_sphere(cfg.ng[0], cfg.qs[0], cfg.cell)
+    b = synth.make_bands(cfg, v_index=np.arange(4), c_index=np.arange(10), gvec_wf=gw)
+    assert 2 * np.abs(gw).max() + np.abs(gc).max() == 16
+    assert oc.alias_free(gw, gc, (17,) * 3) and not oc.alias_free(gw, gc, (16,) * 3)
+    ref = oracle.chi0_bands(b.coef_v, b.e_v, b.coef_c, b.e_c, gw, gc, (24,) * 3)[0]
+    for n in (17, 18, 20):
+        got = oracle.chi0_bands(b.coef_v, b.e_v, b.coef_c, b.e_c, gw, gc, (n,) * 3)[0]
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), n
+    m = {n: oc.pair_density_fft(oc.psi_real_space(b.coef_v, gw, (n,) * 3),
+                                oc.psi_real_space(b.coef_c, gw, (n,) * 3), gc) for n in (16, 17, 24)}
+    assert np.abs(m[17] - m[24]).max() <= 1e-12 * np.abs(m[24]).max()
+    assert np.abs(m[16] - m[24]).max() > 1e-3 * np.abs(m[24]).max()
