@@ -101,6 +101,10 @@ def main():
                          "extensions: the k-point sum, the static COH self-energy and the plasmon-pole "
                          "eps^-1(w); reduced-box: the static inputs on the stated 72^3 grid and on the smallest "
                          "supported alias-free grid (48^3), reported beside the metric, never as it")
+    ap.add_argument("--grid", type=int, default=0,
+                    help="grouped / adjoint workloads: FFT grid N^3 to run on instead of the stated one (an "
+                         "alias-free smaller box gives the same chi0: 64 for the 96^3 workload, 96 for the "
+                         "128^3 one); reported with reduced_box true, beside the metric, never as it")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run every conduction chunk's contraction on the context's stream (no second stream)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -384,9 +388,9 @@ def run_grouped(args, torch, synth, p, dev, backward):
     gw_chi0_backward down to dL/dE_v, dL/dE_col and dL/dn_col (the pair densities are
     recomputed)."""
     cfg = synth.config(4 if backward else 2)
-    nd = cfg.nd
+    nd = args.grid or cfg.nd   # FFT grid; the spheres stay those of the stated grid
     ev_ = synth.HARTREE_EV
-    gw = synth.wf_sphere(nd)
+    gw = synth.wf_sphere(cfg.nd)
     gc = synth.chi_sphere(cfg.ng[0], cfg.qs[0], cfg.cell)
     e_all = synth.conduction_energies(cfg)
     nwin = int(round((cfg.emax_ev - cfg.e0_ev) / cfg.de_ev))
@@ -486,7 +490,8 @@ def run_grouped(args, torch, synth, p, dev, backward):
             "warmup": args.warmup, "ms_per_step": hr["ms_per_step"], "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[head_m],
             "data": "synthetic",
-            "config": {"workload": cfg.name + ("-with-adjoint" if backward else ""), "grid": nd, "npw": len(gw),
+            "config": {"workload": cfg.name + ("-with-adjoint" if backward else ""), "grid": nd,
+                       "reduced_box": nd != cfg.nd, "npw": len(gw),
                        "nv": cfg.nv, "nc_generated": cfg.nc, "ncol": len(col), "explicit": n0, "ng": ng,
                        "pairs": npair, "q": list(cfg.qs[0]), "omega": 0.0, "e0_ev": cfg.e0_ev, "de_ev": cfg.de_ev},
             "band_pairs_per_s": hr["band_pairs_per_s"], "modes": results, "roofline": roofline,

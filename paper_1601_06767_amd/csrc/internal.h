@@ -155,6 +155,7 @@ int pair_radix(int nd, int K);   // line radix R of the (nd, K) instance (0 if n
   X(24, 8, 9)            \
   X(24, 8, 11)           \
   X(48, 8, 15)           \
+  X(64, 16, 19)          \
   X(72, 8, 9)            \
   X(72, 8, 11)           \
   X(72, 8, 13)           \
@@ -164,6 +165,7 @@ int pair_radix(int nd, int K);   // line radix R of the (nd, K) instance (0 if n
   X(96, 16, 17)          \
   X(96, 16, 19)          \
   X(96, 16, 21)          \
+  X(96, 16, 25)          \
   X(128, 16, 23)         \
   X(128, 16, 25)         \
   X(128, 16, 27)

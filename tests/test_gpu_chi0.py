@@ -198,15 +198,19 @@ def test_invalid_arguments_raise(g):
         p.gw_chi0_build(g.ctx, [prob], [len(case.gc)], [0.0], 0.0, p.GW_FP64, workspace=ws)
 
 
-def test_reduced_alias_free_grid_gives_the_same_chi0(g):
-    # the 72^3 workload's spheres (wavefunction radius 18, chi radius 7 at NG 2000) are
-    # alias-free on 48^3 (2 * 18 + 7 < 48): the build on the smaller grid reproduces the
-    # oracle's chi0 on the stated 72^3 grid, in every precision
+# (workload, NG, smaller grid): the spheres of the 72^3 workload (wavefunction radius 18,
+# chi radius 7 at NG 2000) are alias-free on 48^3 (2 * 18 + 7 < 48), those of the 96^3 one
+# (24, 9) on 64^3, those of the 128^3 one (32, 12) on 96^3
+@pytest.mark.parametrize("cfg,ng,small_nd", [(1, 2000, 48), (2, 4000, 64), (4, 8000, 96)],
+                         ids=["72cube-on-48", "96cube-on-64", "128cube-on-96"])
+def test_reduced_alias_free_grid_gives_the_same_chi0(g, cfg, ng, small_nd):
+    # the build on the smaller grid reproduces the oracle's chi0 on the stated grid, in
+    # every precision
     import dataclasses
-    case = make_case(1, nv=4, nc=13, ng=2000)
-    small = dataclasses.replace(case, nd=48)
-    assert 2 * np.abs(case.gw).max() + np.abs(case.gc).max() < 48
-    ref = oracle.chi0_bands(case.coef_v, case.e_v, case.coef_c, case.e_c, case.gw, case.gc, (72,) * 3)[0]
+    case = make_case(cfg, nv=4, nc=13, ng=ng)
+    small = dataclasses.replace(case, nd=small_nd)
+    assert 2 * np.abs(case.gw).max() + np.abs(case.gc).max() < small_nd
+    ref = oracle.chi0_bands(case.coef_v, case.e_v, case.coef_c, case.e_c, case.gw, case.gc, (case.nd,) * 3)[0]
     for prec, tol in (("fp64", 1e-10), ("fp32", 2e-5), ("bf16x3", 1e-4)):
         chi = g.chi0(small, prec=prec)[0]
         fro, mx = rel_err(chi, ref)
