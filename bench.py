@@ -105,6 +105,8 @@ def main():
                     help="grouped / adjoint workloads: FFT grid N^3 to run on instead of the stated one (an "
                          "alias-free smaller box gives the same chi0: 64 for the 96^3 workload, 96 for the "
                          "128^3 one); reported with reduced_box true, beside the metric, never as it")
+    ap.add_argument("--no-reduced-box", action="store_true",
+                    help="static workload: skip the extra head-mode steps on the 48^3 alias-free grid")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run every conduction chunk's contraction on the context's stream (no second stream)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -217,6 +219,38 @@ def main():
 
     head = modes[0]
     hr = results[head]
+    # the head mode on the smallest supported alias-free grid (2 * 18 + 7 < 48): the same chi0
+    # with less work, reported beside the metric (which stays on the stated grid)
+    reduced = None
+    if not args.no_reduced_box:
+        geom_s = p.gw_geom_create(ctx, (48,) * 3, gw, gc)
+        prob_s = p.make_problem(geom_s, cv, ev, cc, ec)
+        need = p.gw_chi0_workspace_size(ctx, [prob_s], 1, p.PRECISIONS[head])
+        ws_s = ws if need <= wsb else torch.empty(need, dtype=torch.uint8, device=dev)
+        out_s = torch.empty(ng * ng, dtype=torch.complex128, device=dev)
+
+        def run_s():
+            p.gw_chi0_build(ctx, [prob_s], [ng], [0.0], 0.0, p.PRECISIONS[head], workspace=ws_s, out=out_s)
+            p.gw_eps_inv(ctx, vcoul, out_s.view(ng, ng), workspace=ws_inv, out=zout)
+        for _ in range(max(1, args.warmup)):
+            run_s()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            run_s()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        p.gw_eps_inv_status(ctx)
+        ms_s = e0.elapsed_time(e1) / args.steps
+        chi_s = out_s.view(ng, ng).cpu().numpy()
+        reduced = {"grid": 48, "mode": head, "ms_per_step": ms_s, "speedup_vs_stated_grid": hr["ms_per_step"] / ms_s,
+                   "max_rel_diff_vs_stated_grid": float(np.abs(chi_s - chis[head]).max() / np.abs(chis[head]).max()),
+                   "note": "same chi0 on the smallest supported alias-free grid; beside the metric, not it"}
+        log(f"{head} on 48^3: {ms_s:.1f} ms/step ({reduced['speedup_vs_stated_grid']:.2f}x), "
+            f"max rel diff {reduced['max_rel_diff_vs_stated_grid']:.1e}")
+        p.gw_geom_destroy(geom_s)
+        del ws_s, out_s
     # dominant kernel of the headline mode and its roofline
     st = hr["stages_ms_per_step"]
     dom = max(st, key=st.get)
@@ -269,7 +303,7 @@ def main():
             "config": {"workload": cfg.name, "grid": nd, "npw": len(gw), "nv": cfg.nv, "ncol": cfg.nc, "ng": ng,
                        "pairs": npair, "q": list(cfg.qs[0]), "omega": 0.0},
             "band_pairs_per_s": hr["band_pairs_per_s"], "modes": results, "roofline": roofline,
-            "cpu_baseline": cpu}
+            "cpu_baseline": cpu, "reduced_box": reduced}
     print(json.dumps(line))
 
 
