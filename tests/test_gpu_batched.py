@@ -99,16 +99,24 @@ def test_tuner_choices_keep_parity(g):
         assert fro <= tol and mx <= tol, (prec, fro, mx)
 
 
-# 72^3 with NG 2600 / 3600 gives K = 17 / 19, where the lean split-line form (5) is built
-@pytest.mark.parametrize("cfg,ng", [(0, None), (1, 300), (1, 2600), (1, 3600), (2, 2600), (4, 6500)],
-                         ids=["24cube", "72cube", "72cube-K17", "72cube-K19", "96cube", "128cube"])
-def test_every_pair_kernel_form_matches_oracle(g, cfg, ng):
+# 72^3 with NG 2600 / 3600 gives K = 17 / 19, where the lean split-line form (5) is built;
+# the last three run a workload's spheres on its smaller alias-free grid (the instances
+# (48, K 15), (64, K 19) and (96, K 25)) against the oracle on the stated grid
+@pytest.mark.parametrize("cfg,ng,grid", [(0, None, None), (1, 300, None), (1, 2600, None), (1, 3600, None),
+                                         (2, 2600, None), (4, 6500, None), (1, 2000, 48), (2, 4000, 64),
+                                         (4, 8000, 96)],
+                         ids=["24cube", "72cube", "72cube-K17", "72cube-K19", "96cube", "128cube", "72cube-on-48",
+                              "96cube-on-64", "128cube-on-96"])
+def test_every_pair_kernel_form_matches_oracle(g, cfg, ng, grid):
     # each form of the pair kernel forced through gw_tune_set, float64 and float32, on a
     # conduction count that is not a multiple of the workgroup's 8 columns
+    import dataclasses
     p = g.p
     case = make_case(cfg, nv=4, nc=13, ng=ng)
-    prob = g.problem(case)
     ref = ref_chi0(case, [0.0], 0.0)[0]
+    if grid is not None:
+        case = dataclasses.replace(case, nd=grid)
+    prob = g.problem(case)
     for prec, tol in (("fp64", 1e-10), ("fp32", 2e-5)):
         for form in (1, 2, 3, 4, 5):
             p.gw_tune_set(g.ctx, prob, p.PRECISIONS[prec], form, 0)
