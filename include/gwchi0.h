@@ -113,8 +113,10 @@ gw_status gw_ctx_set_overlap(gw_ctx* ctx, int mode);
  * (reading of Eq. (chi0)'s matrix element, whose exponent is printed without ".r").
  * Every grid that meets the bound gives the same chi0 up to rounding, so the smallest
  * supported one is the cheapest (the 72^3 workload's spheres, 2 x 18 + 7 = 43, are exact on
- * 48^3).  A sphere whose pair-kernel instance (grid, 2 max|n_chi| + 1) is not built gives
- * GW_EUNSUPPORTED.  The geometry keeps its own device copies of the index tables. */
+ * 48^3).  The pair kernels are built for these (grid, K = 2 max|n_chi| + 1): 24^3 with K 5,
+ * 7, 9, 11; 48^3 with 15; 64^3 with 19; 72^3 with 9 ... 19 (odd); 96^3 with 17, 19, 21, 25;
+ * 128^3 with 23, 25, 27.  Another combination gives GW_EUNSUPPORTED.  The geometry keeps
+ * its own device copies of the index tables. */
 gw_status gw_geom_create(gw_ctx* ctx, const int n_fft[3], int npw, const int32_t* gvec_wf, int ng,
                          const int32_t* gvec_chi, gw_geom** out);
 gw_status gw_geom_destroy(gw_geom* geom);
