@@ -157,12 +157,40 @@ constexpr int BKS = 16;     // G' per stage
 constexpr int BROWA = 56;   // bf16 per LDS row: 48 used, padded so 8 rows read together hit distinct banks
 constexpr int BMI = 4, BNJ = 2;
 
+// chibar split once per call into the LDS image of its rows: for row G and block kb of 16 G',
+// 96 bf16 = hi [re | im | -im] then lo [re | im | -im] (zero beyond ng), so that the tiles
+// stage chibar with plain 16-byte copies instead of converting it once per pair tile.
+constexpr int GSPLIT = 96;   // bf16 per (row, 16-G' block)
+__global__ void k_split_gbar(const double2* __restrict__ gbar, int ng, int nkb, unsigned short* __restrict__ out) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;   // (row, block, G' in block)
+  if (e >= (size_t)ng * nkb * 16) return;
+  const int i = (int)(e % 16);
+  const size_t rb = e / 16;   // row * nkb + kb
+  const int kb = (int)(rb % nkb), row = (int)(rb / nkb);
+  const int col = kb * 16 + i;
+  float re = 0.f, im = 0.f;
+  if (col < ng) {
+    const double2 x = gbar[(size_t)row * ng + col];
+    re = (float)x.x;
+    im = (float)x.y;
+  }
+  const unsigned short rh = bf16_rne(re), ih = bf16_rne(im);
+  const unsigned short rl = bf16_rne(re - bf16_val(rh)), il = bf16_rne(im - bf16_val(ih));
+  unsigned short* o = out + rb * GSPLIT;
+  o[i] = rh;
+  o[16 + i] = ih;
+  o[32 + i] = ih ^ 0x8000;
+  o[48 + i] = rl;
+  o[64 + i] = il;
+  o[80 + i] = il ^ 0x8000;
+}
+
 // One workgroup per CU (162 registers): capped at 128 registers for a second one, it
 // spills and runs slower (measured 9.4 against 5.4 ms per 32k-pair launch at NG 2000; the
 // float32 kernel takes 9.2 ms).  Stages of 32 G' (two blocks of 16 between barriers) were
 // no faster (5.6 ms).
 __global__ __launch_bounds__(512) void k_adjoint_bf16x3(const float2* __restrict__ m, int npair, int ng, int ngp,
-                                                           const double2* __restrict__ gbar,
+                                                           const uint4* __restrict__ gsplit,
                                                            double2* __restrict__ part) {
   __shared__ __align__(16) unsigned short s[2][2][BT][BROWA];   // [M | chibar][hi | lo][row][k']
   __shared__ double2 sred[4][BT];
@@ -191,16 +219,21 @@ __global__ __launch_bounds__(512) void k_adjoint_bf16x3(const float2* __restrict
       cre[i][j] = f32x4{0, 0, 0, 0};
       cim[i][j] = f32x4{0, 0, 0, 0};
     }
+  // op 0 (M rows): two G' of 4 rows per thread, split here.  op 1 (chibar rows): six of the
+  // 12 16-byte pieces of the pre-split row images per stage (128 rows x 12 pieces)
+  const int nkb = (ng + BKS - 1) / BKS;
+  const int t1 = tid - 2 * BT;
   float2 pf[4][2];
+  uint4 pg[6];
   auto fetch = [&](int k0) {
-    const int k = k0 + 2 * kp;
+    if (op == 0) {
+      const int k = k0 + 2 * kp;
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      const int row = rg + 32 * rr;
-      float2 x0{0.f, 0.f}, x1{0.f, 0.f};
-      if (row < nrow && k < ng) {
-        const size_t at = base0 + (size_t)row * ld + k;
-        if (op == 0) {
+      for (int rr = 0; rr < 4; ++rr) {
+        const int row = rg + 32 * rr;
+        float2 x0{0.f, 0.f}, x1{0.f, 0.f};
+        if (row < nrow && k < ng) {
+          const size_t at = base0 + (size_t)row * ld + k;
           if (k + 1 < ng) {
             // k even and ngp even: 16-byte aligned
             const float4 v = *(const float4*)(m + at);
@@ -209,17 +242,19 @@ __global__ __launch_bounds__(512) void k_adjoint_bf16x3(const float2* __restrict
           } else {
             x0 = m[at];
           }
-        } else {
-          const double2 d0 = gbar[at];
-          x0 = float2{(float)d0.x, (float)d0.y};
-          if (k + 1 < ng) {
-            const double2 d1 = gbar[at + 1];
-            x1 = float2{(float)d1.x, (float)d1.y};
-          }
         }
+        pf[rr][0] = x0;
+        pf[rr][1] = x1;
       }
-      pf[rr][0] = x0;
-      pf[rr][1] = x1;
+    } else {
+      const int kb = k0 / BKS;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        const int qv = t1 + 2 * BT * i, row = qv / 12, c = qv % 12;
+        uint4 v = {0u, 0u, 0u, 0u};
+        if (row < nrow) v = gsplit[((size_t)(q0 + row) * nkb + kb) * (GSPLIT / 8) + c];
+        pg[i] = v;
+      }
     }
   };
   fetch(0);
@@ -227,27 +262,31 @@ __global__ __launch_bounds__(512) void k_adjoint_bf16x3(const float2* __restrict
   const int im_off = lg < 2 ? 16 + 8 * lg : 8 * (lg - 2);   // [bi | br]
   for (int k0 = 0; k0 < ng; k0 += BKS) {
     __syncthreads();
+    if (op == 0) {
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      // two consecutive G' as one 32-bit word (the lower G' in the low half)
-      unsigned rh = 0, rl = 0, ih = 0, il = 0;
+      for (int rr = 0; rr < 4; ++rr) {
+        // two consecutive G' as one 32-bit word (the lower G' in the low half)
+        unsigned rh = 0, rl = 0, ih = 0, il = 0;
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const unsigned short a = bf16_rne(pf[rr][e].x), b = bf16_rne(pf[rr][e].y);
-        rh |= (unsigned)a << (16 * e);
-        ih |= (unsigned)b << (16 * e);
-        rl |= (unsigned)bf16_rne(pf[rr][e].x - bf16_val(a)) << (16 * e);
-        il |= (unsigned)bf16_rne(pf[rr][e].y - bf16_val(b)) << (16 * e);
+        for (int e = 0; e < 2; ++e) {
+          const unsigned short a = bf16_rne(pf[rr][e].x), b = bf16_rne(pf[rr][e].y);
+          rh |= (unsigned)a << (16 * e);
+          ih |= (unsigned)b << (16 * e);
+          rl |= (unsigned)bf16_rne(pf[rr][e].x - bf16_val(a)) << (16 * e);
+          il |= (unsigned)bf16_rne(pf[rr][e].y - bf16_val(b)) << (16 * e);
+        }
+        const int row = rg + 32 * rr;
+        *(unsigned*)&s[0][0][row][2 * kp] = rh;
+        *(unsigned*)&s[0][0][row][16 + 2 * kp] = ih;
+        *(unsigned*)&s[0][1][row][2 * kp] = rl;
+        *(unsigned*)&s[0][1][row][16 + 2 * kp] = il;
       }
-      const int row = rg + 32 * rr;
-      *(unsigned*)&s[op][0][row][2 * kp] = rh;
-      *(unsigned*)&s[op][0][row][16 + 2 * kp] = ih;
-      *(unsigned*)&s[op][1][row][2 * kp] = rl;
-      *(unsigned*)&s[op][1][row][16 + 2 * kp] = il;
-      if (op == 1) {
-        // flipping the sign bits of hi and lo splits -bi exactly
-        *(unsigned*)&s[1][0][row][32 + 2 * kp] = ih ^ 0x80008000u;
-        *(unsigned*)&s[1][1][row][32 + 2 * kp] = il ^ 0x80008000u;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        const int qv = t1 + 2 * BT * i, row = qv / 12, c = qv % 12;
+        // pieces 0..5: hi [re | im | -im], 6..11: lo
+        *(uint4*)&s[1][c / 6][row][8 * (c % 6)] = pg[i];
       }
     }
     __syncthreads();
@@ -394,12 +433,17 @@ size_t adjoint_partial_bytes(int npair, int ngp) { return (size_t)npair * (ngp /
 
 int adjoint_tile(int mode) { return mode == 2 ? BT : AT; }
 
-hipError_t launch_adjoint_bf16x3(const void* m, int npair, int ng, int ngp, const double2* gbar, double2* part,
-                                 hipStream_t st) {
+size_t gbar_split_bytes(int ng) { return (size_t)ng * ((ng + BKS - 1) / BKS) * GSPLIT * sizeof(unsigned short); }
+
+hipError_t launch_adjoint_bf16x3(const void* m, int npair, int ng, int ngp, const double2* gbar, void* gsplit,
+                                 double2* part, hipStream_t st) {
   if (ngp % BT != 0) return hipErrorInvalidValue;
+  const int nkb = (ng + BKS - 1) / BKS;
+  const size_t ne = (size_t)ng * nkb * 16;
+  k_split_gbar<<<(unsigned)((ne + 255) / 256), 256, 0, st>>>(gbar, ng, nkb, (unsigned short*)gsplit);
   const int ntg = ngp / BT;
   const int nb = ((npair + BT - 1) / BT) * ntg;
-  k_adjoint_bf16x3<<<nb, 512, 0, st>>>((const float2*)m, npair, ng, ngp, gbar, part);
+  k_adjoint_bf16x3<<<nb, 512, 0, st>>>((const float2*)m, npair, ng, ngp, (const uint4*)gsplit, part);
   return hipGetLastError();
 }
 

@@ -51,6 +51,7 @@ struct Layout {
   int nparts = 1, nomega = 1, mode = 0;
   std::vector<ProbPlan> pp;
   size_t off_psic = 0, off_scr = 0, off_q = 0, off_part = 0, off_dx = 0, off_dn = 0, off_counter = 0, total = 0;
+  size_t off_gsplit = 0;   // backward, split-bf16 mode: chibar split into bf16 row images
   // coefficient gradients (backward, float64): mbar and a weighted copy of M per chunk,
   // ubar of the chunk's columns and of the valence slots, column gradients of a chunk
   size_t off_mbar = 0, off_atmp = 0, off_ubarc = 0, off_ubarv = 0, off_cbar = 0;
@@ -136,6 +137,11 @@ Layout make_layout(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nom
   L.off_q = take(max_q);
   if (backward) {
     L.off_part = take(max_part);
+    if (L.mode == 2) {
+      size_t gs = 0;
+      for (const auto& q : L.pp) gs = std::max(gs, gw::gbar_split_bytes(q.p->geom->g.ng));
+      L.off_gsplit = take(gs);
+    }
     L.off_dx = take(max_np * sizeof(double));
     L.off_dn = take(max_np * sizeof(double));
     if (L.fp64) {
@@ -573,7 +579,8 @@ gw_status backward_entry(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, i
         const double2* gb = (const double2*)gin + (size_t)iw * g.ng * g.ng;
         hipError_t e =
             L.fp64        ? gw::launch_adjoint<double>(ws + q.off_m, q.npair, g.ng, g.ngp, gb, part, ctx->stream)
-            : L.mode == 2 ? gw::launch_adjoint_bf16x3(ws + q.off_m, q.npair, g.ng, g.ngp, gb, part, ctx->stream)
+            : L.mode == 2 ? gw::launch_adjoint_bf16x3(ws + q.off_m, q.npair, g.ng, g.ngp, gb, ws + L.off_gsplit, part,
+                                                      ctx->stream)
                           : gw::launch_adjoint<float>(ws + q.off_m, q.npair, g.ng, g.ngp, gb, part, ctx->stream);
         GW_HIP(ctx, e);
         GW_HIP(ctx, gw::launch_adjoint_pairs(part, g.ngp / gw::adjoint_tile(L.mode), p.e_v, p.nv, q.nvs, p.e_col,

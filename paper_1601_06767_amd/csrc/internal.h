@@ -250,9 +250,11 @@ int adjoint_tile(int mode);                          // G per partial sum in thi
 template <typename T>
 hipError_t launch_adjoint(const void* m, int npair, int ng, int ngp, const double2* gbar, double2* part,
                           hipStream_t st);
-// split-bf16 x3 form over float pair densities (ngp a multiple of 128)
-hipError_t launch_adjoint_bf16x3(const void* m, int npair, int ng, int ngp, const double2* gbar, double2* part,
-                                 hipStream_t st);
+// split-bf16 x3 form over float pair densities (ngp a multiple of 128); gsplit is scratch of
+// gbar_split_bytes(ng) for chibar split into bf16 row images
+size_t gbar_split_bytes(int ng);
+hipError_t launch_adjoint_bf16x3(const void* m, int npair, int ng, int ngp, const double2* gbar, void* gsplit,
+                                 double2* part, hipStream_t st);
 // ntg = ngp / adjoint_tile(mode) partial sums per pair
 hipError_t launch_adjoint_pairs(const double2* part, int ntg, const double* e_v, int nv, int nvs, const double* e_col,
                                 const double* n_col, int c0, int ncol, int cc, double omega, double delta, double* dx,
