@@ -185,11 +185,37 @@ __global__ void k_split_gbar(const double2* __restrict__ gbar, int ng, int nkb, 
   o[80 + i] = il ^ 0x8000;
 }
 
+// The pair densities split the same way, once per chunk: for pair row p and block kb of 16 G',
+// 64 bf16 = hi [re | im] then lo [re | im] (zero beyond ng).
+constexpr int MSPLIT = 64;   // bf16 per (pair row, 16-G' block)
+__global__ void k_split_m(const float2* __restrict__ m, int npair, int ng, int ngp, int nkb,
+                          unsigned short* __restrict__ out) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;   // (row, block, G' in block)
+  if (e >= (size_t)npair * nkb * 16) return;
+  const int i = (int)(e % 16);
+  const size_t rb = e / 16;
+  const int kb = (int)(rb % nkb), row = (int)(rb / nkb);
+  const int col = kb * 16 + i;
+  float re = 0.f, im = 0.f;
+  if (col < ng) {
+    const float2 x = m[(size_t)row * ngp + col];
+    re = x.x;
+    im = x.y;
+  }
+  const unsigned short rh = bf16_rne(re), ih = bf16_rne(im);
+  unsigned short* o = out + rb * MSPLIT;
+  o[i] = rh;
+  o[16 + i] = ih;
+  o[32 + i] = bf16_rne(re - bf16_val(rh));
+  o[48 + i] = bf16_rne(im - bf16_val(ih));
+}
+
 // One workgroup per CU (162 registers): capped at 128 registers for a second one, it
 // spills and runs slower (measured 9.4 against 5.4 ms per 32k-pair launch at NG 2000; the
 // float32 kernel takes 9.2 ms).  Stages of 32 G' (two blocks of 16 between barriers) were
 // no faster (5.6 ms).
 __global__ __launch_bounds__(512) void k_adjoint_bf16x3(const float2* __restrict__ m, int npair, int ng, int ngp,
+                                                           const uint4* __restrict__ msplit,
                                                            const uint4* __restrict__ gsplit,
                                                            double2* __restrict__ part) {
   __shared__ __align__(16) unsigned short s[2][2][BT][BROWA];   // [M | chibar][hi | lo][row][k']
@@ -201,15 +227,9 @@ __global__ __launch_bounds__(512) void k_adjoint_bf16x3(const float2* __restrict
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = wave / 4, wc = wave % 4;
   const int li = lane & 15, lg = lane >> 4;
-  // staging role: operand (M rows or chibar rows, wave-uniform); each thread takes the two
-  // G' 2 kp, 2 kp + 1 of rows rg + 32 rr (rr = 0..3), so that 8 lanes read 16 consecutive G'
-  // of a row (16-byte loads along the contiguous index)
+  // staging role: operand (M rows or chibar rows, wave-uniform)
   const int op = __builtin_amdgcn_readfirstlane(tid / (2 * BT));
-  const int kp = tid % 8;
-  const int rg = (tid % (2 * BT)) / 8;
   const int nrow = op == 0 ? npair - p0 : ng - q0;   // valid rows of this operand's tile
-  const size_t ld = op == 0 ? (size_t)ngp : (size_t)ng;
-  const size_t base0 = op == 0 ? (size_t)p0 * ngp : (size_t)q0 * ng;
 
   f32x4 cre[BMI][BNJ], cim[BMI][BNJ];
 #pragma unroll
@@ -219,32 +239,21 @@ __global__ __launch_bounds__(512) void k_adjoint_bf16x3(const float2* __restrict
       cre[i][j] = f32x4{0, 0, 0, 0};
       cim[i][j] = f32x4{0, 0, 0, 0};
     }
-  // op 0 (M rows): two G' of 4 rows per thread, split here.  op 1 (chibar rows): six of the
-  // 12 16-byte pieces of the pre-split row images per stage (128 rows x 12 pieces)
+  // both operands arrive pre-split as bf16 row images: per stage, op 0 (M rows) copies 4 of
+  // the 128 x 8 16-byte pieces per thread, op 1 (chibar rows) 6 of the 128 x 12
   const int nkb = (ng + BKS - 1) / BKS;
   const int t1 = tid - 2 * BT;
-  float2 pf[4][2];
+  uint4 pm[4];
   uint4 pg[6];
   auto fetch = [&](int k0) {
     if (op == 0) {
-      const int k = k0 + 2 * kp;
+      const int kb = k0 / BKS;
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        const int row = rg + 32 * rr;
-        float2 x0{0.f, 0.f}, x1{0.f, 0.f};
-        if (row < nrow && k < ng) {
-          const size_t at = base0 + (size_t)row * ld + k;
-          if (k + 1 < ng) {
-            // k even and ngp even: 16-byte aligned
-            const float4 v = *(const float4*)(m + at);
-            x0 = float2{v.x, v.y};
-            x1 = float2{v.z, v.w};
-          } else {
-            x0 = m[at];
-          }
-        }
-        pf[rr][0] = x0;
-        pf[rr][1] = x1;
+      for (int i = 0; i < 4; ++i) {
+        const int qv = tid + 2 * BT * i, row = qv / 8, c = qv % 8;
+        uint4 v = {0u, 0u, 0u, 0u};
+        if (row < nrow) v = msplit[((size_t)(p0 + row) * nkb + kb) * (MSPLIT / 8) + c];
+        pm[i] = v;
       }
     } else {
       const int kb = k0 / BKS;
@@ -264,22 +273,10 @@ __global__ __launch_bounds__(512) void k_adjoint_bf16x3(const float2* __restrict
     __syncthreads();
     if (op == 0) {
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        // two consecutive G' as one 32-bit word (the lower G' in the low half)
-        unsigned rh = 0, rl = 0, ih = 0, il = 0;
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const unsigned short a = bf16_rne(pf[rr][e].x), b = bf16_rne(pf[rr][e].y);
-          rh |= (unsigned)a << (16 * e);
-          ih |= (unsigned)b << (16 * e);
-          rl |= (unsigned)bf16_rne(pf[rr][e].x - bf16_val(a)) << (16 * e);
-          il |= (unsigned)bf16_rne(pf[rr][e].y - bf16_val(b)) << (16 * e);
-        }
-        const int row = rg + 32 * rr;
-        *(unsigned*)&s[0][0][row][2 * kp] = rh;
-        *(unsigned*)&s[0][0][row][16 + 2 * kp] = ih;
-        *(unsigned*)&s[0][1][row][2 * kp] = rl;
-        *(unsigned*)&s[0][1][row][16 + 2 * kp] = il;
+      for (int i = 0; i < 4; ++i) {
+        const int qv = tid + 2 * BT * i, row = qv / 8, c = qv % 8;
+        // pieces 0..3: hi [re | im], 4..7: lo
+        *(uint4*)&s[0][c / 4][row][8 * (c % 4)] = pm[i];
       }
     } else {
 #pragma unroll
@@ -435,15 +432,28 @@ int adjoint_tile(int mode) { return mode == 2 ? BT : AT; }
 
 size_t gbar_split_bytes(int ng) { return (size_t)ng * ((ng + BKS - 1) / BKS) * GSPLIT * sizeof(unsigned short); }
 
-hipError_t launch_adjoint_bf16x3(const void* m, int npair, int ng, int ngp, const double2* gbar, void* gsplit,
-                                 double2* part, hipStream_t st) {
+size_t m_split_bytes(int npair, int ng) {
+  return (size_t)npair * ((ng + BKS - 1) / BKS) * MSPLIT * sizeof(unsigned short);
+}
+
+hipError_t launch_split_m(const void* m, int npair, int ng, int ngp, void* msplit, hipStream_t st) {
+  const int nkb = (ng + BKS - 1) / BKS;
+  const size_t ne = (size_t)npair * nkb * 16;
+  k_split_m<<<(unsigned)((ne + 255) / 256), 256, 0, st>>>((const float2*)m, npair, ng, ngp, nkb,
+                                                         (unsigned short*)msplit);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_bf16x3(const void* m, const void* msplit, int npair, int ng, int ngp, const double2* gbar,
+                                 void* gsplit, double2* part, hipStream_t st) {
   if (ngp % BT != 0) return hipErrorInvalidValue;
   const int nkb = (ng + BKS - 1) / BKS;
   const size_t ne = (size_t)ng * nkb * 16;
   k_split_gbar<<<(unsigned)((ne + 255) / 256), 256, 0, st>>>(gbar, ng, nkb, (unsigned short*)gsplit);
   const int ntg = ngp / BT;
   const int nb = ((npair + BT - 1) / BT) * ntg;
-  k_adjoint_bf16x3<<<nb, 512, 0, st>>>((const float2*)m, npair, ng, ngp, (const uint4*)gsplit, part);
+  k_adjoint_bf16x3<<<nb, 512, 0, st>>>((const float2*)m, npair, ng, ngp, (const uint4*)msplit, (const uint4*)gsplit,
+                                       part);
   return hipGetLastError();
 }
 

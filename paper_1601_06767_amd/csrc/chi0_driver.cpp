@@ -52,6 +52,7 @@ struct Layout {
   std::vector<ProbPlan> pp;
   size_t off_psic = 0, off_scr = 0, off_q = 0, off_part = 0, off_dx = 0, off_dn = 0, off_counter = 0, total = 0;
   size_t off_gsplit = 0;   // backward, split-bf16 mode: chibar split into bf16 row images
+  size_t off_msplit = 0;   // and the chunk's pair densities, split the same way
   // coefficient gradients (backward, float64): mbar and a weighted copy of M per chunk,
   // ubar of the chunk's columns and of the valence slots, column gradients of a chunk
   size_t off_mbar = 0, off_atmp = 0, off_ubarc = 0, off_ubarv = 0, off_cbar = 0;
@@ -139,8 +140,13 @@ Layout make_layout(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nom
     L.off_part = take(max_part);
     if (L.mode == 2) {
       size_t gs = 0;
-      for (const auto& q : L.pp) gs = std::max(gs, gw::gbar_split_bytes(q.p->geom->g.ng));
+      size_t ms = 0;
+      for (const auto& q : L.pp) {
+        gs = std::max(gs, gw::gbar_split_bytes(q.p->geom->g.ng));
+        ms = std::max(ms, gw::m_split_bytes(q.npair, q.p->geom->g.ng));
+      }
       L.off_gsplit = take(gs);
+      L.off_msplit = take(ms);
     }
     L.off_dx = take(max_np * sizeof(double));
     L.off_dn = take(max_np * sizeof(double));
@@ -575,12 +581,14 @@ gw_status backward_entry(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, i
       if (s != GW_OK) return s;
       GW_HIP(ctx, gw::launch_fill_f64(dx, q.npair, 0.0, ctx->stream));
       GW_HIP(ctx, gw::launch_fill_f64(dn, q.npair, 0.0, ctx->stream));
+      if (L.mode == 2)
+        GW_HIP(ctx, gw::launch_split_m(ws + q.off_m, q.npair, g.ng, g.ngp, ws + L.off_msplit, ctx->stream));
       for (int iw = 0; iw < nomega; ++iw) {
         const double2* gb = (const double2*)gin + (size_t)iw * g.ng * g.ng;
         hipError_t e =
             L.fp64        ? gw::launch_adjoint<double>(ws + q.off_m, q.npair, g.ng, g.ngp, gb, part, ctx->stream)
-            : L.mode == 2 ? gw::launch_adjoint_bf16x3(ws + q.off_m, q.npair, g.ng, g.ngp, gb, ws + L.off_gsplit, part,
-                                                      ctx->stream)
+            : L.mode == 2 ? gw::launch_adjoint_bf16x3(ws + q.off_m, ws + L.off_msplit, q.npair, g.ng, g.ngp, gb,
+                                                      ws + L.off_gsplit, part, ctx->stream)
                           : gw::launch_adjoint<float>(ws + q.off_m, q.npair, g.ng, g.ngp, gb, part, ctx->stream);
         GW_HIP(ctx, e);
         GW_HIP(ctx, gw::launch_adjoint_pairs(part, g.ngp / gw::adjoint_tile(L.mode), p.e_v, p.nv, q.nvs, p.e_col,

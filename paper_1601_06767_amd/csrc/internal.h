@@ -250,11 +250,14 @@ int adjoint_tile(int mode);                          // G per partial sum in thi
 template <typename T>
 hipError_t launch_adjoint(const void* m, int npair, int ng, int ngp, const double2* gbar, double2* part,
                           hipStream_t st);
-// split-bf16 x3 form over float pair densities (ngp a multiple of 128); gsplit is scratch of
-// gbar_split_bytes(ng) for chibar split into bf16 row images
+// split-bf16 x3 form over float pair densities (ngp a multiple of 128): msplit holds the pair
+// densities split into bf16 row images (m_split_bytes(npair, ng), written by launch_split_m once
+// per chunk), gsplit is scratch of gbar_split_bytes(ng) for chibar split the same way
 size_t gbar_split_bytes(int ng);
-hipError_t launch_adjoint_bf16x3(const void* m, int npair, int ng, int ngp, const double2* gbar, void* gsplit,
-                                 double2* part, hipStream_t st);
+size_t m_split_bytes(int npair, int ng);
+hipError_t launch_split_m(const void* m, int npair, int ng, int ngp, void* msplit, hipStream_t st);
+hipError_t launch_adjoint_bf16x3(const void* m, const void* msplit, int npair, int ng, int ngp, const double2* gbar,
+                                 void* gsplit, double2* part, hipStream_t st);
 // ntg = ngp / adjoint_tile(mode) partial sums per pair
 hipError_t launch_adjoint_pairs(const double2* part, int ntg, const double* e_v, int nv, int nvs, const double* e_col,
                                 const double* n_col, int c0, int ncol, int cc, double omega, double delta, double* dx,
