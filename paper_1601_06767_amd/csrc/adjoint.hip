@@ -154,7 +154,6 @@ __global__ __launch_bounds__(256) void k_adjoint(const cx<T>* __restrict__ m, in
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int BT = 128;     // pairs and G per tile
 constexpr int BKS = 16;     // G' per stage
-constexpr int BROWA = 56;   // bf16 per LDS row: 48 used, padded so 8 rows read together hit distinct banks
 constexpr int BMI = 4, BNJ = 2;
 
 // chibar split once per call into the LDS image of its rows: for row G and block kb of 16 G',
@@ -210,26 +209,63 @@ __global__ void k_split_m(const float2* __restrict__ m, int npair, int ng, int n
   o[48 + i] = bf16_rne(im - bf16_val(ih));
 }
 
-// One workgroup per CU (162 registers): capped at 128 registers for a second one, it
-// spills and runs slower (measured 9.4 against 5.4 ms per 32k-pair launch at NG 2000; the
-// float32 kernel takes 9.2 ms).  Stages of 32 G' (two blocks of 16 between barriers) were
+// Both operands are staged straight from their split images into LDS by 16-byte direct loads
+// (one wave instruction fills 64 consecutive 16-byte LDS units) into two buffers, so the
+// staging takes no registers and no LDS store pass.  The buffers are separate arrays and the
+// stage loop is unrolled by two, so that the compiler sees that a stage's LDS reads cannot
+// alias the direct loads in flight into the other buffer and does not wait for them.  LDS units of one stage: the 128 M rows
+// of 8 pieces (piece c of row r at unit 8 r + (c ^ (r & 7))), then the 128 chibar rows of 12
+// (piece p of row r at UM + 12 r + (p ^ 2 ((r >> 2) & 1))); the XORs give every MFMA fragment
+// read of 16 rows x 4 pieces four accesses per bank group, the minimum.  Rows past npair or
+// ng load the last valid row: they only feed products that the epilogue drops.
+// One workgroup per CU.  Measured with register staging (the former form), per 32k-pair
+// launch at NG 2000: 5.4 ms converting chibar in every tile, 4.2 ms with it pre-split;
+// capped at 128 registers for a second workgroup it spilled (9.4 ms); stages of 32 G' were
 // no faster (5.6 ms).
+constexpr int UM = BT * 8, UG = BT * 12, UST = UM + UG;   // 16-byte LDS units per stage
+constexpr int UPL = UST / 512;                            // units per lane per stage
+static_assert(UPL * 512 == UST && UM % 64 == 0, "stage units must split into whole wave instructions");
 __global__ __launch_bounds__(512) void k_adjoint_bf16x3(const float2* __restrict__ m, int npair, int ng, int ngp,
                                                            const uint4* __restrict__ msplit,
                                                            const uint4* __restrict__ gsplit,
                                                            double2* __restrict__ part) {
-  __shared__ __align__(16) unsigned short s[2][2][BT][BROWA];   // [M | chibar][hi | lo][row][k']
+  __shared__ __align__(16) uint4 sa[UST];
+  __shared__ __align__(16) uint4 sb[UST];
   __shared__ double2 sred[4][BT];
   const int ntg = ngp / BT;
   const int p0 = (blockIdx.x / ntg) * BT;
   const int tg = blockIdx.x % ntg;
   const int q0 = tg * BT;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave / 4, wc = wave % 4;
   const int li = lane & 15, lg = lane >> 4;
-  // staging role: operand (M rows or chibar rows, wave-uniform)
-  const int op = __builtin_amdgcn_readfirstlane(tid / (2 * BT));
-  const int nrow = op == 0 ? npair - p0 : ng - q0;   // valid rows of this operand's tile
+  const int nkb = (ng + BKS - 1) / BKS;
+
+  // this lane's source of unit 64 (8 i + wave) + lane, for every stage (block kb adds
+  // 8 kb or 12 kb pieces; the block of 64 units, and so the operand, is wave-uniform)
+  const uint4* src[UPL];
+#pragma unroll
+  for (int i = 0; i < UPL; ++i) {
+    const int ub = 8 * i + wave;
+    const int u = 64 * ub + lane;
+    if (ub * 64 < UM) {
+      const int r = u / 8, c = (u % 8) ^ (r & 7);
+      src[i] = msplit + (size_t)min(p0 + r, npair - 1) * nkb * 8 + c;
+    } else {
+      const int u2 = u - UM, r = u2 / 12, pc = (u2 % 12) ^ (2 * ((r >> 2) & 1));
+      src[i] = gsplit + (size_t)min(q0 + r, ng - 1) * nkb * 12 + pc;
+    }
+  }
+  auto issue = [&](int kb, uint4* buf) {
+#pragma unroll
+    for (int i = 0; i < UPL; ++i) {
+      const int ub = 8 * i + wave;
+      const int step = ub * 64 < UM ? 8 : 12;
+      __builtin_amdgcn_global_load_lds((const void*)(src[i] + (size_t)kb * step),
+                                       (__attribute__((address_space(3))) void*)&buf[64 * ub], 16, 0, 0);
+    }
+  };
 
   f32x4 cre[BMI][BNJ], cim[BMI][BNJ];
 #pragma unroll
@@ -239,69 +275,32 @@ __global__ __launch_bounds__(512) void k_adjoint_bf16x3(const float2* __restrict
       cre[i][j] = f32x4{0, 0, 0, 0};
       cim[i][j] = f32x4{0, 0, 0, 0};
     }
-  // both operands arrive pre-split as bf16 row images: per stage, op 0 (M rows) copies 4 of
-  // the 128 x 8 16-byte pieces per thread, op 1 (chibar rows) 6 of the 128 x 12
-  const int nkb = (ng + BKS - 1) / BKS;
-  const int t1 = tid - 2 * BT;
-  uint4 pm[4];
-  uint4 pg[6];
-  auto fetch = [&](int k0) {
-    if (op == 0) {
-      const int kb = k0 / BKS;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int qv = tid + 2 * BT * i, row = qv / 8, c = qv % 8;
-        uint4 v = {0u, 0u, 0u, 0u};
-        if (row < nrow) v = msplit[((size_t)(p0 + row) * nkb + kb) * (MSPLIT / 8) + c];
-        pm[i] = v;
-      }
-    } else {
-      const int kb = k0 / BKS;
-#pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        const int qv = t1 + 2 * BT * i, row = qv / 12, c = qv % 12;
-        uint4 v = {0u, 0u, 0u, 0u};
-        if (row < nrow) v = gsplit[((size_t)(q0 + row) * nkb + kb) * (GSPLIT / 8) + c];
-        pg[i] = v;
-      }
-    }
-  };
-  fetch(0);
-  const int re_off = lg < 2 ? 8 * lg : 32 + 8 * (lg - 2);   // [br | -bi]
-  const int im_off = lg < 2 ? 16 + 8 * lg : 8 * (lg - 2);   // [bi | br]
-  for (int k0 = 0; k0 < ng; k0 += BKS) {
+  // chibar pieces of the two products: Re takes [br | -bi] (0, 1, 4, 5), Im [bi | br] (2, 3, 0, 1)
+  const int pre = lg < 2 ? lg : 2 + lg;
+  const int pim = lg < 2 ? 2 + lg : lg - 2;
+  auto stage = [&](int kb, const uint4* cur, uint4* next) {
+    // this wave's direct loads of stage kb have landed; the barrier makes everyone's visible
+    // and ends every wave's reads of the buffer that the next issue overwrites
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (op == 0) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int qv = tid + 2 * BT * i, row = qv / 8, c = qv % 8;
-        // pieces 0..3: hi [re | im], 4..7: lo
-        *(uint4*)&s[0][c / 4][row][8 * (c % 4)] = pm[i];
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        const int qv = t1 + 2 * BT * i, row = qv / 12, c = qv % 12;
-        // pieces 0..5: hi [re | im | -im], 6..11: lo
-        *(uint4*)&s[1][c / 6][row][8 * (c % 6)] = pg[i];
-      }
-    }
-    __syncthreads();
-    if (k0 + BKS < ng) fetch(k0 + BKS);
+    if (kb + 1 < nkb) issue(kb + 1, next);
+    const uint4* sm = cur;
+    const uint4* sg = cur + UM;
     bf16x8 xh[BMI], xl[BMI], reh[BNJ], rel[BNJ], imh[BNJ], iml[BNJ];
 #pragma unroll
     for (int i = 0; i < BMI; ++i) {
       const int r = 16 * BMI * wr + 16 * i + li;
-      xh[i] = *(const bf16x8*)&s[0][0][r][8 * lg];
-      xl[i] = *(const bf16x8*)&s[0][1][r][8 * lg];
+      xh[i] = __builtin_bit_cast(bf16x8, sm[8 * r + (lg ^ (r & 7))]);
+      xl[i] = __builtin_bit_cast(bf16x8, sm[8 * r + ((4 + lg) ^ (r & 7))]);
     }
 #pragma unroll
     for (int j = 0; j < BNJ; ++j) {
       const int r = 16 * BNJ * wc + 16 * j + li;
-      reh[j] = *(const bf16x8*)&s[1][0][r][re_off];
-      rel[j] = *(const bf16x8*)&s[1][1][r][re_off];
-      imh[j] = *(const bf16x8*)&s[1][0][r][im_off];
-      iml[j] = *(const bf16x8*)&s[1][1][r][im_off];
+      const int sw = 2 * ((r >> 2) & 1);
+      reh[j] = __builtin_bit_cast(bf16x8, sg[12 * r + (pre ^ sw)]);
+      rel[j] = __builtin_bit_cast(bf16x8, sg[12 * r + ((6 + pre) ^ sw)]);
+      imh[j] = __builtin_bit_cast(bf16x8, sg[12 * r + (pim ^ sw)]);
+      iml[j] = __builtin_bit_cast(bf16x8, sg[12 * r + ((6 + pim) ^ sw)]);
     }
 #pragma unroll
     for (int i = 0; i < BMI; ++i)
@@ -314,6 +313,11 @@ __global__ __launch_bounds__(512) void k_adjoint_bf16x3(const float2* __restrict
         cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[i], iml[j], cim[i][j], 0, 0, 0);
         cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl[i], imh[j], cim[i][j], 0, 0, 0);
       }
+  };
+  issue(0, sa);
+  for (int kb = 0; kb < nkb; kb += 2) {
+    stage(kb, sa, sb);
+    if (kb + 1 < nkb) stage(kb + 1, sb, sa);
   }
   // epilogue: per pair row, sum over this tile's G of conj(M[p][G]) Y[p][G]; result rows of
   // the bf16 16x16x32 MFMA are 4 (lane / 16) + r, columns lane % 16
