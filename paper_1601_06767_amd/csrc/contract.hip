@@ -119,16 +119,31 @@ __device__ __forceinline__ int range_len(int nk, int ksplit) {
 }
 
 // ---------------------------------------------------------------- f64 / f32 MFMA tile
+// A stage is KD pairs.  Its rows of M (1 KB per tile row in both precisions) go straight
+// into LDS by 16-byte direct loads (global_load_lds_dwordx4, one wave instruction per row),
+// into two buffers that are separate arrays, with the stage loop unrolled by two: the
+// compiler then sees that the reads of one buffer cannot alias the loads in flight into the
+// other and does not wait for them, and the staging holds no registers.  Two 8-pair
+// buffers take the LDS of one 16-pair stage, so three float64 workgroups still share a CU.
+// The weights scale the A fragments in registers; rows past the range load the range's last
+// row and get weight 0.
+constexpr int KD = 8;   // pairs per stage of the direct-load tile
 template <typename T, int TILE>
 __device__ void tile_mfma(const cx<T>* __restrict__ m, const double* __restrict__ w, int nk, int ngp, int ksplit,
                           double2* __restrict__ acc, int t, int ks) {
   using V = cx<T>;
   using A4 = typename Mfma<T>::acc;
   using G = TileGeo<TILE>;
-  constexpr int NT = 64 * G::NW;
+  constexpr int NW = G::NW;
   constexpr int MI = G::MI, NJ = G::NJ;
-  __shared__ V sA[KC][TILE];
-  __shared__ V sB[KC][TILE];
+  static_assert(TILE * sizeof(V) == 1024, "a tile row is one wave instruction of 64 x 16 bytes");
+  static_assert(KD % NW == 0 || NW % KD == 0, "rows must split evenly over the waves");
+  constexpr int RPW = 2 * KD / NW;   // rows (A then B) per wave per stage
+  static_assert(RPW * NW == 2 * KD && KD % RPW == 0 || KD % NW == 0, "rows per wave");
+  __shared__ __align__(16) V sA0[KD][TILE];
+  __shared__ __align__(16) V sB0[KD][TILE];
+  __shared__ __align__(16) V sA1[KD][TILE];
+  __shared__ __align__(16) V sB1[KD][TILE];
   int ti, tj;
   tile_coords(t, &ti, &tj);
   const int g0 = ti * TILE, h0 = tj * TILE;
@@ -136,10 +151,9 @@ __device__ void tile_mfma(const cx<T>* __restrict__ m, const double* __restrict_
   const int k0 = ks * per;
   const int k1 = min(nk, k0 + per);
   const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int wr = wave / G::WC, wc = wave % G::WC;
   const int li = lane & 15, lk = lane >> 4;
-  constexpr int NR = (KC * TILE) / NT;
 
   A4 cre[MI][NJ], cim[MI][NJ];
 #pragma unroll
@@ -149,44 +163,52 @@ __device__ void tile_mfma(const cx<T>* __restrict__ m, const double* __restrict_
       cre[i][j] = A4{0, 0, 0, 0};
       cim[i][j] = A4{0, 0, 0, 0};
     }
-  V pa[NR], pb[NR];
-  auto fetch = [&](int kk) {
-    const bool full = kk + KC <= k1;   // every stage but the last of a range
+  // row q = NW i + wave of a stage: A rows are q < KD, B rows the rest (i decides, since
+  // wave < NW and KD is a multiple of NW or the rows per wave)
+  auto issue = [&](int kk, V (*dA)[TILE], V (*dB)[TILE]) {
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const int e = tid + NT * r;
-      const int k = e / TILE, g = e % TILE;
-      V a{T(0), T(0)}, b{T(0), T(0)};
-      if (full || kk + k < k1) {
-        const size_t row = (size_t)(kk + k) * ngp;
-        a = m[row + g0 + g];
-        const V bb = m[row + h0 + g];
-        const T s = T(w[kk + k]);
-        b = V{bb.x * s, bb.y * s};
-      }
-      pa[r] = a;
-      pb[r] = b;
+    for (int i = 0; i < RPW; ++i) {
+      const int q = NW * i + wave;
+      const bool isb = NW * i >= KD;
+      const int k = isb ? q - KD : q;
+      const int row = min(kk + k, k1 - 1);
+      const char* src = (const char*)(m + (size_t)row * ngp + (isb ? h0 : g0)) + 16 * lane;
+      V* dst = isb ? &dB[k][0] : &dA[k][0];
+      __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
     }
   };
-  if (k0 < k1) fetch(k0);
-  for (int kk = k0; kk < k1; kk += KC) {
-    __syncthreads();
+  double wn[KD / 4];
+  auto load_w = [&](int kk) {
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const int e = tid + NT * r;
-      sA[e / TILE][e % TILE] = pa[r];
-      sB[e / TILE][e % TILE] = pb[r];
+    for (int s = 0; s < KD / 4; ++s) {
+      const int k = kk + 4 * s + lk;
+      wn[s] = k < k1 ? w[k] : 0.0;
     }
+  };
+  auto stage = [&](int kk, V (*cA)[TILE], V (*cB)[TILE], V (*nA)[TILE], V (*nB)[TILE]) {
+    // this wave's loads of the stage have landed; the barrier makes everyone's visible and
+    // ends every wave's reads of the buffer that the next issue overwrites
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (kk + KC < k1) fetch(kk + KC);
+    double wcur[KD / 4];
 #pragma unroll
-    for (int s = 0; s < KC / 4; ++s) {
+    for (int s = 0; s < KD / 4; ++s) wcur[s] = wn[s];
+    if (kk + KD < k1) {
+      issue(kk + KD, nA, nB);
+      load_w(kk + KD);
+    }
+#pragma unroll
+    for (int s = 0; s < KD / 4; ++s) {
       const int k = 4 * s + lk;
+      const T ws = T(wcur[s]);
       V a[MI], b[NJ];
 #pragma unroll
-      for (int i = 0; i < MI; ++i) a[i] = sA[k][16 * MI * wr + 16 * i + li];
+      for (int i = 0; i < MI; ++i) {
+        const V x = cA[k][16 * MI * wr + 16 * i + li];
+        a[i] = V{x.x * ws, x.y * ws};
+      }
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) b[j] = sB[k][16 * NJ * wc + 16 * j + li];
+      for (int j = 0; j < NJ; ++j) b[j] = cB[k][16 * NJ * wc + 16 * j + li];
 #pragma unroll
       for (int i = 0; i < MI; ++i)
 #pragma unroll
@@ -197,6 +219,14 @@ __device__ void tile_mfma(const cx<T>* __restrict__ m, const double* __restrict_
           cim[i][j] = Mfma<T>::run(-a[i].x, b[j].y, cim[i][j]);
         }
     }
+  };
+  if (k0 < k1) {
+    issue(k0, sA0, sB0);
+    load_w(k0);
+  }
+  for (int kk = k0; kk < k1; kk += 2 * KD) {
+    stage(kk, sA0, sB0, sA1, sB1);
+    if (kk + KD < k1) stage(kk + KD, sA1, sB1, sA0, sB0);
   }
   store_tile<MI, NJ>(acc + (size_t)ks * ngp * ngp, ngp, g0 + 16 * MI * wr, h0 + 16 * NJ * wc, cre, cim, li, lk,
                      std::is_same<T, double>::value);
@@ -469,51 +499,37 @@ hipError_t launch_weights(const double* e_v, int v0, int nv_valid, int nvs, cons
 
 int contract_tile(int mode) { return mode == 0 ? 64 : 128; }
 
-namespace {
-template <int TILE>
-hipError_t contract_grid(int mode, const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
-                         hipStream_t st) {
-  constexpr int NT = 64 * TileGeo<TILE>::NW;
-  const int nt = ngp / TILE;
+// Tiles per mode (contract_tile): 64 in float64, 128 in float32 and split-bf16 x3; only
+// these forms are built.
+hipError_t launch_contract(int mode, const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
+                           hipStream_t st) {
+  const int tile = contract_tile(mode);
+  if (ngp % tile != 0) return hipErrorInvalidValue;
+  const int nt = ngp / tile;
   const int ntl = nt * (nt + 1) / 2;
   const int nb = ntl * ksplit;
   if (mode == 0)
-    k_contract<0, TILE><<<nb, NT, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
+    k_contract<0, 64><<<nb, 64 * TileGeo<64>::NW, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
   else if (mode == 1)
-    k_contract<1, TILE><<<nb, NT, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
+    k_contract<1, 128><<<nb, 64 * TileGeo<128>::NW, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
   else
-    k_contract<2, TILE><<<nb, NT, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
+    k_contract<2, 128><<<nb, 64 * TileGeo<128>::NW, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
   return hipGetLastError();
-}
-
-template <int TILE>
-hipError_t contract_batch(int mode, const ContractBatch& bt, int* counter, int grid, bool alone, hipStream_t st) {
-  constexpr int NT = 64 * TileGeo<TILE>::NW;
-  if (mode == 0)
-    k_contract_batch<0, TILE><<<grid, NT, 0, st>>>(bt, counter);
-  else if (mode == 1)
-    k_contract_batch<1, TILE><<<grid, NT, 0, st>>>(bt, counter);
-  else if (alone)
-    k_contract_batch<2, TILE, 4><<<grid, NT, 0, st>>>(bt, counter);
-  else
-    k_contract_batch<2, TILE><<<grid, NT, 0, st>>>(bt, counter);
-  return hipGetLastError();
-}
-}  // namespace
-
-hipError_t launch_contract(int mode, const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
-                           hipStream_t st) {
-  if (ngp % contract_tile(mode) != 0) return hipErrorInvalidValue;
-  return contract_tile(mode) == 64 ? contract_grid<64>(mode, m, w, nk, ngp, ksplit, acc, st)
-                                   : contract_grid<128>(mode, m, w, nk, ngp, ksplit, acc, st);
 }
 
 hipError_t launch_contract_batch(int mode, const ContractBatch& bt, int* counter, int grid, bool alone,
                                  hipStream_t st) {
   for (int b = 0; b < bt.nprob; ++b)
     if (bt.p[b].ngp % contract_tile(mode) != 0) return hipErrorInvalidValue;
-  return contract_tile(mode) == 64 ? contract_batch<64>(mode, bt, counter, grid, alone, st)
-                                   : contract_batch<128>(mode, bt, counter, grid, alone, st);
+  if (mode == 0)
+    k_contract_batch<0, 64><<<grid, 64 * TileGeo<64>::NW, 0, st>>>(bt, counter);
+  else if (mode == 1)
+    k_contract_batch<1, 128><<<grid, 64 * TileGeo<128>::NW, 0, st>>>(bt, counter);
+  else if (alone)
+    k_contract_batch<2, 128, 4><<<grid, 64 * TileGeo<128>::NW, 0, st>>>(bt, counter);
+  else
+    k_contract_batch<2, 128><<<grid, 64 * TileGeo<128>::NW, 0, st>>>(bt, counter);
+  return hipGetLastError();
 }
 
 hipError_t launch_finalize(const double2* accA, const double2* accB, int ksplit, int ng, int ngp, double2* chi,
