@@ -7,8 +7,9 @@
 //
 // One work item = one 64 x 64 lower tile (G, G') of one job (q-point, frequency, part)
 // over one of ksplit ranges of pairs; each item owns a float64 partial sum (no
-// atomics, fixed summation order).  The next stage of pairs is fetched into registers
-// while the current one runs on MFMA.  Items are run either as a plain grid (one
+// atomics, fixed summation order).  The next stage of pairs is loaded (straight into LDS
+// in float64 / float32, into registers in split-bf16) while the current one runs on MFMA.
+// Items are run either as a plain grid (one
 // job) or by a persistent grid that pulls items from a counter, ordered so that the
 // problems with the largest dielectric spheres come first.
 //
@@ -137,9 +138,8 @@ __device__ void tile_mfma(const cx<T>* __restrict__ m, const double* __restrict_
   constexpr int NW = G::NW;
   constexpr int MI = G::MI, NJ = G::NJ;
   static_assert(TILE * sizeof(V) == 1024, "a tile row is one wave instruction of 64 x 16 bytes");
-  static_assert(KD % NW == 0 || NW % KD == 0, "rows must split evenly over the waves");
   constexpr int RPW = 2 * KD / NW;   // rows (A then B) per wave per stage
-  static_assert(RPW * NW == 2 * KD && KD % RPW == 0 || KD % NW == 0, "rows per wave");
+  static_assert(RPW * NW == 2 * KD, "the 2 KD rows of a stage must split evenly over the waves");
   __shared__ __align__(16) V sA0[KD][TILE];
   __shared__ __align__(16) V sB0[KD][TILE];
   __shared__ __align__(16) V sA1[KD][TILE];
@@ -163,13 +163,12 @@ __device__ void tile_mfma(const cx<T>* __restrict__ m, const double* __restrict_
       cre[i][j] = A4{0, 0, 0, 0};
       cim[i][j] = A4{0, 0, 0, 0};
     }
-  // row q = NW i + wave of a stage: A rows are q < KD, B rows the rest (i decides, since
-  // wave < NW and KD is a multiple of NW or the rows per wave)
+  // row q = NW i + wave of a stage (wave-uniform): A rows are q < KD, B rows the rest
   auto issue = [&](int kk, V (*dA)[TILE], V (*dB)[TILE]) {
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
       const int q = NW * i + wave;
-      const bool isb = NW * i >= KD;
+      const bool isb = q >= KD;
       const int k = isb ? q - KD : q;
       const int row = min(kk + k, k1 - 1);
       const char* src = (const char*)(m + (size_t)row * ngp + (isb ? h0 : g0)) + 16 * lane;
