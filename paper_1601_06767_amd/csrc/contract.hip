@@ -5,13 +5,12 @@
 // H_x = sum_p x_p M_p M_p^H Hermitian, so every job is a Hermitian rank-k update with
 // real per-pair weights, computed for the lower tiles only and mirrored at the end.
 //
-// One work item = one 64 x 64 lower tile (G, G') of one job (q-point, frequency, part)
-// over one of ksplit ranges of pairs; each item owns a float64 partial sum (no
-// atomics, fixed summation order).  The next stage of pairs is loaded (straight into LDS
-// in float64 / float32, into registers in split-bf16) while the current one runs on MFMA.
-// Items are run either as a plain grid (one
-// job) or by a persistent grid that pulls items from a counter, ordered so that the
-// problems with the largest dielectric spheres come first.
+// One work item = one lower tile (G, G') of one job (q-point, frequency, part), 64 x 64 in
+// float64 and 128 x 128 otherwise, over one of ksplit ranges of pairs; each item owns a
+// float64 partial sum (no atomics, fixed summation order).  The next stage of pairs is
+// loaded (straight into LDS in float64 / float32, into registers in split-bf16) while the
+// current one runs on MFMA.  A persistent grid pulls the items from a counter, ordered so
+// that the problems with the largest dielectric spheres come first.
 //
 // MFMA forms: f64 / f32 16x16x4 with Re += a.re b.re + a.im b.im and
 // Im += a.im b.re - a.re b.im (b = w M(G')), and split-bf16 x3 (see below).
@@ -395,18 +394,10 @@ __device__ __forceinline__ void run_item(const void* m, const double* w, int nk,
     tile_bf16x3<TILE>(m, w, nk, ngp, ksplit, acc, t, ks);
 }
 
-// Items are ordered pair-range major (all tiles of range 0, then range 1, ...): the
-// workgroups in flight read the same few thousand rows of M, which stay in cache.
-template <int MODE, int TILE>
-__global__ __launch_bounds__(64 * TileGeo<TILE>::NW) void k_contract(const void* __restrict__ m,
-                                                                    const double* __restrict__ w, int nk, int ngp,
-                                                                    int ksplit, int ntl, double2* __restrict__ acc) {
-  run_item<MODE, TILE>(m, w, nk, ngp, ksplit, acc, blockIdx.x % ntl, blockIdx.x / ntl);
-}
-
 // Persistent grid over all items of a batch; items of problem b occupy
 // [item0[b], item0[b+1]) and decode as (job, split, tile), job = w_index * nparts + part,
-// tile fastest (pair-range major, as above).  MINW = waves per SIMD the registers must
+// tile fastest: pair-range major (all tiles of range 0, then range 1, ...), so that the
+// workgroups in flight read the same few thousand rows of M, which stay in cache.  MINW = waves per SIMD the registers must
 // allow: 4 holds two 512-thread split-bf16 workgroups per CU (128 registers), used when
 // the contraction has the CUs to itself; 1 leaves registers for the pair kernels that run
 // beside it on the other stream.
@@ -500,22 +491,6 @@ int contract_tile(int mode) { return mode == 0 ? 64 : 128; }
 
 // Tiles per mode (contract_tile): 64 in float64, 128 in float32 and split-bf16 x3; only
 // these forms are built.
-hipError_t launch_contract(int mode, const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
-                           hipStream_t st) {
-  const int tile = contract_tile(mode);
-  if (ngp % tile != 0) return hipErrorInvalidValue;
-  const int nt = ngp / tile;
-  const int ntl = nt * (nt + 1) / 2;
-  const int nb = ntl * ksplit;
-  if (mode == 0)
-    k_contract<0, 64><<<nb, 64 * TileGeo<64>::NW, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
-  else if (mode == 1)
-    k_contract<1, 128><<<nb, 64 * TileGeo<128>::NW, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
-  else
-    k_contract<2, 128><<<nb, 64 * TileGeo<128>::NW, 0, st>>>(m, w, nk, ngp, ksplit, ntl, acc);
-  return hipGetLastError();
-}
-
 hipError_t launch_contract_batch(int mode, const ContractBatch& bt, int* counter, int grid, bool alone,
                                  hipStream_t st) {
   for (int b = 0; b < bt.nprob; ++b)

@@ -178,10 +178,8 @@ hipError_t launch_weights(const double* e_v, int v0, int nv_valid, int nvs, cons
                           int c0, int nc_valid, int ncs, double omega, double delta, int nparts, double* w,
                           hipStream_t st);
 
-// acc[ks][G][G'] (lower tiles) += sum_k m[k][G] w[k] conj(m[k][G']);  mode 0 f64, 1 f32, 2 bf16x3
-hipError_t launch_contract(int mode, const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
-                           hipStream_t st);
-// Batched contraction: per problem, nomega * nparts jobs (job j uses w + j nk and
+// Contraction acc[ks][G][G'] (lower tiles) += sum_k m[k][G] w[k] conj(m[k][G']) (mode 0 f64,
+// 1 f32, 2 bf16x3), batched: per problem, nomega * nparts jobs (job j uses w + j nk and
 // acc + j ksplit ngp^2), each split into ntl lower tiles x ksplit pair ranges; one
 // persistent launch pulls the items from *counter (zeroed beforehand).
 struct ContractProb {
