@@ -221,7 +221,9 @@ __global__ void k_split_m(const float2* __restrict__ m, int npair, int ng, int n
 // One workgroup per CU.  Measured with register staging (the former form), per 32k-pair
 // launch at NG 2000: 5.4 ms converting chibar in every tile, 4.2 ms with it pre-split;
 // capped at 128 registers for a second workgroup it spilled (9.4 ms); stages of 32 G' were
-// no faster (5.6 ms).
+// no faster (5.6 ms).  A third buffer (loads two stages ahead) gains nothing as written: the
+// compiler counts the direct loads as pending LDS writes and waits for all of them at every
+// workgroup barrier, even one fenced for LDS only.
 constexpr int UM = BT * 8, UG = BT * 12, UST = UM + UG;   // 16-byte LDS units per stage
 constexpr int UPL = UST / 512;                            // units per lane per stage
 static_assert(UPL * 512 == UST && UM % 64 == 0, "stage units must split into whole wave instructions");
