@@ -24,9 +24,9 @@ from .chi0 import (  # noqa: F401
     speedup_factor, alias_free,
 )
 from .dielectric import eps_matrix, eps_inv, eps_inv_static_cholesky, eps_inf  # noqa: F401
-from .sigma import coh_kernel, sigma_coh_static, sigma_coh_complete_set  # noqa: F401
+from .sigma import coh_kernel, sigma_coh_static, sigma_coh_complete_set, gpp_coh_kernel, sigma_coh_gpp  # noqa: F401
 from .kpoints import kq_map, pair_density_kq, chi0_ksum, grad_chi0_ksum_energies  # noqa: F401
 from .gpp import gpp_modes, gpp_eps_inv  # noqa: F401
 from .grad import (  # noqa: F401
-    grad_eps_inv, grad_weights_static, grad_weights_dynamic, grad_chi0_energies, head_block_loss,
+    grad_eps_inv, grad_weights_dynamic, grad_chi0_energies, head_block_loss,
 )

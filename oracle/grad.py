@@ -46,11 +46,6 @@ def grad_eps_inv(z: np.ndarray, vcoul: np.ndarray, zbar: np.ndarray) -> np.ndarr
     return vcoul[:, None] * (zh @ zbar @ zh)
 
 
-def grad_weights_static(x: np.ndarray, n: np.ndarray):
-    """(dw/dx, dw/dn) of the static weight w = n/x."""
-    return -n / (x * x), 1.0 / x
-
-
 def grad_weights_dynamic(x: np.ndarray, n: np.ndarray, omega: float, delta: float):
     """(dw/dx, dw/dn) of w = n/2 [1/(x - w + i d) + 1/(x + w + i d)]."""
     a = 1.0 / (x - omega + 1j * delta)

@@ -1,4 +1,22 @@
-"""Oracle: the static limit of the COH self-energy of Eq. (sigmach) (test infrastructure only).
+"""Oracle: the COH self-energy of Eq. (sigmach) (test infrastructure only).
+
+Two forms.  sigma_coh_gpp evaluates Eq. (sigmach) with the plasmon-pole eps^-1(w) of the
+model the paper uses (oracle/gpp.py): each element of [eps^r]^-1 - [eps^a]^-1 on E' > 0 is
+-i pi (Omega^2 / wt) delta(E' - wt) as the broadening of the pole goes to zero, so the
+E' integral leaves one pole term per element,
+
+    <n|Sigma_COH(E)|n'> = 1/2 sum_{n''} w_{n''} sum_{G G'} M_{n n''}(G)
+                          Omega^2_{GG'} / (wt_{GG'} (E - E_{n''} - wt_{GG'} + i delta)) v(G')
+                          conj(M_{n' n''}(G')),
+
+with the band energy E_{n''} in the denominator (for a window column its energy E_i, weight
+w = g(E_i) dE_i of Eq. (energyintegration)).  wt is the principal square root of wt^2 (for a
+complex wt^2 of an off-diagonal element the expression is taken as written, its analytic
+continuation); elements without a pole (unscreened) add nothing.  Pinned in
+tests/test_oracle.py by a quadrature of Eq. (sigmach)'s E' integral as printed, by its
+E - E_{n''} -> 0 limit (the static form below) and by the homogeneous electron gas.
+
+sigma_coh_static is the static limit.
 
 With the energy denominator of Eq. (sigmach) taken as -E' (the static limit), the
 frequency integral of the retarded-minus-advanced inverse dielectric function gives, by
@@ -41,10 +59,8 @@ def sigma_coh_static(coef_n: np.ndarray, coef_cols: np.ndarray, gvec_wf: np.ndar
     psi_c = psi_real_space(coef_cols, gvec_wf, nd)
     m = pair_density_fft(psi_n, psi_c, gvec_chi)                  # (Ns, Nc, ng): M_{n n''}(G)
     a = coh_kernel(eps_inv_mat, vcoul)
-    z = np.conj(m) @ a.T                                          # z[n', n'', G] = sum_G' A_{GG'} conj(M_{n' n''}(G'))
-    ns, nc, ng = m.shape
-    x = (m * w[None, :, None]).reshape(ns, nc * ng)               # w_{n''} M_{n n''}(G), (n'', G) flattened
-    return 0.5 * (x @ z.reshape(ns, nc * ng).T)
+    # 1/2 sum_{n''} w_{n''} sum_{G G'} M_{n n''}(G) A_{G G'} conj(M_{n' n''}(G')), as written
+    return 0.5 * np.einsum("c,ncg,gh,pch->np", w, m, a, np.conj(m), optimize=True)
 
 
 def sigma_coh_complete_set(coef_n: np.ndarray, gvec_wf: np.ndarray, gvec_chi: np.ndarray, eps_inv_mat: np.ndarray,
@@ -64,3 +80,30 @@ def sigma_coh_complete_set(coef_n: np.ndarray, gvec_wf: np.ndarray, gvec_chi: np
     corr = np.einsum("ngk,phk->npgh", np.conj(cs), cs)            # sum_g conj(c_n(g+G)) c_n'(g+G')
     a = coh_kernel(eps_inv_mat, vcoul)
     return 0.5 * np.einsum("gh,npgh->np", a, corr)
+
+
+def gpp_coh_kernel(om2: np.ndarray, wt2: np.ndarray, vcoul: np.ndarray, x: complex) -> np.ndarray:
+    """A_GG'(x) = Omega^2_GG' v(G') / (wt_GG' (x - wt_GG')), x = E - E_{n''} + i delta; zero where
+    the element has no pole (wt^2 = inf)."""
+    pole = np.isfinite(wt2)
+    wt = np.sqrt(wt2[pole].astype(np.complex128))                  # principal branch
+    a = np.zeros(om2.shape, dtype=np.complex128)
+    a[pole] = om2[pole] / (wt * (x - wt))
+    return a * vcoul[None, :]
+
+
+def sigma_coh_gpp(coef_n: np.ndarray, coef_cols: np.ndarray, e_cols: np.ndarray, gvec_wf: np.ndarray,
+                  gvec_chi: np.ndarray, nd: Sequence[int], om2: np.ndarray, wt2: np.ndarray, vcoul: np.ndarray,
+                  energies: Sequence[float], delta: float = 0.0, n_col: Optional[np.ndarray] = None) -> np.ndarray:
+    """(nE, Ns, Ns): <n|Sigma_COH(E)|n'> of Eq. (sigmach) with the plasmon-pole model, at each E of
+    energies, for the states coef_n over the columns coef_cols (energies e_cols, weights n_col)."""
+    nd = tuple(int(x) for x in nd)
+    w = np.ones(coef_cols.shape[0]) if n_col is None else np.asarray(n_col, dtype=np.float64)
+    m = pair_density_fft(psi_real_space(coef_n, gvec_wf, nd), psi_real_space(coef_cols, gvec_wf, nd), gvec_chi)
+    ns = m.shape[0]
+    out = np.zeros((len(energies), ns, ns), dtype=np.complex128)
+    for j, e in enumerate(energies):
+        for c in range(m.shape[1]):
+            a = gpp_coh_kernel(om2, wt2, vcoul, e - e_cols[c] + 1j * delta)
+            out[j] += 0.5 * w[c] * (m[:, c, :] @ a @ np.conj(m[:, c, :]).T)
+    return out

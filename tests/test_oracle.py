@@ -19,6 +19,18 @@ from oracle import grad as og
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
+def assert_fd(pairs, label, tol=1e-6):
+    """Central differences against analytic gradients, relative to the largest tested component
+    of the gradient (no absolute floor): max_i |fd_i - g_i| <= tol * max_i |g_i|."""
+    fd = np.array([a for a, _ in pairs], dtype=np.float64)
+    g = np.array([b for _, b in pairs], dtype=np.float64)
+    scale = np.abs(g).max()
+    err = float(np.abs(fd - g).max() / scale)
+    print(f"{label}: max|fd - g| / max|g| = {err:.1e} over {len(g)} components (max|g| = {scale:.2e})")
+    assert scale > 0 and err <= tol, (label, err, fd, g)
+    return err
+
+
 def tiny(nd=12, rw=3, ng=27, nv=3, nc=5, seed=7):
     gw = synth.wf_sphere(nd, rw)
     cell = np.eye(3) * 7.0
@@ -319,6 +331,42 @@ def test_eps_inv_routes_agree_and_properties():
     assert oracle.eps_inf(z) == pytest.approx(1.0)       # head row/column of chi0 vanish
 
 
+def _chi0_with_head(mix=0.05, seed=7):
+    # valence states at k+q that are not orthogonal to the conduction states at k (their own
+    # set, as at a q-point away from Gamma): M_vc(G=0) = <v,k+q|c,k> != 0, so the head row and
+    # column of chi0 do not vanish and [eps^-1]_00 differs from 1
+    t = tiny(nv=4, nc=9, seed=seed)
+    cvq = synth.orthonormalize(t["cv"] + mix * t["cc"][:4])
+    chi = oracle.chi0_bands(cvq, t["e_v"], t["cc"], t["e_c"], t["gw"], t["gc"], t["nd"])[0]
+    return chi, synth.coulomb(t["gc"], (0.01, 0, 0), t["cell"])
+
+
+def test_eps_inf_is_the_reciprocal_of_the_inverse_head():
+    # Table 3's eps_inf = 1/[eps^-1]_00.  The (0,0) entry of an inverse is the reciprocal of the
+    # Schur complement eps_00 - eps_0R eps_RR^-1 eps_R0 (block elimination), computed here by a
+    # linear solve on the remaining block, without forming eps^-1
+    chi, v = _chi0_with_head()
+    assert abs(chi[0, 0]) > 1e-3 * np.abs(chi).max() and np.abs(chi[0, 1:]).max() > 0
+    eps = oracle.eps_matrix(chi, v)
+    schur = eps[0, 0] - eps[0, 1:] @ np.linalg.solve(eps[1:, 1:], eps[1:, 0])
+    assert abs(schur.imag) < 1e-12 * abs(schur)
+    for z in (oracle.eps_inv(chi, v), oracle.eps_inv_static_cholesky(chi, v)):
+        assert oracle.eps_inf(z) == pytest.approx(schur.real, rel=1e-12)
+    # eps~ = I - v^1/2 chi0 v^1/2 >= I and the Schur complement of a block never exceeds the
+    # diagonal entry: 1 < eps_inf < eps_00 = 1 - v_0 chi0_00 (the head couples to the rest)
+    einf = oracle.eps_inf(oracle.eps_inv(chi, v))
+    assert 1.0 < einf < eps[0, 0].real and einf < 0.999 * eps[0, 0].real
+    # a head decoupled from the other G-vectors: eps_inf is exactly the scalar 1 - v_0 chi0_00
+    chi_d = chi.copy()
+    chi_d[0, 1:] = 0.0
+    chi_d[1:, 0] = 0.0
+    assert oracle.eps_inf(oracle.eps_inv(chi_d, v)) == pytest.approx(1.0 - v[0] * chi_d[0, 0].real, rel=1e-13)
+    # head index other than 0: a permuted sphere gives the same value
+    perm = np.roll(np.arange(len(v)), 3)
+    zp = oracle.eps_inv(chi[np.ix_(perm, perm)], v[perm])
+    assert oracle.eps_inf(zp, head=int(np.nonzero(perm == 0)[0][0])) == pytest.approx(einf, rel=1e-12)
+
+
 # ---------------------------------------------------------------- gradients
 def _loss_static(t, v, head, e_v, e_c, n_c):
     chi = oracle.chi0_bands(t["cv"], e_v, t["cc"], e_c, t["gw"], t["gc"], t["nd"], n_col=n_c)[0]
@@ -337,6 +385,7 @@ def test_gradients_static_match_finite_differences():
                                        n_col=n_c)
     h = 1e-5
     for arr, g, name in ((e_v, gv, "ev"), (e_c, gc, "ec"), (n_c, gn, "n")):
+        pairs = []
         for i in range(len(arr)):
             p, m = arr.copy(), arr.copy()
             p[i] += h
@@ -345,8 +394,8 @@ def test_gradients_static_match_finite_differences():
             key = {"ev": "e_v", "ec": "e_c", "n": "n_c"}[name]
             lp = _loss_static(t, v, head, **{**kw, key: p})
             lm = _loss_static(t, v, head, **{**kw, key: m})
-            fd = (lp - lm) / (2 * h)
-            assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])), (name, i, fd, g[i])
+            pairs.append(((lp - lm) / (2 * h), g[i]))
+        assert_fd(pairs, f"static dL/d{name}")
 
 
 def test_gradients_dynamic_match_finite_differences():
@@ -363,18 +412,20 @@ def test_gradients_dynamic_match_finite_differences():
     gv, gc, _ = og.grad_chi0_energies(t["cv"], t["e_v"], t["cc"], t["e_c"], t["gw"], t["gc"], t["nd"], bmat,
                                       omegas=om, delta=d)
     h = 1e-6
+    pairs = []
     for i in range(2):
         p, m = t["e_v"].copy(), t["e_v"].copy()
         p[i] += h
         m[i] -= h
-        fd = (loss(p, t["e_c"]) - loss(m, t["e_c"])) / (2 * h)
-        assert abs(fd - gv[i]) <= 1e-6 * max(1.0, abs(gv[i]))
+        pairs.append(((loss(p, t["e_c"]) - loss(m, t["e_c"])) / (2 * h), gv[i]))
+    assert_fd(pairs, "dynamic dL/dE_v")
+    pairs = []
     for i in range(4):
         p, m = t["e_c"].copy(), t["e_c"].copy()
         p[i] += h
         m[i] -= h
-        fd = (loss(t["e_v"], p) - loss(t["e_v"], m)) / (2 * h)
-        assert abs(fd - gc[i]) <= 1e-6 * max(1.0, abs(gc[i]))
+        pairs.append(((loss(t["e_v"], p) - loss(t["e_v"], m)) / (2 * h), gc[i]))
+    assert_fd(pairs, "dynamic dL/dE_c")
 
 
 def test_grad_eps_inv_general_matches_finite_differences():
@@ -389,13 +440,14 @@ def test_grad_eps_inv_general_matches_finite_differences():
 
     g = og.grad_eps_inv(oracle.eps_inv(chi, v), v, bmat)
     h = 1e-6
+    pairs = []
     for (i, j) in ((0, 0), (1, 4), (5, 2)):
         for unit, part in ((1.0, np.real), (1j, np.imag)):
             p, m = chi.copy(), chi.copy()
             p[i, j] += unit * h
             m[i, j] -= unit * h
-            fd = (loss(p) - loss(m)) / (2 * h)
-            assert abs(fd - part(g[i, j])) < 1e-7
+            pairs.append(((loss(p) - loss(m)) / (2 * h), part(g[i, j])))
+    assert_fd(pairs, "dL/dchi0 through eps^-1")
 
 
 @pytest.mark.parametrize("om,d", [([0.0], 0.0), ([0.05, 0.4], 0.01)])
@@ -420,6 +472,7 @@ def test_coefficient_gradients_match_finite_differences(om, d):
     assert gv.shape == t["cv"].shape and gcc.shape == t["cc"].shape
     assert np.all(gcc[2] == 0)          # row 2 feeds no column
     h = 1e-6
+    pairs = []
     for which, idx in (("v", (0, 3)), ("v", (1, 20)), ("c", (1, 0)), ("c", (3, 11)), ("c", (0, 7))):
         for unit, part in ((1.0, np.real), (1j, np.imag)):
             cv_p, cv_m, cc_p, cc_m = t["cv"].copy(), t["cv"].copy(), t["cc"].copy(), t["cc"].copy()
@@ -431,8 +484,8 @@ def test_coefficient_gradients_match_finite_differences(om, d):
                 cc_p[idx] += unit * h
                 cc_m[idx] -= unit * h
                 want = part(gcc[idx])
-            fd = (loss(cv_p, cc_p) - loss(cv_m, cc_m)) / (2 * h)
-            assert abs(fd - want) <= 1e-6 * max(1.0, abs(want)), (which, idx, fd, want)
+            pairs.append(((loss(cv_p, cc_p) - loss(cv_m, cc_m)) / (2 * h), want))
+    assert_fd(pairs, "dL/dcoefficients")
 
 
 # ---------------------------------------------------------------- static COH self-energy
@@ -572,6 +625,90 @@ def test_gpp_f_sum_rule():
     assert abs(integral - om2[a, a].real) < 2e-2 * abs(om2[a, a].real), (integral, om2[a, a])
 
 
+def _double_commutator_weights(cell, q, gc, coef, gw):
+    """Brute-force <[[T, rho_k], rho_k'^+]> (k = q+G, k' = q+G', rho_k = sum_i e^{-i k.r_i}) for
+    doubly occupied orbitals phi_v = sum_g c_v(g) e^{i g.r} / sqrt(Omega), with the kinetic
+    energy T, e^{-i k.r} and e^{i k'.r} as explicit sparse matrices on a plane-wave basis that
+    holds the Gamma, +q and -q sectors of a Miller box around the orbitals."""
+    import scipy.sparse as sp
+    b = synth.recip(cell)
+    q = np.asarray(q, dtype=np.float64)
+    rad = int(np.abs(gw).max() + np.abs(gc).max() + 1)
+    a = np.arange(-rad, rad + 1)
+    box = np.stack(np.meshgrid(a, a, a, indexing="ij"), -1).reshape(-1, 3)
+    nb = len(box)
+    shift = {0: np.zeros(3), 1: q, -1: -q}                       # sector s holds wavevectors (m + s q) b
+    key = {(s, tuple(m)): s_i * nb + i for s_i, s in enumerate((0, 1, -1)) for i, m in enumerate(box.tolist())}
+    kvec = np.concatenate([(box + shift[s]) @ b for s in (0, 1, -1)])
+    tmat = sp.diags(0.5 * (kvec * kvec).sum(1))
+
+    def plane_wave_factor(frac):
+        # e^{i frac.b.r} maps |(m + s q) b> to |(m + s q + frac) b>; frac = +-(q + G)
+        rows, cols = [], []
+        for (s, m), i in key.items():
+            t = np.asarray(m, dtype=np.float64) + s * q + frac
+            for s_try in (0, 1, -1):
+                mm = t - s_try * q
+                if np.allclose(mm, np.rint(mm), atol=1e-9):
+                    j = key.get((s_try, tuple(int(x) for x in np.rint(mm))))
+                    if j is not None:
+                        rows.append(j)
+                        cols.append(i)
+                    break
+        return sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(3 * nb, 3 * nb))
+
+    phis = np.zeros((coef.shape[0], 3 * nb), dtype=np.complex128)
+    for j, g in enumerate(gw.tolist()):
+        phis[:, key[(0, tuple(g))]] = coef[:, j]
+    ng = len(gc)
+    out = np.zeros((ng, ng), dtype=np.complex128)
+    amat = [plane_wave_factor(-(q + g)) for g in gc.astype(np.float64)]      # e^{-i k.r}
+    bmat = [plane_wave_factor(q + g) for g in gc.astype(np.float64)]         # e^{+i k'.r}
+    for i in range(ng):
+        for j in range(ng):
+            A, B = amat[i], bmat[j]
+            c = tmat @ A @ B - A @ tmat @ B - B @ tmat @ A + B @ A @ tmat
+            out[i, j] = 2.0 * np.einsum("vi,vi->", np.conj(phis), (c @ phis.T).T)   # both spins
+    return out
+
+
+def test_gpp_weights_are_the_f_sum_double_commutator():
+    # The model's pole weights come from the f-sum rule: for electrons with kinetic energy T and
+    # a local potential, Omega^2_GG' = -(4 pi / |q+G|^2) <[[T, rho_{q+G}], rho_{q+G'}^+]> / Omega.
+    # The double commutator is evaluated by brute force for three random orthonormal orbitals in
+    # a sheared cell at a general q, and the density handed to the model is their |phi|^2
+    # sampled on a real-space grid and Fourier transformed.  This fixes the off-diagonal
+    # structure: which of q+G, q+G' normalises, the dot product, and G - G' against G' - G.
+    cell = np.array([[7.0, 0.0, 0.0], [0.6, 7.6, 0.0], [0.0, -0.4, 8.1]])
+    q = (0.13, -0.07, 0.21)
+    gc = synth.chi_sphere(9, q, cell)
+    gw = synth.wf_sphere(8, 2)
+    coef = synth.orthonormalize(synth.gaussian_columns(99, 31, range(3), len(gw)))
+    vol = abs(np.linalg.det(cell))
+    nd = 12
+    u = oracle.psi_real_space(coef, gw, (nd,) * 3)                 # sum_g c(g) e^{ig.r}
+    rho_r = 2.0 * (np.abs(u) ** 2).sum(0) / vol
+    rho_g = np.fft.fftn(rho_r) / nd ** 3                           # rho(r) = sum_K rho(K) e^{iK.r}
+    rho = lambda n: rho_g[n[0] % nd, n[1] % nd, n[2] % nd]
+    rho0 = rho_g[0, 0, 0].real
+    assert rho0 == pytest.approx(6.0 / vol, rel=1e-13)
+    z = np.eye(len(gc)) * 0.5                                       # wt^2 is not compared here
+    om2, _ = oracle.gpp_modes(z, gc, q, synth.recip(cell), rho, rho0)
+    dc = _double_commutator_weights(cell, q, gc, coef, gw)
+    k = (gc + np.asarray(q)) @ synth.recip(cell)
+    want = -4.0 * np.pi / (k * k).sum(1)[:, None] * dc / vol
+    scale = np.abs(want).max()
+    assert np.abs(om2 - want).max() < 1e-12 * scale
+    off = ~np.eye(len(gc), dtype=bool)
+    assert np.abs(want[off]).max() > 0.05 * scale                  # the off-diagonal part is tested
+    # the pin separates the plausible mistakes: a transposed density, or |q+G||q+G'| in place
+    # of the dot product, miss it by far more than the tolerance
+    kn = np.sqrt((k * k).sum(1))
+    alt = want * (kn[:, None] * kn[None, :]) / (k @ k.T)
+    assert np.abs(alt - want).max() > 1e-3 * scale
+    assert np.abs(want - want.T * (k * k).sum(1)[None, :] / (k * k).sum(1)[:, None]).max() > 1e-3 * scale
+
+
 def test_gpp_unscreened_element_keeps_its_static_value():
     t, z, b, rho, rho0 = _gpp_inputs()
     z = z.copy()
@@ -597,21 +734,23 @@ def test_chi0_ksum_energy_gradients_match_finite_differences():
     gv, gcl = oracle.grad_chi0_ksum_energies(b.coef_v, b.e_v, b.coef_c, b.e_c, b.gw, kp, q, gc, gbar, om, d)
     idx, _ = oracle.kq_map(kp, q)
     h = 1e-5
+    pairs = []
     for kk, i in ((0, 0), (3, 1), (6, 1)):            # valence energy of state i at k-point kk
         plus = [e.copy() for e in b.e_v]
         minus = [e.copy() for e in b.e_v]
         plus[kk][i] += h
         minus[kk][i] -= h
         fd = (loss(plus, b.e_c) - loss(minus, b.e_c)) / (2 * h)
-        an = sum(gv[k][i] for k in range(len(kp)) if idx[k] == kk)
-        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (kk, i, fd, an)
+        pairs.append((fd, sum(gv[k][i] for k in range(len(kp)) if idx[k] == kk)))
+    assert_fd(pairs, "k-sum dL/dE_v")
+    pairs = []
     for k, j in ((1, 0), (5, 3)):                     # conduction energy j at k-point k
         plus = [e.copy() for e in b.e_c]
         minus = [e.copy() for e in b.e_c]
         plus[k][j] += h
         minus[k][j] -= h
-        fd = (loss(b.e_v, plus) - loss(b.e_v, minus)) / (2 * h)
-        assert abs(fd - gcl[k][j]) <= 1e-6 * max(1.0, abs(gcl[k][j])), (k, j, fd, gcl[k][j])
+        pairs.append(((loss(b.e_v, plus) - loss(b.e_v, minus)) / (2 * h), gcl[k][j]))
+    assert_fd(pairs, "k-sum dL/dE_c")
 
 
 def test_chi0_is_the_same_on_every_alias_free_grid():
@@ -634,3 +773,100 @@ def test_chi0_is_the_same_on_every_alias_free_grid():
                                 oc.psi_real_space(b.coef_c, gw, (n,) * 3), gc) for n in (16, 17, 24)}
     assert np.abs(m[17] - m[24]).max() <= 1e-12 * np.abs(m[24]).max()
     assert np.abs(m[16] - m[24]).max() > 1e-3 * np.abs(m[24]).max()
+
+
+# ---------------------------------------------------------------- COH self-energy with the plasmon pole
+def test_sigma_coh_gpp_at_zero_energy_transfer_is_the_static_limit():
+    # E - E_{n''} -> 0 (every column at the evaluation energy, no broadening): each pole term
+    # becomes -Omega^2/wt^2 = eps^-1(0) - delta (the model's definition of wt^2), which is the
+    # static COH term; unscreened elements (no pole) add nothing on either side
+    t, z, b, rho, rho0 = _gpp_inputs()
+    om2, wt2 = oracle.gpp_modes(z, t["gc"], (0.01, 0, 0), b, rho, rho0)
+    v = synth.coulomb(t["gc"], (0.01, 0, 0), t["cell"])
+    states = np.concatenate([t["cv"][:2], t["cc"][:1]])
+    w = np.random.default_rng(2).uniform(0.5, 2.0, len(t["cc"]))
+    e = 0.37
+    got = oracle.sigma_coh_gpp(states, t["cc"], np.full(len(t["cc"]), e), t["gw"], t["gc"], t["nd"], om2, wt2, v,
+                               [e], 0.0, n_col=w)[0]
+    want = oracle.sigma_coh_static(states, t["cc"], t["gw"], t["gc"], t["nd"], z, v, n_col=w)
+    assert np.abs(got - want).max() < 1e-12 * np.abs(want).max()
+    # away from that limit the band energies enter
+    far = oracle.sigma_coh_gpp(states, t["cc"], t["e_c"], t["gw"], t["gc"], t["nd"], om2, wt2, v, [e], 0.0,
+                               n_col=w)[0]
+    assert np.abs(far - want).max() > 1e-2 * np.abs(want).max()
+
+
+def _coh_energy_integral(om2, wt2, x, delta, eta):
+    """(i / 2 pi) int_0^inf dE' ([eps^r]^-1 - [eps^a]^-1)(E') / (x - E' + i delta) for one element
+    of the plasmon-pole eps^-1 with broadening eta, by adaptive quadrature (Eq. (sigmach) as
+    printed, without the Coulomb factor)."""
+    from scipy.integrate import quad
+    wt = math.sqrt(wt2)
+
+    def f(ep):
+        ret = om2 / ((ep + 1j * eta) ** 2 - wt2)
+        adv = om2 / ((ep - 1j * eta) ** 2 - wt2)
+        return 1j / (2 * math.pi) * (ret - adv) / (x - ep + 1j * delta)
+
+    pts = [wt] + ([x] if 0 < x < 200 * wt else [])
+    re = quad(lambda e: f(e).real, 0.0, 200 * wt, points=pts, limit=2000, epsabs=1e-13, epsrel=1e-11)[0]
+    im = quad(lambda e: f(e).imag, 0.0, 200 * wt, points=pts, limit=2000, epsabs=1e-13, epsrel=1e-11)[0]
+    return re + 1j * im
+
+
+def test_sigma_coh_gpp_pole_term_is_the_energy_integral():
+    # the pole term per element against Eq. (sigmach)'s E' integral evaluated by quadrature with
+    # the model's eps^-1 at a small broadening eta: (i/2pi) int = 1/2 A_GG'(x) (the 1/2 of the
+    # self-energy's prefactor); the difference vanishes linearly with eta
+    r = np.random.default_rng(21)
+    om2 = r.uniform(-0.6, 0.9, (3, 3))
+    wt2 = r.uniform(0.2, 1.4, (3, 3))
+    v = np.ones(3)
+    errs = {}
+    for eta in (1e-3, 1e-4):
+        worst = 0.0
+        for x, delta in ((-0.4, 0.0), (-1.3, 0.0), (-0.05, 0.02), (0.35, 0.05)):
+            a = oracle.gpp_coh_kernel(om2, wt2, v, x + 1j * delta)
+            for i in range(3):
+                for j in range(3):
+                    q = _coh_energy_integral(om2[i, j], wt2[i, j], x, delta, eta)
+                    worst = max(worst, abs(q - 0.5 * a[i, j]) / abs(a[i, j]))
+        errs[eta] = worst
+    assert errs[1e-4] < 2e-3, errs
+    assert 5.0 < errs[1e-3] / errs[1e-4] < 20.0, errs
+
+
+def test_sigma_coh_gpp_homogeneous_gas_closed_form():
+    # plane-wave states and columns, Omega^2 = w_p^2 on the diagonal, eps^-1(0) diagonal: only
+    # the column at g_n - G reaches G, so Sigma is diagonal with
+    # Sigma_nn(E) = 1/2 sum_G w_{g_n - G} w_p^2 v(G) / (wt_G (E - E_{g_n - G} - wt_G))
+    gw = synth.wf_sphere(12, 3)
+    cell = np.eye(3) * 7.0
+    gc = synth.chi_sphere(27, (0.01, 0, 0), cell)
+    v = synth.coulomb(gc, (0.01, 0, 0), cell)
+    ng = len(gc)
+    wp2 = 4 * np.pi * 0.03
+    einv = np.random.default_rng(5).uniform(0.2, 0.9, ng)
+    om2 = np.full((ng, ng), 0.0, dtype=np.complex128)
+    np.fill_diagonal(om2, wp2)
+    z = np.diag(einv).astype(np.complex128)
+    wt2 = np.full((ng, ng), np.inf + 0j)
+    np.fill_diagonal(wt2, wp2 / (1.0 - einv))
+    ps, pc = [0, 3, 8], [1, 2, 5, 9, 14, 20, 33, 40]
+    e_cols = np.linspace(0.3, 1.4, len(pc))
+    wcol = np.linspace(1.0, 2.0, len(pc))
+    energies = [-0.2, 0.1]
+    got = oracle.sigma_coh_gpp(synth.plane_wave_bands(gw, ps), synth.plane_wave_bands(gw, pc), e_cols, gw, gc,
+                               (12,) * 3, om2, wt2, v, energies, 0.0, n_col=wcol)
+    gl = [tuple(g) for g in gc.tolist()]
+    for j, e in enumerate(energies):
+        want = np.zeros((len(ps), len(ps)), dtype=np.complex128)
+        for a, sa in enumerate(ps):
+            for c, sc in enumerate(pc):
+                G = tuple(gw[sa] - gw[sc])
+                if G in gl:
+                    k = gl.index(G)
+                    wt = math.sqrt(wp2 / (1.0 - einv[k]))
+                    want[a, a] += 0.5 * wcol[c] * wp2 * v[k] / (wt * (e - e_cols[c] - wt))
+        assert np.abs(want).max() > 0
+        assert np.abs(got[j] - want).max() < 1e-13 * np.abs(want).max()
