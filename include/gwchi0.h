@@ -103,6 +103,15 @@ gw_status gw_ctx_set_overlap(gw_ctx* ctx, int mode);
 /* Plane-wave geometry of one q-point (set-up; synchronises the stream).
  *   n_fft[3]   FFT grid N1, N2, N3 (host).  The kernels need N1 = N2 = N3 in
  *              {24, 32, 48, 64, 72, 96, 128}; other grids give GW_EUNSUPPORTED.
+ *   cell, q    host, or both NULL: the lattice vectors a1, a2, a3 as rows (9 doubles, bohr)
+ *              and q in reciprocal-lattice units (3 doubles).  With them the dielectric
+ *              sphere is checked to be the first ng G-vectors in the order
+ *              (|q+G|^2, n1, n2, n3) -- the cutoff sphere of the dielectric matrix, ordered
+ *              as the library's output rows -- with keys equal to a relative 1e-12 counted
+ *              as ties and decided by the Miller indices, and with no G missing below the cut
+ *              (GW_EINVAL otherwise, naming the entry).  The pair densities themselves do not
+ *              use q: the caller supplies the valence states at k+q.  NULL skips the check
+ *              (e.g. for the k-point sum's shifted spheres G + G0 of gw_chi0_build_ksum).
  *   npw, gvec_wf   wavefunction sphere: npw x 3 int32 Miller indices (host), the
  *              order in which coefficient rows are stored.
  *   ng, gvec_chi   dielectric sphere: ng x 3 int32 Miller indices (host), the row and
@@ -116,10 +125,20 @@ gw_status gw_ctx_set_overlap(gw_ctx* ctx, int mode);
  * 48^3).  The pair kernels are built for these (grid, K = 2 max|n_chi| + 1): 24^3 with K 5,
  * 7, 9, 11; 48^3 with 15; 64^3 with 19; 72^3 with 9 ... 19 (odd); 96^3 with 17, 19, 21, 25;
  * 128^3 with 23, 25, 27.  Another combination gives GW_EUNSUPPORTED.  The geometry keeps
- * its own device copies of the index tables. */
-gw_status gw_geom_create(gw_ctx* ctx, const int n_fft[3], int npw, const int32_t* gvec_wf, int ng,
-                         const int32_t* gvec_chi, gw_geom** out);
+ * its own device copies of the index tables.  Destroying a geometry also drops the graphs
+ * that graph mode captured with it (gw_ctx_set_graph); a geometry may outlive its context
+ * (it is then only destroyed). */
+gw_status gw_geom_create(gw_ctx* ctx, const int n_fft[3], const double* cell, const double* q, int npw,
+                         const int32_t* gvec_wf, int ng, const int32_t* gvec_chi, gw_geom** out);
 gw_status gw_geom_destroy(gw_geom* geom);
+
+/* The dielectric-sphere check of gw_geom_create on its own (host only, no context or GPU):
+ * GW_OK if gvec_chi (ng x 3 int32, host) is the first ng G-vectors in the order
+ * (|q+G|^2, n1, n2, n3) for the cell (9 doubles, rows = lattice vectors, bohr) and q
+ * (3 doubles, reciprocal-lattice units); else GW_EINVAL with the reason copied into msg
+ * (msg_len bytes including the terminating zero; msg may be NULL). */
+gw_status gw_sphere_check(const double* cell, const double* q, int ng, const int32_t* gvec_chi, char* msg,
+                          size_t msg_len);
 
 /* ---------------------------------------------------------------- chi0 */
 
@@ -132,8 +151,16 @@ gw_status gw_geom_destroy(gw_geom* geom);
  *                         multiplicity (1 for a band, g(E_i) dE_i for a window);
  *                         n_col NULL = all 1.  Eq. (energyintegration) is then the
  *                         plain column sum.
- * Values are not inspected on the host; a zero denominator E_v - E_col with
- * omega = delta = 0 gives non-finite output. */
+ * Value checks: the entry points that take problems (gw_chi0_build, gw_chi0_build_ksum,
+ * gw_chi0_backward, gw_chi0_backward_ksum, gw_pair_density, gw_sigma_coh_static,
+ * gw_sigma_coh_gpp) run one small kernel over the device arrays and read its flag back
+ * (a synchronisation of the stream): GW_EINVAL for a non-finite energy (e_v, e_col), a
+ * negative or non-finite n_col, or a col_band entry outside [0, nband).  The check is
+ * skipped while the context's stream is being captured into a HIP graph (no
+ * synchronisation is allowed there) and on replays of graph mode (checked when captured);
+ * the kernels then never read or write outside the coefficient rows (column rows are
+ * clamped on reads and skipped on writes) and only the result is undefined.  A zero
+ * denominator E_v - E_col with omega = delta = 0 gives non-finite output. */
 typedef struct {
   const gw_geom* geom;
   int nv;
@@ -166,7 +193,7 @@ gw_status gw_chi0_workspace_size(gw_ctx* ctx, const gw_chi0_problem* probs, int 
  *   chi0    device output, complex128: for each problem p in order, nomega blocks of
  *           ng_p x ng_p row-major, [p][omega][G][G'].
  * GW_EINVAL: nprob < 1, nomega < 1, delta < 0, nv < 1, ncol < 1, NULL data pointers,
- * ncol > nband without col_band, workspace too small. */
+ * ncol > nband without col_band, workspace too small, and the value checks above. */
 gw_status gw_chi0_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, const double* omega,
                         double delta, gw_precision prec, void* workspace, size_t ws_bytes, void* chi0);
 
@@ -310,6 +337,36 @@ gw_status gw_eps_inv_backward(gw_ctx* ctx, int ng, int nbatch, const double* vco
 gw_status gw_sigma_coh_workspace_size(gw_ctx* ctx, const gw_chi0_problem* prob, size_t* bytes);
 gw_status gw_sigma_coh_static(gw_ctx* ctx, const gw_chi0_problem* prob, const double* vcoul, const void* eps_inv,
                               void* workspace, size_t ws_bytes, void* sigma);
+
+/* The COH self-energy of Eq. (sigmach) with the plasmon-pole model the paper uses for the
+ * frequency dependence of eps^-1 (gw_gpp_eps_inv).  Each element of [eps^r]^-1 - [eps^a]^-1 on
+ * E' > 0 is then -i pi (Omega^2 / wt) delta(E' - wt) (as the pole's broadening goes to zero),
+ * and the E' integral leaves, for states n, n' and energies E_j,
+ *   <n|Sigma_COH(E_j)|n'> = 1/2 sum_q sum_c w_c sum_{G G'} M_{n c}(G)
+ *        Omega^2_GG' v(q+G') / (wt_GG' (E_j - E_c - wt_GG' + i delta)) conj(M_{n' c}(G')),
+ * M the matrix element of Eq. (chi0) between state n and column c (a band with weight w = 1 at
+ * its energy E_c, or a window representative with w = g(E_i) dE_i at E_i: the grouping of Eq.
+ * (energyintegration), which the paper applies to this sum), wt the principal square root of
+ * wt^2.  Elements without a pole (wt^2 = +inf, unscreened) or with Omega^2 = 0 add nothing.
+ * With E_j - E_c -> 0 every term becomes 1/2 [eps^-1(0) - 1] v: the static form above.
+ *   probs, nq   one problem per q of the sum (the sum over q of Eq. (sigmach)): coef_v / nv the
+ *               states n at k (1 .. 32, the same count in every problem), coef_c, nband, ncol,
+ *               col_band, e_col (required), n_col (NULL = all 1) the columns at k - q.  A column
+ *               set at k - q = k'' + G0 is passed relabelled, as for gw_chi0_build_ksum.  The
+ *               problems are added in order; a 1/N_q goes into v.
+ *   vcoul       host array of nq device pointers: ng_q doubles v(q+G) each.
+ *   modes       host array of nq device pointers: 2 ng_q^2 complex128 each, Omega^2 then wt^2,
+ *               row-major (the modes output of gw_gpp_eps_inv).
+ *   energies    host, nenergy >= 1 real energies E_j (Hartree);  delta >= 0.
+ *   sigma       device complex128 nenergy x nv x nv, [j][n][n'] (overwritten).
+ * Float64 throughout.  Workspace: gw_sigma_coh_gpp_workspace_size.  GW_EINVAL for more than 32
+ * states, differing state counts, NULL arguments, non-finite energies, a small workspace or the
+ * value checks of gw_chi0_problem. */
+gw_status gw_sigma_coh_gpp_workspace_size(gw_ctx* ctx, const gw_chi0_problem* probs, int nq, int nenergy,
+                                          size_t* bytes);
+gw_status gw_sigma_coh_gpp(gw_ctx* ctx, const gw_chi0_problem* probs, int nq, const double* const* vcoul,
+                           const void* const* modes, int nenergy, const double* energies, double delta,
+                           void* workspace, size_t ws_bytes, void* sigma);
 
 /* ---------------------------------------------------------------- plasmon pole */
 

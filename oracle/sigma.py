@@ -12,7 +12,8 @@ E' integral leaves one pole term per element,
 with the band energy E_{n''} in the denominator (for a window column its energy E_i, weight
 w = g(E_i) dE_i of Eq. (energyintegration)).  wt is the principal square root of wt^2 (for a
 complex wt^2 of an off-diagonal element the expression is taken as written, its analytic
-continuation); elements without a pole (unscreened) add nothing.  Pinned in
+continuation); elements without a pole (unscreened) or without pole weight (Omega^2 = 0) add
+nothing.  Pinned in
 tests/test_oracle.py by a quadrature of Eq. (sigmach)'s E' integral as printed, by its
 E - E_{n''} -> 0 limit (the static form below) and by the homogeneous electron gas.
 
@@ -84,8 +85,8 @@ def sigma_coh_complete_set(coef_n: np.ndarray, gvec_wf: np.ndarray, gvec_chi: np
 
 def gpp_coh_kernel(om2: np.ndarray, wt2: np.ndarray, vcoul: np.ndarray, x: complex) -> np.ndarray:
     """A_GG'(x) = Omega^2_GG' v(G') / (wt_GG' (x - wt_GG')), x = E - E_{n''} + i delta; zero where
-    the element has no pole (wt^2 = inf)."""
-    pole = np.isfinite(wt2)
+    the element has no pole (wt^2 = inf) or no pole weight (Omega^2 = 0)."""
+    pole = np.isfinite(wt2) & (om2 != 0)
     wt = np.sqrt(wt2[pole].astype(np.complex128))                  # principal branch
     a = np.zeros(om2.shape, dtype=np.complex128)
     a[pole] = om2[pole] / (wt * (x - wt))

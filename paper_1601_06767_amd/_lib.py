@@ -47,8 +47,9 @@ _sig("gw_version", C.c_char_p, [])
 _sig("gw_ctx_create", C.c_int, [C.c_int, vp, C.POINTER(vp)])
 _sig("gw_ctx_destroy", C.c_int, [vp])
 _sig("gw_last_error", C.c_char_p, [vp])
-_sig("gw_geom_create", C.c_int, [vp, C.POINTER(C.c_int), C.c_int, i32p, C.c_int, i32p, C.POINTER(vp)])
+_sig("gw_geom_create", C.c_int, [vp, C.POINTER(C.c_int), dp, dp, C.c_int, i32p, C.c_int, i32p, C.POINTER(vp)])
 _sig("gw_geom_destroy", C.c_int, [vp])
+_sig("gw_sphere_check", C.c_int, [dp, dp, C.c_int, i32p, C.c_char_p, C.c_size_t])
 _sig("gw_chi0_workspace_size", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, C.c_int,
                                          C.POINTER(C.c_size_t)])
 _sig("gw_chi0_build", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, dp, C.c_double, C.c_int, vp,
@@ -85,6 +86,10 @@ _sig("gw_gpp_eps_inv", C.c_int, [vp, C.c_int, i32p, dp, dp, C.c_int, vp, vp, C.c
                                  vp, vp])
 _sig("gw_sigma_coh_static", C.c_int, [vp, C.POINTER(gw_chi0_problem), vp, vp, vp, C.c_size_t, vp])
 _sig("gw_ctx_stage_times", C.c_int, [vp, dp, C.POINTER(C.c_longlong), C.c_int])
+_sig("gw_sigma_coh_gpp_workspace_size", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int,
+                                                  C.POINTER(C.c_size_t)])
+_sig("gw_sigma_coh_gpp", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.POINTER(vp), C.POINTER(vp), C.c_int, dp,
+                                   C.c_double, vp, C.c_size_t, vp])
 
 STAGES = ["band", "planes", "finish", "weights", "contract", "finalize", "eps_inv", "backward"]
 
@@ -94,7 +99,7 @@ EXPORTED = ["gw_ctx_set_timing", "gw_ctx_stage_times", "gw_ctx_set_graph", "gw_t
             "gw_version", "gw_ctx_create", "gw_ctx_destroy", "gw_last_error", "gw_geom_create", "gw_geom_destroy",
             "gw_chi0_workspace_size", "gw_chi0_build", "gw_chi0_backward", "gw_pair_density_workspace_size", "gw_pair_density",
             "gw_eps_inv_workspace_size", "gw_eps_inv", "gw_eps_inv_status", "gw_eps_inv_backward",
-            "gw_group_windows"]
+            "gw_group_windows", "gw_sphere_check", "gw_sigma_coh_gpp_workspace_size", "gw_sigma_coh_gpp"]
 
 
 class GwError(RuntimeError):
@@ -179,13 +184,20 @@ def gw_ctx_stage_times(ctx, reset: bool = False) -> dict:
     return {s: (ms[i], n[i]) for i, s in enumerate(STAGES)}
 
 
-def gw_geom_create(ctx, n_fft: Sequence[int], gvec_wf: np.ndarray, gvec_chi: np.ndarray):
+def gw_geom_create(ctx, n_fft: Sequence[int], gvec_wf: np.ndarray, gvec_chi: np.ndarray, cell=None, q=None):
+    """Geometry of one q-point; with cell (3 x 3, rows = lattice vectors, bohr) and q (reciprocal-lattice
+    units) the library checks that gvec_chi is the sphere ordered by (|q+G|^2, n1, n2, n3)."""
     gw_ = np.ascontiguousarray(gvec_wf, dtype=np.int32)
     gc = np.ascontiguousarray(gvec_chi, dtype=np.int32)
     nf = (C.c_int * 3)(*[int(x) for x in n_fft])
+    if (cell is None) != (q is None):
+        raise ValueError("give both cell and q, or neither")
+    cl = None if cell is None else np.ascontiguousarray(np.asarray(cell, dtype=np.float64).reshape(9))
+    qq = None if q is None else np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(3))
     out = vp()
-    _check(lib.gw_geom_create(ctx, nf, gw_.shape[0], gw_.ctypes.data_as(i32p), gc.shape[0], gc.ctypes.data_as(i32p),
-                              C.byref(out)), ctx)
+    _check(lib.gw_geom_create(ctx, nf, None if cl is None else cl.ctypes.data_as(dp),
+                              None if qq is None else qq.ctypes.data_as(dp), gw_.shape[0], gw_.ctypes.data_as(i32p),
+                              gc.shape[0], gc.ctypes.data_as(i32p), C.byref(out)), ctx)
     _npw[out.value] = int(gw_.shape[0])
     return out
 
@@ -195,6 +207,21 @@ _npw = {}   # wavefunction-sphere size per geometry handle
 
 def _geom_npw(geom) -> int:
     return _npw[geom if isinstance(geom, int) else geom.value]
+
+
+def gw_sphere_check(cell, q, gvec_chi: np.ndarray) -> str:
+    """'' if gvec_chi is the sphere ordered by (|q+G|^2, n1, n2, n3) for this cell and q, else the reason."""
+    cl = np.ascontiguousarray(np.asarray(cell, dtype=np.float64).reshape(9))
+    qq = np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(3))
+    gc = np.ascontiguousarray(gvec_chi, dtype=np.int32)
+    buf = C.create_string_buffer(256)
+    st = lib.gw_sphere_check(cl.ctypes.data_as(dp), qq.ctypes.data_as(dp), gc.shape[0], gc.ctypes.data_as(i32p), buf,
+                             256)
+    if st == GW_OK:
+        return ""
+    if st != GW_EINVAL or not buf.value:
+        raise GwError(st, "bad arguments")
+    return buf.value.decode()
 
 
 def gw_geom_destroy(geom) -> None:
@@ -373,6 +400,34 @@ def gw_sigma_coh_static(ctx, problem, vcoul, eps_inv, workspace=None, out=None):
 
 
 # ---------------------------------------------------------------- dielectric
+
+def gw_sigma_coh_gpp(ctx, problems, vcouls, modes, energies: Sequence[float], delta: float = 0.0, workspace=None,
+                     out=None):
+    """COH self-energy of Eq. (sigmach) with the plasmon-pole eps^-1: one problem per q (states
+    coef_v, columns coef_c with energies e_col and weights n_col), each with its Coulomb factors
+    (ng tensor) and modes (2 ng^2 complex128: Omega^2 then wt^2); returns (nenergy, nv, nv) complex128."""
+    import torch
+    arr = _probs(problems)
+    nq = len(arr)
+    if len(vcouls) != nq or len(modes) != nq:
+        raise ValueError("one Coulomb vector and one mode array per problem")
+    en = np.ascontiguousarray(np.asarray(energies, dtype=np.float64))
+    vv = [v.contiguous() for v in vcouls]
+    mm = [m.contiguous() for m in modes]
+    vp_arr = (vp * nq)(*[vp(_ptr(v)) for v in vv])
+    mp_arr = (vp * nq)(*[vp(_ptr(m)) for m in mm])
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if workspace is None:
+        n = C.c_size_t()
+        _check(lib.gw_sigma_coh_gpp_workspace_size(ctx, arr, nq, len(en), C.byref(n)), ctx)
+        workspace = torch.empty(n.value, dtype=torch.uint8, device=dev)
+    ns = arr[0].nv
+    if out is None:
+        out = torch.empty((len(en), ns, ns), dtype=torch.complex128, device=dev)
+    _check(lib.gw_sigma_coh_gpp(ctx, arr, nq, vp_arr, mp_arr, len(en), en.ctypes.data_as(dp), float(delta),
+                                _ptr(workspace), workspace.numel(), _ptr(out)), ctx)
+    return out
+
 def gw_eps_inv_workspace_size(ctx, ng: int, nbatch: int) -> int:
     n = C.c_size_t()
     _check(lib.gw_eps_inv_workspace_size(ctx, ng, nbatch, C.byref(n)), ctx)

@@ -63,9 +63,9 @@ class _EpsInv(torch.autograd.Function):
 _geom_ng = {}
 
 
-def geometry(gctx, n_fft: Sequence[int], gvec_wf, gvec_chi):
+def geometry(gctx, n_fft: Sequence[int], gvec_wf, gvec_chi, cell=None, q=None):
     """gw_geom_create, remembering the dielectric-sphere size for the autograd wrappers."""
-    g = L.gw_geom_create(gctx, n_fft, gvec_wf, gvec_chi)
+    g = L.gw_geom_create(gctx, n_fft, gvec_wf, gvec_chi, cell, q)
     _geom_ng[g.value] = len(gvec_chi)
     return g
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cstdint>
 #include <cmath>
@@ -20,8 +21,104 @@ using gw::Geom;
 namespace {
 
 std::string g_create_error;
+std::atomic<unsigned long long> g_geom_ids{0};
 
 size_t round_up(size_t x, size_t m) { return (x + m - 1) / m * m; }
+
+// Reciprocal lattice vectors as rows, b_i . a_j = 2 pi delta_ij, of a cell with the lattice
+// vectors as rows; false for a singular cell.
+bool reciprocal(const double* a, double* b) {
+  const double det = a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+                     a[2] * (a[3] * a[7] - a[4] * a[6]);
+  if (!(std::fabs(det) > 0.0) || !std::isfinite(det)) return false;
+  const double f = 2.0 * 3.141592653589793238462643383279502884 / det;
+  // b = 2 pi (a^-1)^T: rows are the cofactor rows of a over det
+  b[0] = f * (a[4] * a[8] - a[5] * a[7]);
+  b[1] = f * (a[5] * a[6] - a[3] * a[8]);
+  b[2] = f * (a[3] * a[7] - a[4] * a[6]);
+  b[3] = f * (a[2] * a[7] - a[1] * a[8]);
+  b[4] = f * (a[0] * a[8] - a[2] * a[6]);
+  b[5] = f * (a[1] * a[6] - a[0] * a[7]);
+  b[6] = f * (a[1] * a[5] - a[2] * a[4]);
+  b[7] = f * (a[2] * a[3] - a[0] * a[5]);
+  b[8] = f * (a[0] * a[4] - a[1] * a[3]);
+  return true;
+}
+
+// |q + G|^2 in bohr^-2 for Miller indices n
+double qg2(const double* b, const double* q, const int32_t* n) {
+  double s = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    double x = 0.0;
+    for (int e = 0; e < 3; ++e) x += ((double)n[e] + q[e]) * b[3 * e + d];
+    s += x * x;
+  }
+  return s;
+}
+
+// The dielectric sphere must be the first ng G-vectors in the order (|q+G|^2, n1, n2, n3):
+// ascending keys (keys equal within a relative 1e-12 count as a tie, decided by the Miller
+// indices), and no G outside the list with a key below the list's largest (a cut through a
+// shell keeps the lower Miller indices).  Returns "" or the reason.
+std::string check_sphere_order(const double* cell, const double* q, int ng, const int32_t* gvec) {
+  double b[9];
+  if (!reciprocal(cell, b)) return "singular cell";
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(q[d])) return "non-finite q";
+  const double tol = 1e-12;
+  std::vector<double> key(ng);
+  for (int i = 0; i < ng; ++i) key[i] = qg2(b, q, gvec + 3 * i);
+  auto before = [&](int i, int j) {   // strictly before in the sphere order
+    const double a = key[i], c = key[j];
+    if (c - a > tol * std::max(a, c)) return true;
+    if (a - c > tol * std::max(a, c)) return false;
+    for (int d = 0; d < 3; ++d)
+      if (gvec[3 * i + d] != gvec[3 * j + d]) return gvec[3 * i + d] < gvec[3 * j + d];
+    return false;
+  };
+  for (int i = 0; i + 1 < ng; ++i)
+    if (!before(i, i + 1))
+      return "dielectric sphere not ordered by (|q+G|^2, n1, n2, n3) at entry " + std::to_string(i + 1);
+  // completeness: |n + q| <= |q + G| ||a||_F / (2 pi) bounds every Miller index below the cut
+  double fro = 0.0;
+  for (int i = 0; i < 9; ++i) fro += cell[i] * cell[i];
+  const double kmax = key[ng - 1];
+  const int last = ng - 1;
+  const double rad = std::sqrt(kmax) * std::sqrt(fro) / (2.0 * 3.141592653589793);
+  int lo[3], hi[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = (int)std::floor(-q[d] - rad) - 1;
+    hi[d] = (int)std::ceil(-q[d] + rad) + 1;
+    if (hi[d] - lo[d] > 4096) return "dielectric sphere too large to check";
+  }
+  std::unordered_set<long long> in;
+  auto pack = [](long long a, long long c, long long e) { return ((a + 2048) * 4096 + (c + 2048)) * 4096 + (e + 2048); };
+  for (int i = 0; i < ng; ++i) {
+    for (int d = 0; d < 3; ++d)
+      if (gvec[3 * i + d] < -2047 || gvec[3 * i + d] > 2047) return "Miller index out of range";
+    in.insert(pack(gvec[3 * i], gvec[3 * i + 1], gvec[3 * i + 2]));
+  }
+  std::vector<int32_t> lastv(gvec + 3 * last, gvec + 3 * last + 3);
+  for (int n1 = lo[0]; n1 <= hi[0]; ++n1)
+    for (int n2 = lo[1]; n2 <= hi[1]; ++n2)
+      for (int n3 = lo[2]; n3 <= hi[2]; ++n3) {
+        const int32_t n[3] = {n1, n2, n3};
+        const double k = qg2(b, q, n);
+        if (k > kmax * (1.0 + tol)) continue;
+        bool below = k < kmax * (1.0 - tol);
+        if (!below) {   // a tie with the last entry: below it if its Miller indices are lower
+          for (int d = 0; d < 3; ++d)
+            if (n[d] != lastv[d]) {
+              below = n[d] < lastv[d];
+              break;
+            }
+        }
+        if (below && !in.count(pack(n1, n2, n3)))
+          return "dielectric sphere misses G = (" + std::to_string(n1) + "," + std::to_string(n2) + "," +
+                 std::to_string(n3) + ") below its cut";
+      }
+  return "";
+}
 
 }  // namespace
 
@@ -77,6 +174,8 @@ gw_status gw_ctx_create(int device, void* hip_stream, gw_ctx** out) {
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(device);
   hipError_t e = hipMalloc(&c->d_pivot_flag, sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&c->d_check_flag, sizeof(int));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_check_flag, sizeof(int), hipHostMallocDefault);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
   for (int i = 0; i < 2 && e == hipSuccess; ++i) {
     e = hipEventCreateWithFlags(&c->ev_ready[i], hipEventDisableTiming);
@@ -96,6 +195,8 @@ gw_status gw_ctx_create(int device, void* hip_stream, gw_ctx** out) {
 gw_status gw_ctx_destroy(gw_ctx* ctx) {
   if (!ctx) return GW_EINVAL;
   if (ctx->d_pivot_flag) (void)hipFree(ctx->d_pivot_flag);
+  if (ctx->d_check_flag) (void)hipFree(ctx->d_check_flag);
+  if (ctx->h_check_flag) (void)hipHostFree(ctx->h_check_flag);
   if (ctx->side) {
     (void)hipStreamSynchronize(ctx->side);
     (void)hipStreamDestroy(ctx->side);
@@ -113,18 +214,24 @@ gw_status gw_ctx_destroy(gw_ctx* ctx) {
     (void)hipEventDestroy(m.a);
     (void)hipEventDestroy(m.b);
   }
+  for (gw_geom* gg : ctx->geoms) gg->ctx = nullptr;
   delete ctx;
   return GW_OK;
 }
 
 const char* gw_last_error(const gw_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
 
-gw_status gw_geom_create(gw_ctx* ctx, const int n_fft[3], int npw, const int32_t* gvec_wf, int ng,
-                         const int32_t* gvec_chi, gw_geom** out) {
+gw_status gw_geom_create(gw_ctx* ctx, const int n_fft[3], const double* cell, const double* q, int npw,
+                         const int32_t* gvec_wf, int ng, const int32_t* gvec_chi, gw_geom** out) {
   if (!ctx) return GW_EINVAL;
   if (!out || !n_fft || !gvec_wf || !gvec_chi) return gw::fail(ctx, GW_EINVAL, "NULL argument");
   *out = nullptr;
   if (npw < 1 || ng < 1) return gw::fail(ctx, GW_EINVAL, "npw and ng must be >= 1");
+  if ((cell == nullptr) != (q == nullptr)) return gw::fail(ctx, GW_EINVAL, "give both cell and q, or neither");
+  if (cell) {
+    const std::string why = check_sphere_order(cell, q, ng, gvec_chi);
+    if (!why.empty()) return gw::fail(ctx, GW_EINVAL, why);
+  }
   for (int i = 0; i < 3; ++i)
     if (n_fft[i] < 1) return gw::fail(ctx, GW_EINVAL, "FFT grid must be positive");
   const int nd = n_fft[0];
@@ -163,6 +270,11 @@ gw_status gw_geom_create(gw_ctx* ctx, const int n_fft[3], int npw, const int32_t
   g.K = 2 * rc + 1;
   g.ngp = (int)round_up(ng, gw::kTile);
   g.line = ls;
+  if (cell) {
+    g.has_q = true;
+    for (int d = 0; d < 3; ++d) g.q[d] = q[d];
+    for (int d = 0; d < 9; ++d) g.cell[d] = cell[d];
+  }
   if (g.W > 2 * 64 + 1) return gw::fail(ctx, GW_EUNSUPPORTED, "wavefunction sphere too wide");
   // the pair kernels read the planes in the band transform's split order: same radix
   if (gw::pair_supported(nd, g.K) && gw::pair_radix(nd, g.K) != ls.R)
@@ -201,6 +313,8 @@ gw_status gw_geom_create(gw_ctx* ctx, const int n_fft[3], int npw, const int32_t
   gw_geom* gg = new (std::nothrow) gw_geom();
   if (!gg) return gw::fail(ctx, GW_ENOMEM, "out of host memory");
   gg->ctx = ctx;
+  gg->id = ++g_geom_ids;
+  ctx->geoms.push_back(gg);
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(ctx->device);
@@ -227,8 +341,34 @@ gw_status gw_geom_create(gw_ctx* ctx, const int n_fft[3], int npw, const int32_t
   return GW_OK;
 }
 
+gw_status gw_sphere_check(const double* cell, const double* q, int ng, const int32_t* gvec_chi, char* msg,
+                          size_t msg_len) {
+  if (!cell || !q || ng < 1 || !gvec_chi) return GW_EINVAL;
+  const std::string why = check_sphere_order(cell, q, ng, gvec_chi);
+  if (msg && msg_len > 0) {
+    const size_t n = std::min(msg_len - 1, why.size());
+    std::memcpy(msg, why.data(), n);
+    msg[n] = '\0';
+  }
+  return why.empty() ? GW_OK : GW_EINVAL;
+}
+
 gw_status gw_geom_destroy(gw_geom* geom) {
   if (!geom) return GW_EINVAL;
+  // captured graphs that read this geometry's tables are dropped with it
+  if (gw_ctx* ctx = geom->ctx) {
+    std::vector<gw_ctx::GraphEntry> keep;
+    for (auto& ge : ctx->graphs) {
+      if (std::find(ge.geoms.begin(), ge.geoms.end(), geom->id) != ge.geoms.end()) {
+        (void)hipGraphExecDestroy(ge.exec);
+        (void)hipGraphDestroy(ge.graph);
+      } else {
+        keep.push_back(ge);
+      }
+    }
+    ctx->graphs.swap(keep);
+    ctx->geoms.erase(std::remove(ctx->geoms.begin(), ctx->geoms.end(), geom), ctx->geoms.end());
+  }
   Geom& g = geom->g;
   if (g.d_wf_map) (void)hipFree(g.d_wf_map);
   if (g.d_chi_map) (void)hipFree(g.d_chi_map);

@@ -218,6 +218,32 @@ gw_status check_problem(gw_ctx* ctx, const gw_chi0_problem& p) {
   return GW_OK;
 }
 
+// Checks the values behind the problems' device pointers (finite energies, multiplicities
+// >= 0, column rows in range) with one small kernel and a synchronising read of its flag.
+// Skipped while the context's stream is being captured into a graph (a synchronisation is
+// not allowed there): the kernels then never read or write outside the coefficient rows
+// (column rows are clamped on reads and skipped on writes), and only the result is undefined.
+gw_status check_values(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob) {
+  if (ctx->stream) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    GW_HIP(ctx, hipStreamIsCapturing(ctx->stream, &cs));
+    if (cs != hipStreamCaptureStatusNone) return GW_OK;
+  }
+  GW_HIP(ctx, gw::launch_flag_clear(ctx->d_check_flag, ctx->stream));
+  for (int i = 0; i < nprob; ++i) {
+    const gw_chi0_problem& p = probs[i];
+    GW_HIP(ctx, gw::launch_check_columns(p.e_v, p.nv, p.e_col, p.n_col, p.col_band, p.ncol, p.nband,
+                                         ctx->d_check_flag, ctx->stream));
+  }
+  GW_HIP(ctx, hipMemcpyAsync(ctx->h_check_flag, ctx->d_check_flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  const int f = *ctx->h_check_flag;
+  if (f & 4) return gw::fail(ctx, GW_EINVAL, "a col_band entry is outside [0, nband)");
+  if (f & 2) return gw::fail(ctx, GW_EINVAL, "a column multiplicity n_col is negative or not finite");
+  if (f & 1) return gw::fail(ctx, GW_EINVAL, "a band or column energy is not finite");
+  return GW_OK;
+}
+
 gw_status check_common(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nomega, const double* omega,
                        double delta, gw_precision prec) {
   if (!probs || nprob < 1 || nomega < 1 || !omega) return gw::fail(ctx, GW_EINVAL, "bad arguments");
@@ -403,7 +429,7 @@ gw_status coef_grad_chunk(gw_ctx* ctx, const Layout& L, const ProbPlan& q, const
                                             ws + L.off_scr, ws + L.off_cbar + (size_t)s0 * g.npw * sizeof(double2),
                                             ctx->stream));
     }
-    GW_HIP(ctx, gw::launch_scatter_cols(ws + L.off_cbar, nvalid, p.col_band, c0, g.npw, gcc, ctx->stream));
+    GW_HIP(ctx, gw::launch_scatter_cols(ws + L.off_cbar, nvalid, p.col_band, c0, g.npw, p.nband, gcc, ctx->stream));
   }
   if (want_v)
     GW_HIP(ctx, gw::launch_ubar(g, ws + L.off_q, ws + L.off_psic, q.nvs, q.cc, false, ws + L.off_ubarv, ctx->stream));
@@ -424,6 +450,7 @@ std::string graph_key(const gw_chi0_problem* probs, int nprob, int nomega, const
   add(&ws, sizeof ws);
   add(&ws_bytes, sizeof ws_bytes);
   add(&out, sizeof out);
+  for (int i = 0; i < nprob; ++i) add(&probs[i].geom->id, sizeof probs[i].geom->id);
   return k;
 }
 
@@ -469,9 +496,12 @@ gw_status build_entry(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int 
       if (probs[i].geom->g.ng != probs[0].geom->g.ng)
         return gw::fail(ctx, GW_EINVAL, "a k-point sum needs the same dielectric-sphere size in every problem");
   DeviceScope dev(ctx->device);
-  if (!ctx->graph)
+  if (!ctx->graph) {
+    s = check_values(ctx, probs, nprob);
+    if (s != GW_OK) return s;
     return enqueue_build_all(ctx, probs, nprob, nomega, omega, delta, prec, (char*)workspace, ws_bytes, (char*)chi0,
                              ksum);
+  }
   // graph mode: replay the captured launch sequence of an identical call
   if (!ctx->stream) return gw::fail(ctx, GW_EINVAL, "graph mode needs a context on a non-null stream");
   const std::string key = graph_key(probs, nprob, nomega, omega, delta, prec, workspace, ws_bytes, chi0, ksum);
@@ -480,6 +510,8 @@ gw_status build_entry(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int 
       GW_HIP(ctx, hipGraphLaunch(ge.exec, ctx->stream));
       return GW_OK;
     }
+  s = check_values(ctx, probs, nprob);   // values are checked when a call is captured, not on replays
+  if (s != GW_OK) return s;
   const bool timing = ctx->timing;
   ctx->timing = false;   // no event nodes in a captured graph
   GW_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
@@ -498,7 +530,9 @@ gw_status build_entry(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int 
     (void)hipGraphDestroy(graph);
     return gw::fail(ctx, GW_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
   }
-  ctx->graphs.push_back(gw_ctx::GraphEntry{key, graph, exec});
+  std::vector<unsigned long long> ids;
+  for (int i = 0; i < nprob; ++i) ids.push_back(probs[i].geom->id);
+  ctx->graphs.push_back(gw_ctx::GraphEntry{key, graph, exec, ids});
   GW_HIP(ctx, hipGraphLaunch(exec, ctx->stream));
   return GW_OK;
 }
@@ -550,6 +584,8 @@ gw_status backward_entry(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, i
   if (want_coef && prec != GW_FP64)
     return gw::fail(ctx, GW_EUNSUPPORTED, "coefficient gradients are computed in the float64 mode only");
   DeviceScope dev(ctx->device);
+  st = check_values(ctx, probs, nprob);
+  if (st != GW_OK) return st;
   char* ws = (char*)workspace;
   const char* gin = (const char*)grad_chi0;
   size_t off_ev = 0, off_ec = 0, off_cv = 0, off_cc = 0;
@@ -667,6 +703,8 @@ gw_status gw_pair_density(gw_ctx* ctx, const gw_chi0_problem* prob, int v0, int 
   if (q.cc < (int)round_up(ncs, 8)) return gw::fail(ctx, GW_EINVAL, "pair block too large for one pass");
   if (L.total > ws_bytes) return gw::fail(ctx, GW_EINVAL, "workspace too small: need " + std::to_string(L.total));
   DeviceScope dev(ctx->device);
+  s = check_values(ctx, prob, 1);
+  if (s != GW_OK) return s;
   char* ws = (char*)workspace;
   s = band_to_real(ctx, L, g, (const double2*)prob->coef_v, prob->nv, nullptr, v0, v0 + nvs, q.nvs, ws, ws + q.off_psiv);
   if (s != GW_OK) return s;
@@ -740,6 +778,8 @@ gw_status gw_sigma_coh_static(gw_ctx* ctx, const gw_chi0_problem* prob, const do
   const ProbPlan& q = L.pp[0];
   const Geom& g = p.geom->g;
   DeviceScope dev(ctx->device);
+  s = check_values(ctx, prob, 1);
+  if (s != GW_OK) return s;
   char* ws = (char*)workspace;
   GW_HIP(ctx, gw::launch_fill_c128(sigma, (size_t)p.nv * p.nv, ctx->stream));
   GW_HIP(ctx, gw::launch_coh_kernel(eps_inv, vcoul, g.ng, g.ngp, ws + c.off_a, ctx->stream));
@@ -758,6 +798,118 @@ gw_status gw_sigma_coh_static(gw_ctx* ctx, const gw_chi0_problem* prob, const do
     GW_HIP(ctx, gw::launch_coh_reduce(ws + q.off_m, ws + c.off_z, p.nv, q.cc, g.ngp, nvalid, p.n_col, c0, c.nblk,
                                       ws + c.off_part, sigma, ctx->stream));
   }
+  return GW_OK;
+}
+
+namespace {
+// workspace of gw_sigma_coh_gpp: per problem the float64 pair-transform layout of the states x
+// one chunk of columns and the (B, wt) tiles (two ngp^2 complex arrays), the largest over the
+// problems; then the tile partials of every (state block, state block, energy block) pass
+struct GppCohLayout {
+  size_t region = 0, off_part = 0, part_pass = 0, total = 0;
+  int nsb = 0, neb = 0, ngp_max = 0;
+};
+
+GppCohLayout gpp_coh_layout(gw_ctx* ctx, const gw_chi0_problem* probs, int nq, int nenergy) {
+  GppCohLayout c;
+  for (int i = 0; i < nq; ++i) {
+    const Layout L = make_layout(ctx, probs + i, 1, 1, false, GW_FP64, false);
+    const Geom& g = probs[i].geom->g;
+    const size_t r = round_up(L.total, 256) + 2 * round_up((size_t)g.ngp * g.ngp * sizeof(double2), 256);
+    c.region = std::max(c.region, r);
+    c.ngp_max = std::max(c.ngp_max, g.ngp);
+    c.part_pass = std::max(c.part_pass, gw::gpp_coh_part_bytes(g.ngp));
+  }
+  const int bs = gw::gpp_coh_states_per_block(), be = gw::gpp_coh_energies_per_pass();
+  c.nsb = (probs[0].nv + bs - 1) / bs;
+  c.neb = (nenergy + be - 1) / be;
+  c.off_part = c.region;
+  c.total = c.off_part + (size_t)c.nsb * c.nsb * c.neb * c.part_pass;
+  return c;
+}
+
+gw_status check_gpp_coh(gw_ctx* ctx, const gw_chi0_problem* probs, int nq, int nenergy, const double* energies,
+                        double delta) {
+  if (!probs || nq < 1) return gw::fail(ctx, GW_EINVAL, "no problems");
+  for (int i = 0; i < nq; ++i) {
+    gw_status s = check_coh(ctx, probs + i);
+    if (s != GW_OK) return s;
+    if (!probs[i].e_col) return gw::fail(ctx, GW_EINVAL, "the plasmon-pole form needs the column energies e_col");
+    if (probs[i].nv != probs[0].nv) return gw::fail(ctx, GW_EINVAL, "every problem needs the same states");
+    if (probs[i].geom->g.ngp % gw::gpp_coh_tile() != 0) return gw::fail(ctx, GW_EINVAL, "sphere padding");
+  }
+  if (nenergy < 1 || !energies) return gw::fail(ctx, GW_EINVAL, "nenergy must be >= 1");
+  for (int j = 0; j < nenergy; ++j)
+    if (!std::isfinite(energies[j])) return gw::fail(ctx, GW_EINVAL, "non-finite energy");
+  if (!(delta >= 0.0) || !std::isfinite(delta)) return gw::fail(ctx, GW_EINVAL, "delta must be finite and >= 0");
+  return GW_OK;
+}
+}  // namespace
+
+gw_status gw_sigma_coh_gpp_workspace_size(gw_ctx* ctx, const gw_chi0_problem* probs, int nq, int nenergy,
+                                          size_t* bytes) {
+  if (!ctx) return GW_EINVAL;
+  if (!bytes) return gw::fail(ctx, GW_EINVAL, "NULL argument");
+  const double e0 = 0.0;
+  std::vector<double> zero(std::max(1, nenergy), e0);
+  gw_status s = check_gpp_coh(ctx, probs, nq, nenergy, zero.data(), 0.0);
+  if (s != GW_OK) return s;
+  *bytes = gpp_coh_layout(ctx, probs, nq, nenergy).total;
+  return GW_OK;
+}
+
+gw_status gw_sigma_coh_gpp(gw_ctx* ctx, const gw_chi0_problem* probs, int nq, const double* const* vcoul,
+                           const void* const* modes, int nenergy, const double* energies, double delta,
+                           void* workspace, size_t ws_bytes, void* sigma) {
+  if (!ctx) return GW_EINVAL;
+  gw_status s = check_gpp_coh(ctx, probs, nq, nenergy, energies, delta);
+  if (s != GW_OK) return s;
+  if (!vcoul || !modes || !workspace || !sigma) return gw::fail(ctx, GW_EINVAL, "NULL argument");
+  for (int i = 0; i < nq; ++i)
+    if (!vcoul[i] || !modes[i]) return gw::fail(ctx, GW_EINVAL, "NULL Coulomb factors or plasmon-pole modes");
+  const GppCohLayout c = gpp_coh_layout(ctx, probs, nq, nenergy);
+  if (c.total > ws_bytes) return gw::fail(ctx, GW_EINVAL, "workspace too small: need " + std::to_string(c.total));
+  DeviceScope dev(ctx->device);
+  s = check_values(ctx, probs, nq);
+  if (s != GW_OK) return s;
+  char* ws = (char*)workspace;
+  const int ns = probs[0].nv;
+  const int be = gw::gpp_coh_energies_per_pass();
+  GW_HIP(ctx, gw::launch_fill_c128(sigma, (size_t)nenergy * ns * ns, ctx->stream));
+  GW_HIP(ctx, gw::launch_fill_c128(ws + c.off_part, (c.total - c.off_part) / sizeof(double2), ctx->stream));
+  auto pass_part = [&](int sa, int sb, int eb) {
+    return ws + c.off_part + ((size_t)(sa * c.nsb + sb) * c.neb + eb) * c.part_pass;
+  };
+  for (int iq = 0; iq < nq; ++iq) {
+    const gw_chi0_problem& p = probs[iq];
+    const Layout L = make_layout(ctx, &p, 1, 1, false, GW_FP64, false);
+    const ProbPlan& q = L.pp[0];
+    const Geom& g = p.geom->g;
+    char* bw = ws + round_up(L.total, 256);
+    char* wt = bw + round_up((size_t)g.ngp * g.ngp * sizeof(double2), 256);
+    GW_HIP(ctx, gw::launch_gpp_coh_prep(modes[iq], vcoul[iq], g.ng, g.ngp, bw, wt, ctx->stream));
+    s = band_to_real(ctx, L, g, (const double2*)p.coef_v, p.nv, nullptr, 0, p.nv, q.nvs, ws, ws + q.off_psiv);
+    if (s != GW_OK) return s;
+    for (int c0 = 0; c0 < p.ncol; c0 += q.cc) {
+      s = band_to_real(ctx, L, g, (const double2*)p.coef_c, p.nband, p.col_band, c0, p.ncol, q.cc, ws,
+                       ws + L.off_psic);
+      if (s != GW_OK) return s;
+      s = pair_block(ctx, L, q, ws);
+      if (s != GW_OK) return s;
+      const int nvalid = std::min(q.cc, p.ncol - c0);
+      for (int sa = 0; sa < c.nsb; ++sa)
+        for (int sb = 0; sb < c.nsb; ++sb)
+          for (int eb = 0; eb < c.neb; ++eb)
+            GW_HIP(ctx, gw::launch_gpp_coh(bw, wt, g.ngp, ws + q.off_m, q.cc, ns, sa, sb, nvalid, p.e_col, p.n_col,
+                                           c0, energies + eb * be, std::min(be, nenergy - eb * be), delta,
+                                           pass_part(sa, sb, eb), ctx->stream));
+    }
+  }
+  for (int sa = 0; sa < c.nsb; ++sa)
+    for (int sb = 0; sb < c.nsb; ++sb)
+      for (int eb = 0; eb < c.neb; ++eb)
+        GW_HIP(ctx, gw::launch_gpp_coh_sum(pass_part(sa, sb, eb), c.ngp_max, std::min(be, nenergy - eb * be), ns, sa,
+                                           sb, eb * be, sigma, ctx->stream));
   return GW_OK;
 }
 

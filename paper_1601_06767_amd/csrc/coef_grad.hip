@@ -276,11 +276,12 @@ __global__ __launch_bounds__(256) void k_bandT_ab(const double2* __restrict__ tB
 // grad[row(c)][g] += cbar[c][g] for the valid columns c < ncol of a chunk, row(c) =
 // col_band[c0 + c] (or c0 + c); one thread per g walks the columns in order.
 __global__ void k_scatter_cols(const double2* __restrict__ cbar, int ncol, const int32_t* __restrict__ col_band,
-                               int c0, int npw, double2* __restrict__ grad) {
+                               int c0, int npw, int nband, double2* __restrict__ grad) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= npw) return;
   for (int c = 0; c < ncol; ++c) {
     const int row = col_band ? col_band[c0 + c] : c0 + c;
+    if (row < 0 || row >= nband) continue;   // an out-of-range column row is never written
     double2* d = grad + (size_t)row * npw + g;
     *d = cadd(*d, cbar[(size_t)c * npw + g]);
   }
@@ -364,9 +365,10 @@ hipError_t launch_band_from_real(const Geom& g, const void* ubar, int nslot, voi
   return hipGetLastError();
 }
 
-hipError_t launch_scatter_cols(const void* cbar, int ncol, const int32_t* col_band, int c0, int npw, void* grad,
-                               hipStream_t st) {
-  k_scatter_cols<<<(npw + 255) / 256, 256, 0, st>>>((const double2*)cbar, ncol, col_band, c0, npw, (double2*)grad);
+hipError_t launch_scatter_cols(const void* cbar, int ncol, const int32_t* col_band, int c0, int npw, int nband,
+                               void* grad, hipStream_t st) {
+  k_scatter_cols<<<(npw + 255) / 256, 256, 0, st>>>((const double2*)cbar, ncol, col_band, c0, npw, nband,
+                                                    (double2*)grad);
   return hipGetLastError();
 }
 

@@ -71,6 +71,24 @@ __global__ void k_weights(const double* __restrict__ e_v, int v0, int nv_valid, 
   if (nparts == 2) w[np + p] = wi;
 }
 
+// Values the band sum cannot use set bits of *flag (NULL arrays are not read): 1 a non-finite band or column energy,
+// 2 a negative or non-finite column multiplicity, 4 a column row outside [0, nband).
+__global__ void k_check_columns(const double* __restrict__ e_v, int nv, const double* __restrict__ e_col,
+                                const double* __restrict__ n_col, const int32_t* __restrict__ col_band, int ncol,
+                                int nband, int* __restrict__ flag) {
+  int bad = 0;
+  const int n = nv > ncol ? nv : ncol;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    if (i < nv && e_v && !isfinite(e_v[i])) bad |= 1;
+    if (i < ncol) {
+      if (e_col && !isfinite(e_col[i])) bad |= 1;
+      if (n_col && !(n_col[i] >= 0.0 && isfinite(n_col[i]))) bad |= 2;
+      if (col_band && (col_band[i] < 0 || col_band[i] >= nband)) bad |= 4;
+    }
+  }
+  if (bad) atomicOr(flag, bad);
+}
+
 __device__ __forceinline__ void tile_coords(int t, int* ti, int* tj) {
   int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
   while ((i + 1) * (i + 2) / 2 <= t) ++i;
@@ -484,6 +502,14 @@ hipError_t launch_weights(const double* e_v, int v0, int nv_valid, int nvs, cons
   const int np = nvs * ncs;
   k_weights<<<(np + 255) / 256, 256, 0, st>>>(e_v, v0, nv_valid, nvs, e_col, n_col, c0, nc_valid, ncs, omega, delta,
                                                nparts, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_columns(const double* e_v, int nv, const double* e_col, const double* n_col,
+                                const int32_t* col_band, int ncol, int nband, int* flag, hipStream_t st) {
+  const int n = nv > ncol ? nv : ncol;
+  const int blocks = n < 256 * 64 ? (n + 255) / 256 : 64;
+  k_check_columns<<<blocks, 256, 0, st>>>(e_v, nv, e_col, n_col, col_band, ncol, nband, flag);
   return hipGetLastError();
 }
 

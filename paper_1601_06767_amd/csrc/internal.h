@@ -27,6 +27,8 @@ struct gw_ctx {
   hipEvent_t ev_ready[2] = {}, ev_free[2] = {}, ev_join = nullptr;
   std::string err;
   int* d_pivot_flag = nullptr;   // set by the inversion kernels on a zero pivot
+  int* d_check_flag = nullptr;   // set by the input check of the band-sum entry points
+  int* h_check_flag = nullptr;   // pinned host copy of it
   // stage timers: events recorded around launches while timing is on
   bool timing = false;
   struct Mark {
@@ -44,8 +46,11 @@ struct gw_ctx {
     std::string key;
     hipGraph_t graph;
     hipGraphExec_t exec;
+    std::vector<unsigned long long> geoms;   // ids of the geometries the captured launches read
   };
   std::vector<GraphEntry> graphs;
+  // live geometries created on this context (a context destroyed first detaches them)
+  std::vector<struct gw_geom*> geoms;
 };
 
 namespace gw {
@@ -106,12 +111,16 @@ struct Geom {
   float2* d_tw32 = nullptr;
   double2* d_twk64 = nullptr;    // [b][j] = exp(+2 pi i (j - rchi) b / nd), b < nd, j < K
   float2* d_twk32 = nullptr;
+  bool has_q = false;            // cell and q given: the dielectric sphere's order was checked
+  double q[3] = {0.0, 0.0, 0.0}; // reciprocal-lattice units
+  double cell[9] = {};           // lattice vectors as rows (bohr)
 };
 
 }  // namespace gw
 
 struct gw_geom {
   gw_ctx* ctx = nullptr;
+  unsigned long long id = 0;   // unique per geometry in the process (graph-cache keys)
   gw::Geom g;
 };
 
@@ -133,6 +142,18 @@ int coh_max_states();
 hipError_t launch_coh_kernel(const void* eps_inv, const double* v, int ng, int ngp, void* at, hipStream_t st);
 hipError_t launch_coh_reduce(const void* m, const void* z, int ns, int cc, int ngp, int nvalid, const double* n_col,
                              int c0, int nblk, void* part, void* s, hipStream_t st);
+// plasmon-pole COH self-energy (sigma.hip): (B, wt) tiles, the tile kernel over a chunk of
+// pair densities M[n][c][ngp], and the fixed-order sum of the tile partials into out[j][n][n']
+int gpp_coh_tile();
+int gpp_coh_states_per_block();
+int gpp_coh_energies_per_pass();
+size_t gpp_coh_part_bytes(int ngp);
+hipError_t launch_gpp_coh_prep(const void* modes, const double* v, int ng, int ngp, void* b, void* w, hipStream_t st);
+hipError_t launch_gpp_coh(const void* b, const void* w, int ngp, const void* m, int cc, int ns, int sa, int sb,
+                          int nvalid, const double* e_col, const double* n_col, int c0, const double* energies, int ne,
+                          double delta, void* part, hipStream_t st);
+hipError_t launch_gpp_coh_sum(const void* part, int ngp, int ne, int ns, int sa, int sb, int e0, void* out,
+                              hipStream_t st);
 // plasmon-pole extension (gpp.hip)
 hipError_t launch_gpp(const void* eps0, int ng, const double* kvec, const int32_t* gvec, const void* rho, int half,
                       const double* omega, int nomega, double eta, void* modes, void* out, hipStream_t st);
@@ -222,8 +243,8 @@ hipError_t launch_ubar(const Geom& g, const void* qbar, const void* partner, int
 // cbar[slot][npw] = the transpose of the band transform of ubar[slot] (tB: band scratch)
 hipError_t launch_band_from_real(const Geom& g, const void* ubar, int nslot, void* tB, void* cbar, hipStream_t st);
 // grad[row(c)] += cbar[c] for c < ncol, row(c) = col_band ? col_band[c0 + c] : c0 + c
-hipError_t launch_scatter_cols(const void* cbar, int ncol, const int32_t* col_band, int c0, int npw, void* grad,
-                               hipStream_t st);
+hipError_t launch_scatter_cols(const void* cbar, int ncol, const int32_t* col_band, int c0, int npw, int nband,
+                               void* grad, hipStream_t st);
 hipError_t launch_fill_c128(void* p, size_t n, hipStream_t st);
 
 // ---------------------------------------------------------------- dielectric
@@ -263,5 +284,7 @@ hipError_t launch_adjoint_pairs(const double2* part, int ntg, const double* e_v,
 hipError_t launch_adjoint_reduce(const double* dx, const double* dn, int nv, int cc, int c0, int ncol, double* g_ev,
                                  double* g_ec, double* g_n, hipStream_t st);
 hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t st);
+hipError_t launch_check_columns(const double* e_v, int nv, const double* e_col, const double* n_col,
+                                const int32_t* col_band, int ncol, int nband, int* flag, hipStream_t st);
 
 }  // namespace gw

@@ -185,8 +185,14 @@ def recip(cell: np.ndarray) -> np.ndarray:
     return 2.0 * math.pi * np.linalg.inv(cell).T
 
 
+SHELL_TOL = 1e-12   # |q+G|^2 values within this relative distance are one shell
+
+
 def chi_sphere(ng: int, q: Sequence[float], cell: np.ndarray) -> np.ndarray:
-    """First ng Miller indices in the order (|q+G|^2, n1, n2, n3); int32 (ng, 3)."""
+    """First ng Miller indices in the order (|q+G|^2, n1, n2, n3); int32 (ng, 3).
+
+    Keys that agree to a relative SHELL_TOL are one shell (equal |q+G| computed in another
+    summation order can differ in the last bit), ordered by the Miller indices."""
     q = np.asarray(q, dtype=np.float64)
     b = recip(cell)
     r = 1
@@ -198,7 +204,12 @@ def chi_sphere(ng: int, q: Sequence[float], cell: np.ndarray) -> np.ndarray:
         outside_min = ((r + 1 - np.abs(q).max()) * np.linalg.svd(b, compute_uv=False).min()) ** 2
         inside = key < outside_min
         if inside.sum() >= ng:
-            order = np.lexsort((g[:, 2], g[:, 1], g[:, 0], key))
+            by_key = np.argsort(key, kind="stable")
+            ks = key[by_key]
+            new_shell = np.concatenate([[True], ks[1:] - ks[:-1] > SHELL_TOL * np.maximum(ks[1:], ks[:-1])])
+            shell = np.empty(len(key), dtype=np.int64)
+            shell[by_key] = np.cumsum(new_shell)
+            order = np.lexsort((g[:, 2], g[:, 1], g[:, 0], shell))
             sel = order[:ng]
             if key[sel].max() < outside_min:
                 return np.ascontiguousarray(g[sel].astype(np.int32))
@@ -248,6 +259,36 @@ def gaussian_columns(cfg_index: int, stream: int, bands: Sequence[int], npw: int
         x = g.standard_normal(2 * npw).reshape(npw, 2) * math.sqrt(0.5)
         out[i] = x[:, 0] + 1j * x[:, 1]
     return out
+
+
+def gaussian_columns_threaded(cfg_index: int, stream: int, bands: Sequence[int], npw: int,
+                              workers: int = 16, out: Optional[np.ndarray] = None) -> np.ndarray:
+    """gaussian_columns with the bands split over threads (each band keeps its own generator,
+    so the rows are the same bits)."""
+    from concurrent.futures import ThreadPoolExecutor
+    bands = np.asarray(bands)
+    if out is None:
+        out = np.empty((len(bands), npw), dtype=np.complex128)
+    step = max(1, -(-len(bands) // (4 * workers)))
+
+    def job(k):
+        out[k:k + step] = gaussian_columns(cfg_index, stream, bands[k:k + step], npw)
+    with ThreadPoolExecutor(workers) as ex:
+        list(ex.map(job, range(0, len(bands), step)))
+    return out
+
+
+def orthonormalize_on_device(rows: np.ndarray, device: str = "cuda"):
+    """orthonormalize() run by torch on the GPU, the result left there (a torch tensor of rows):
+    input preparation only, for workloads whose coefficient sets are only needed on the GPU."""
+    import torch  # local: only used to speed up input preparation
+    t = torch.from_numpy(rows).to(device).T
+    q, r = torch.linalg.qr(t)
+    del t
+    d = torch.diagonal(r)
+    q.mul_(torch.conj(d / d.abs())[None, :])
+    del r
+    return q.T.contiguous()
 
 
 def orthonormalize(rows: np.ndarray, device: Optional[str] = None) -> np.ndarray:

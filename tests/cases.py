@@ -25,6 +25,7 @@ class Case:
     col_band: Optional[np.ndarray] = None
     e_col: Optional[np.ndarray] = None
     n_col: Optional[np.ndarray] = None
+    q: Optional[tuple] = None     # the q-point of the dielectric sphere (checked by the geometry when set)
 
     def columns(self):
         if self.e_col is None:
@@ -41,7 +42,7 @@ def make_case(cfg_index: int, nv: Optional[int] = None, nc: Optional[int] = None
     nc = cfg.nc if nc is None else nc
     b = synth.make_bands(cfg, v_index=np.arange(0, nv * v_stride, v_stride), c_index=np.arange(nc), gvec_wf=gw,
                          iq=iq, device=device)
-    return Case(cfg, cfg.nd, gw, gc, b.coef_v, b.e_v, b.coef_c, b.e_c)
+    return Case(cfg, cfg.nd, gw, gc, b.coef_v, b.e_v, b.coef_c, b.e_c, q=tuple(cfg.qs[iq]))
 
 
 def many_valence_rows(case: Case, nv: int, seed: int = 12) -> Case:
@@ -80,7 +81,8 @@ class Gpu:
     def geom(self, case: Case):
         key = (case.nd, case.gw.tobytes(), case.gc.tobytes())
         if key not in self._geoms:
-            self._geoms[key] = self.p.gw_geom_create(self.ctx, (case.nd,) * 3, case.gw, case.gc)
+            cell, q = (None, None) if case.q is None else (case.cfg.cell, case.q)
+            self._geoms[key] = self.p.gw_geom_create(self.ctx, (case.nd,) * 3, case.gw, case.gc, cell, q)
         return self._geoms[key]
 
     def problem(self, case: Case):

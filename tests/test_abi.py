@@ -128,3 +128,47 @@ def test_torch_complex_gradient_convention():
     b = torch.tensor([0.5, 2.0], dtype=torch.float64)
     (z.real * a + z.imag * b).sum().backward()
     assert torch.allclose(z.grad, torch.complex(a, b))
+
+
+def test_sphere_check_accepts_the_ordered_spheres_of_every_workload():
+    # the dielectric sphere is the first NG G-vectors by (|q+G|^2, n1, n2, n3); the 24^3
+    # workload's NG = 259 cuts a degenerate shell, the batched workload has q at the zone boundary
+    import synth
+    p = _lib()
+    for ci in range(5):
+        cfg = synth.config(ci)
+        for ng, q in zip(cfg.ng, cfg.qs):
+            gc = synth.chi_sphere(ng, q, cfg.cell)
+            assert p.gw_sphere_check(cfg.cell, q, gc) == "", (ci, ng, q)
+    sheared = np.array([[7.0, 0.0, 0.0], [0.6, 7.6, 0.0], [0.0, -0.4, 8.1]])
+    q = (0.13, -0.07, 0.21)
+    for ng in (1, 9, 27, 113):
+        assert p.gw_sphere_check(sheared, q, synth.chi_sphere(ng, q, sheared)) == ""
+
+
+def test_sphere_check_rejects_misordered_or_incomplete_spheres():
+    import synth
+    p = _lib()
+    cfg = synth.config(0)
+    q = cfg.qs[0]
+    gc = synth.chi_sphere(259, q, cfg.cell)
+    swapped = gc.copy()
+    swapped[[10, 40]] = swapped[[40, 10]]
+    assert "not ordered" in p.gw_sphere_check(cfg.cell, q, swapped)
+    assert "misses" in p.gw_sphere_check(cfg.cell, q, np.delete(gc, 100, axis=0))
+    # a tie broken against the Miller order: the last two entries of the cut shell swapped
+    key = (((gc + np.asarray(q)) @ synth.recip(cfg.cell)) ** 2).sum(1)
+    i = next(j for j in range(len(gc) - 1) if key[j] == key[j + 1])
+    tie = gc.copy()
+    tie[[i, i + 1]] = tie[[i + 1, i]]
+    assert "not ordered" in p.gw_sphere_check(cfg.cell, q, tie)
+    # a degenerate shell cut keeps the lower Miller indices: taking a higher one instead misses G
+    cut = gc.copy()
+    full = synth.chi_sphere(261, q, cfg.cell)
+    cut[-1] = full[-1]
+    assert p.gw_sphere_check(cfg.cell, q, cut) != ""
+    # the sphere of another q, or another cell
+    assert p.gw_sphere_check(cfg.cell, (0.5, 0.0, 0.0), gc) != ""
+    assert p.gw_sphere_check(np.eye(3) * 8.4 * np.array([1.0, 1.0, 1.3]), q, gc) != ""
+    with pytest.raises(p.GwError):
+        p.gw_sphere_check(np.zeros((3, 3)), q, gc[:0])

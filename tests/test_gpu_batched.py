@@ -58,7 +58,7 @@ def test_graph_capture_replays_match_eager(g):
     case = make_case(0, nv=6, nc=30)
     stream = torch.cuda.Stream()
     ctx = p.gw_ctx_create(0, stream)
-    geom = p.gw_geom_create(ctx, (case.nd,) * 3, case.gw, case.gc)
+    geom = p.gw_geom_create(ctx, (case.nd,) * 3, case.gw, case.gc, case.cfg.cell, case.q)
     cv, cc = g.t(case.coef_v), g.t(case.coef_c)
     ev, ec = g.t(case.e_v.copy()), g.t(case.e_c.copy())
     prob = p.make_problem(geom, cv, ev, cc, ec)
@@ -192,7 +192,7 @@ def test_chunk_overlap_with_several_problems_and_graph_replay(g):
     cases = [many_valence_rows(make_case(0, ng=ng), 400) for ng in (259, 150)]
     stream = torch.cuda.Stream()
     ctx = p.gw_ctx_create(0, stream)
-    geoms = [p.gw_geom_create(ctx, (c.nd,) * 3, c.gw, c.gc) for c in cases]
+    geoms = [p.gw_geom_create(ctx, (c.nd,) * 3, c.gw, c.gc, c.cfg.cell, c.q) for c in cases]
     probs = [p.make_problem(gm, g.t(c.coef_v), g.t(c.e_v), g.t(c.coef_c), g.t(c.e_c)) for gm, c in zip(geoms, cases)]
     ngs = [len(c.gc) for c in cases]
     om = [0.0, 3.0 / EV]
@@ -224,3 +224,39 @@ def test_chunk_overlap_with_several_problems_and_graph_replay(g):
     for gm in geoms:
         p.gw_geom_destroy(gm)
     p.gw_ctx_destroy(ctx)
+
+
+def test_graph_cache_drops_the_graphs_of_a_destroyed_geometry(g):
+    # graph mode keys a capture by its arguments; a geometry destroyed and recreated (possibly at
+    # the same host address) with another sphere size must get a capture of its own
+    torch = g.torch
+    p = g.p
+    case = make_case(0, nv=6, nc=30)
+    small = make_case(0, nv=6, nc=30, ng=150)
+    stream = torch.cuda.Stream()
+    ctx = p.gw_ctx_create(0, stream)
+    cv, cc = g.t(case.coef_v), g.t(case.coef_c)
+    ev, ec = g.t(case.e_v.copy()), g.t(case.e_c.copy())
+    ng = len(case.gc)
+    out = torch.zeros(ng * ng, dtype=torch.complex128, device=g.dev)
+    results = []
+    with torch.cuda.stream(stream):
+        p.gw_ctx_set_graph(ctx, True)
+        for c in (case, small, case):
+            geom = p.gw_geom_create(ctx, (c.nd,) * 3, c.gw, c.gc, c.cfg.cell, c.q)
+            prob = p.make_problem(geom, cv, ev, cc, ec)
+            ws = torch.empty(p.gw_chi0_workspace_size(ctx, [prob], 1, p.GW_FP64), dtype=torch.uint8, device=g.dev)
+            n = len(c.gc)
+            for _ in range(2):   # capture, then replay
+                chi = p.gw_chi0_build(ctx, [prob], [n], [0.0], 0.0, p.GW_FP64, workspace=ws, out=out)[0][0]
+                results.append(chi.clone())
+            torch.cuda.synchronize()
+            p.gw_geom_destroy(geom)
+        p.gw_ctx_set_graph(ctx, False)
+    torch.cuda.synchronize()
+    p.gw_ctx_destroy(ctx)
+    for i, c in enumerate((case, small, case)):
+        ref = ref_chi0(c, [0.0], 0.0)[0]
+        for r in results[2 * i: 2 * i + 2]:
+            assert r.shape == ref.shape
+            assert rel_err(r.cpu().numpy(), ref)[0] <= 1e-10

@@ -4,6 +4,8 @@ Tolerances: FP64 mode 1e-10 relative (Frobenius and max-abs over max |chi0|);
 pair densities 1e-12 relative; FP32 mode 2e-5 relative (float32 pair transform,
 float32 MFMA accumulation within a chunk of pairs); split-bf16 x3 mode 1e-4
 (each product keeps about 16 bits of mantissa)."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -218,3 +220,37 @@ def test_reduced_alias_free_grid_gives_the_same_chi0(g, cfg, ng, small_nd):
     # a 32^3 grid is refused (the wavefunction sphere already folds onto itself there)
     with pytest.raises(g.p.GwError, match="collide|alias"):
         g.p.gw_geom_create(g.ctx, (32,) * 3, case.gw, case.gc)
+
+
+def test_values_and_spheres_are_checked(g):
+    # the band-sum entry points check the values behind the device pointers (one synchronising
+    # read): a column row outside the coefficient rows, a negative multiplicity or a non-finite
+    # energy is GW_EINVAL; the geometry checks the dielectric sphere's order when given cell and q
+    case = make_case(0, nv=2, nc=5)
+    p = g.p
+    cases = []
+    bad_row = dataclasses.replace(case, col_band=np.array([0, 1, 5, 2], dtype=np.int32), e_col=case.e_c[:4].copy(),
+                                  n_col=np.ones(4))
+    bad_n = dataclasses.replace(case, col_band=np.arange(4, dtype=np.int32), e_col=case.e_c[:4].copy(),
+                                n_col=np.array([1.0, -0.5, 1.0, 1.0]))
+    e_nan = case.e_c.copy()
+    e_nan[2] = np.nan
+    bad_e = dataclasses.replace(case, e_c=e_nan)
+    for c, what in ((bad_row, "col_band"), (bad_n, "n_col"), (bad_e, "energy")):
+        with pytest.raises(p.GwError, match=what):
+            g.chi0(c)
+        with pytest.raises(p.GwError, match=what):
+            p.gw_chi0_backward(g.ctx, [g.problem(c)], [0.0], 0.0, p.GW_FP64,
+                               g.t(np.zeros((1, len(c.gc), len(c.gc)), dtype=np.complex128)))
+    # a good call afterwards still works
+    ref = oracle.chi0_bands(case.coef_v, case.e_v, case.coef_c, case.e_c, case.gw, case.gc, (case.nd,) * 3)[0]
+    assert np.abs(g.chi0(case)[0] - ref).max() <= 1e-10 * np.abs(ref).max()
+    # sphere order: a swapped pair, or the sphere of another q
+    swapped = case.gc.copy()
+    swapped[[3, 30]] = swapped[[30, 3]]
+    with pytest.raises(p.GwError, match="not ordered"):
+        p.gw_geom_create(g.ctx, (24,) * 3, case.gw, swapped, case.cfg.cell, case.q)
+    with pytest.raises(p.GwError):
+        p.gw_geom_create(g.ctx, (24,) * 3, case.gw, case.gc, case.cfg.cell, (0.5, 0.0, 0.0))
+    geom = p.gw_geom_create(g.ctx, (24,) * 3, case.gw, swapped)     # no cell and q: not checked
+    p.gw_geom_destroy(geom)

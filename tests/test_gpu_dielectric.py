@@ -104,3 +104,57 @@ def test_eps_inv_backward_matches_oracle(g, n):
     out = g.p.gw_eps_inv_backward(g.ctx, torch.from_numpy(v).to(g.dev), torch.from_numpy(ref_z).to(g.dev),
                                   torch.from_numpy(zbar).to(g.dev)).cpu().numpy()
     assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("herm", [True, False], ids=["static", "general"])
+@pytest.mark.parametrize("n", [2000, 4000, 8000])
+def test_eps_inv_at_the_workload_sizes(g, n, herm):
+    # the dielectric-sphere sizes of the 64-, 128- and 256-atom workloads.  Static: a Hermitian
+    # negative semidefinite chi0 with the 256-atom cell's Coulomb factors v(q+G) on its first n
+    # G-vectors (head v(q) ~ 240, tail ~ 1e-4); general: a non-Hermitian chi0 (a dynamic one).
+    torch = g.torch
+    r = np.random.default_rng(n + (7 if herm else 0))
+    a = (r.standard_normal((n, n)) + 1j * r.standard_normal((n, n))) / np.sqrt(n)
+    if herm:
+        at = torch.from_numpy(a).to(g.dev)
+        chi = (-(at @ at.conj().T.contiguous()) / 4.0).cpu().numpy()
+        cfg = synth.config(4)
+        v = synth.coulomb(synth.chi_sphere(n, cfg.qs[0], cfg.cell), cfg.qs[0], cfg.cell)
+    else:
+        chi = a
+        v = np.random.default_rng(n + 1).uniform(0.5, 3.0, n)
+    z = gpu_eps_inv(g, chi, v)
+    ref = oracle.eps_inv(chi, v)
+    err = float(np.abs(z - ref).max() / np.abs(ref).max())
+    eps = torch.from_numpy(oracle.eps_matrix(chi, v)).to(g.dev)
+    eye = torch.eye(n, dtype=torch.complex128, device=g.dev)
+    res = float((eps @ torch.from_numpy(z).to(g.dev) - eye).abs().max().item())
+    res_ref = float((eps @ torch.from_numpy(ref).to(g.dev) - eye).abs().max().item())
+    print(f"n={n} {'static' if herm else 'general'}: max|Z - Z_lapack| / max|Z_lapack| = {err:.2e}, "
+          f"max|eps Z - I| = {res:.2e} (LAPACK {res_ref:.2e}), eps_inf = {oracle.eps_inf(z):.6f} "
+          f"(LAPACK {oracle.eps_inf(ref):.6f})")
+    # two backward-stable inverses differ by about cond(eps) x 1e-16: the static eps~ is positive
+    # definite and well conditioned; the random general matrix I - diag(v) A has eigenvalues near 0
+    # (cond ~ 1e5 at n = 8000), so there the residual is held to LAPACK's own
+    assert err <= (1e-11 if herm else 1e-10)
+    assert res <= 1e-10 and res <= max(4.0 * res_ref, 1e-12)
+    if herm:
+        assert oracle.eps_inf(z) == pytest.approx(oracle.eps_inf(ref), rel=1e-12)
+        assert oracle.eps_inf(ref) > 1.0
+
+
+def test_eps_inf_of_a_chi0_with_a_nonzero_head(g):
+    # Table 3's eps_inf = 1/[eps^-1]_00 needs a head row of chi0: valence states at k+q that are
+    # not orthogonal to the conduction states (their own set, as at q away from Gamma).  The GPU
+    # build and inverse against the oracle's, whose eps_inf is pinned by the Schur complement.
+    case = make_case(0, nv=8, nc=40)
+    case.coef_v = synth.orthonormalize(case.coef_v + 0.05 * case.coef_c[:8])
+    chi = g.chi0(case)[0]
+    ref_chi = oracle.chi0_bands(case.coef_v, case.e_v, case.coef_c, case.e_c, case.gw, case.gc, (case.nd,) * 3)[0]
+    assert np.abs(ref_chi[0, 0]) > 1e-3 * np.abs(ref_chi).max()
+    assert np.abs(chi - ref_chi).max() <= 1e-10 * np.abs(ref_chi).max()
+    v = synth.coulomb(case.gc, case.cfg.qs[0], case.cfg.cell)
+    z = gpu_eps_inv(g, chi, v)
+    want = oracle.eps_inf(oracle.eps_inv(ref_chi, v))
+    assert want > 1.5
+    assert oracle.eps_inf(z) == pytest.approx(want, rel=1e-11)

@@ -32,7 +32,7 @@ def test_full_size_sampled_entries(gpu, full, prec, tol):
     cfg, gw, gc, bands, sample, ref = full
     g = Gpu()
     p = g.p
-    geom = p.gw_geom_create(g.ctx, (cfg.nd,) * 3, gw, gc)
+    geom = p.gw_geom_create(g.ctx, (cfg.nd,) * 3, gw, gc, cfg.cell, cfg.qs[0])
     prob = p.make_problem(geom, g.t(bands.coef_v), g.t(bands.e_v), g.t(bands.coef_c), g.t(bands.e_c))
     chi = p.gw_chi0_build(g.ctx, [prob], [len(gc)], [0.0], 0.0, p.PRECISIONS[prec])[0][0]
     g.torch.cuda.synchronize()
@@ -75,7 +75,7 @@ def test_full_size_grouped_sampled_entries(gpu, grouped, prec, tol):
     assert 0 < n0 < len(e_col) <= n0 + int(round((cfg.emax_ev - cfg.e0_ev) / cfg.de_ev))
     g = Gpu()
     p = g.p
-    geom = p.gw_geom_create(g.ctx, (cfg.nd,) * 3, gw, gc)
+    geom = p.gw_geom_create(g.ctx, (cfg.nd,) * 3, gw, gc, cfg.cell, cfg.qs[0])
     prob = p.make_problem(geom, g.t(bands.coef_v), g.t(bands.e_v), g.t(bands.coef_c), g.t(e_col), g.t(n_col))
     chi = p.gw_chi0_build(g.ctx, [prob], [len(gc)], [0.0], 0.0, p.PRECISIONS[prec])[0][0]
     g.torch.cuda.synchronize()
