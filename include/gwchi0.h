@@ -306,6 +306,15 @@ gw_status gw_pair_density(gw_ctx* ctx, const gw_chi0_problem* prob, int v0, int 
 gw_status gw_eps_inv_workspace_size(gw_ctx* ctx, int ng, int nbatch, size_t* bytes);
 gw_status gw_eps_inv(gw_ctx* ctx, int ng, int nbatch, const double* vcoul, const void* chi0, void* workspace,
                      size_t ws_bytes, void* eps_inv);
+/* gw_eps_inv for callers that cannot allocate (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): the same inverse and kernels, with the scratch in a static
+ * device array of the library (about 68 MiB per GPU, set up when the first context is created
+ * on a GPU and held until the process ends) instead of a workspace argument.  The caller passes
+ * inputs and outputs as for gw_eps_inv; the call allocates nothing.  ng <= 2048 (GW_EINVAL
+ * beyond: use gw_eps_inv).  Every call on a GPU shares that GPU's array, so calls that overlap on
+ * one GPU (other streams, contexts or host threads) race: serialise them.  Zero pivots are
+ * reported by gw_eps_inv_status as for gw_eps_inv. */
+gw_status gw_eps_inv_noalloc(gw_ctx* ctx, int ng, int nbatch, const double* vcoul, const void* chi0, void* eps_inv);
 /* Synchronises the stream; GW_ESINGULAR if the last gw_eps_inv met a zero pivot. */
 gw_status gw_eps_inv_status(gw_ctx* ctx);
 

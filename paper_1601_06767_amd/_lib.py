@@ -65,6 +65,7 @@ _sig("gw_pair_density", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_i
 _sig("gw_eps_inv_workspace_size", C.c_int, [vp, C.c_int, C.c_int, C.POINTER(C.c_size_t)])
 _sig("gw_eps_inv", C.c_int, [vp, C.c_int, C.c_int, vp, vp, vp, C.c_size_t, vp])
 _sig("gw_eps_inv_status", C.c_int, [vp])
+_sig("gw_eps_inv_noalloc", C.c_int, [vp, C.c_int, C.c_int, vp, vp, vp])
 _sig("gw_eps_inv_backward", C.c_int, [vp, C.c_int, C.c_int, vp, vp, vp, vp, C.c_size_t, vp])
 _sig("gw_group_windows", C.c_int, [C.c_int, dp, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double, C.c_double,
                                    i32p, dp, dp, C.POINTER(C.c_int), C.POINTER(C.c_int)])
@@ -99,7 +100,7 @@ EXPORTED = ["gw_ctx_set_timing", "gw_ctx_stage_times", "gw_ctx_set_graph", "gw_t
             "gw_version", "gw_ctx_create", "gw_ctx_destroy", "gw_last_error", "gw_geom_create", "gw_geom_destroy",
             "gw_chi0_workspace_size", "gw_chi0_build", "gw_chi0_backward", "gw_pair_density_workspace_size", "gw_pair_density",
             "gw_eps_inv_workspace_size", "gw_eps_inv", "gw_eps_inv_status", "gw_eps_inv_backward",
-            "gw_group_windows", "gw_sphere_check", "gw_sigma_coh_gpp_workspace_size", "gw_sigma_coh_gpp"]
+            "gw_group_windows", "gw_sphere_check", "gw_sigma_coh_gpp_workspace_size", "gw_sigma_coh_gpp", "gw_eps_inv_noalloc"]
 
 
 class GwError(RuntimeError):
@@ -448,6 +449,15 @@ def gw_eps_inv(ctx, vcoul, chi0, workspace=None, out=None):
         out = torch.empty_like(c)
     _check(lib.gw_eps_inv(ctx, ng, nb, _ptr(v), _ptr(c), _ptr(workspace), workspace.numel(), _ptr(out)), ctx)
     return out[0] if squeeze else out
+
+
+def gw_eps_inv_noalloc(ctx, vcoul, chi0, out):
+    """gw_eps_inv without allocation: the library's static scratch (ng <= 2048); the caller passes
+    the output (same shape as chi0, complex128)."""
+    nb = 1 if chi0.dim() == 2 else chi0.shape[0]
+    ng = chi0.shape[-1]
+    _check(lib.gw_eps_inv_noalloc(ctx, ng, nb, _ptr(vcoul), _ptr(chi0), _ptr(out)), ctx)
+    return out
 
 
 def gw_eps_inv_status(ctx) -> None:

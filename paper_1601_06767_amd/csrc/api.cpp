@@ -173,7 +173,9 @@ gw_status gw_ctx_create(int device, void* hip_stream, gw_ctx** out) {
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(device);
-  hipError_t e = hipMalloc(&c->d_pivot_flag, sizeof(int));
+  // the scratch of the allocation-free inverse: its address on this device, looked up once
+  hipError_t e = gw::noalloc_scratch_init(device);
+  if (e == hipSuccess) e = hipMalloc(&c->d_pivot_flag, sizeof(int));
   if (e == hipSuccess) e = hipMalloc(&c->d_check_flag, sizeof(int));
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_check_flag, sizeof(int), hipHostMallocDefault);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
@@ -634,6 +636,32 @@ gw_status gw_eps_inv(gw_ctx* ctx, int ng, int nbatch, const double* vcoul, const
     for (int b = 0; b < nbatch; ++b)
       GW_HIP(ctx, gw::launch_eps_inv(ng, vcoul + (size_t)b * ng, (const double2*)chi0 + b * nn,
                                      (double2*)eps_inv + b * nn, workspace, ctx->d_pivot_flag, ctx->stream));
+    return GW_OK;
+  };
+  gw_status s = run();
+  (void)hipSetDevice(prev);
+  return s;
+}
+
+gw_status gw_eps_inv_noalloc(gw_ctx* ctx, int ng, int nbatch, const double* vcoul, const void* chi0, void* eps_inv) {
+  if (!ctx) return GW_EINVAL;
+  if (ng < 1 || nbatch < 1 || !vcoul || !chi0 || !eps_inv) return gw::fail(ctx, GW_EINVAL, "bad arguments");
+  if (chi0 == eps_inv) return gw::fail(ctx, GW_EINVAL, "eps_inv may not alias chi0");
+  if (ng > gw::kNoAllocMaxNg)
+    return gw::fail(ctx, GW_EINVAL, "ng = " + std::to_string(ng) + " exceeds the allocation-free maximum of " +
+                                        std::to_string(gw::kNoAllocMaxNg) + " (use gw_eps_inv with a workspace)");
+  void* scratch = gw::noalloc_scratch(ctx->device);
+  if (!scratch) return gw::fail(ctx, GW_EDEVICE, "allocation-free scratch not set up on this device");
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(ctx->device);
+  auto run = [&]() -> gw_status {
+    GW_HIP(ctx, gw::launch_flag_clear(ctx->d_pivot_flag, ctx->stream));
+    gw::StageScope sc(ctx, gw::kStageEpsInv);
+    const size_t nn = (size_t)ng * ng;
+    for (int b = 0; b < nbatch; ++b)
+      GW_HIP(ctx, gw::launch_eps_inv(ng, vcoul + (size_t)b * ng, (const double2*)chi0 + b * nn,
+                                     (double2*)eps_inv + b * nn, scratch, ctx->d_pivot_flag, ctx->stream));
     return GW_OK;
   };
   gw_status s = run();

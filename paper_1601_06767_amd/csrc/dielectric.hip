@@ -15,6 +15,8 @@
 //
 // zgemm: C = alpha op(A) op(B) + beta C for complex128 row-major matrices, op = identity
 // or conjugate transpose, on MFMA f64 16x16x4 with 64 x 64 tiles.
+#include <mutex>
+
 #include "common.h"
 #include "internal.h"
 
@@ -330,12 +332,43 @@ hipError_t launch_zgemm(int m, int n, int k, double2 alpha, const double2* A, in
   return launch_zgemm_op(m, n, k, alpha, A, lda, cta ? kOpC : kOpN, B, ldb, ctb ? kOpC : kOpN, beta, C, ldc, st);
 }
 
-size_t eps_inv_workspace(int n) {
-  const size_t nb = kNb;
-  const size_t ncand = (n + kStepRows - 1) / kStepRows;
-  return (size_t)n * n * sizeof(double2) + 2 * (size_t)n * nb * sizeof(double2) + 2 * (size_t)n * sizeof(int) +
-         2 * ncand * (sizeof(double) + sizeof(int)) + 1024;
+constexpr size_t eps_inv_bytes(int n) {
+  return (size_t)n * n * sizeof(double2) + 2 * (size_t)n * kNb * sizeof(double2) + 2 * (size_t)n * sizeof(int) +
+         2 * (size_t)((n + kStepRows - 1) / kStepRows) * (sizeof(double) + sizeof(int)) + 1024;
 }
+
+size_t eps_inv_workspace(int n) { return eps_inv_bytes(n); }
+
+// ---------------------------------------------------------------- inverse without allocation
+// Scratch of gw_eps_inv_noalloc: one file-scope device array, one copy per GPU, held until the
+// process ends.  Host code never uses the array's name for its memory: the device address is
+// looked up once per device (noalloc_scratch_init, called with the device current when a
+// context is created there) and kept in noalloc_ptr.
+constexpr size_t kNoAllocBytes = eps_inv_bytes(kNoAllocMaxNg);
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kNoAllocMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (g_noalloc_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess) g_noalloc_ptr[device] = ptr;
+  return e;
+}
+
+void* noalloc_scratch(int device) {
+  if (device < 0 || device >= kNoAllocMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  return g_noalloc_ptr[device];
+}
+
+size_t noalloc_scratch_bytes() { return kNoAllocBytes; }
 
 hipError_t launch_eps_inv(int n, const double* v, const double2* chi, double2* out, void* ws, int* flag,
                           hipStream_t st) {

@@ -256,6 +256,12 @@ enum { kOpN = 0, kOpC = 1, kOpT = 2, kOpConj = 3 };
 hipError_t launch_zgemm_op(int m, int n, int k, double2 alpha, const double2* A, int lda, int opa, const double2* B,
                            int ldb, int opb, double2 beta, double2* C, int ldc, hipStream_t st);
 size_t eps_inv_workspace(int n);
+// allocation-free inverse: a static device scratch array for spheres up to kNoAllocMaxNg
+constexpr int kNoAllocMaxNg = 2048;
+constexpr int kNoAllocMaxDevices = 64;
+hipError_t noalloc_scratch_init(int device);   // with the device current; once per device
+void* noalloc_scratch(int device);             // its device address there (nullptr before init)
+size_t noalloc_scratch_bytes();
 hipError_t launch_eps_inv(int n, const double* v, const double2* chi, double2* out, void* ws, int* flag,
                           hipStream_t st);
 size_t eps_inv_backward_workspace(int n);
