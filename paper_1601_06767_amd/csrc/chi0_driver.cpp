@@ -43,12 +43,14 @@ struct ProbPlan {
   int nvs = 0, cc = 0, npair = 0, ksplit = 1, ntl = 0, minb = 0;
   size_t off_psiv = 0, off_m = 0, off_w = 0, off_acc = 0, acc_one = 0;
   size_t off_m2 = 0, off_w2 = 0;   // second pair-density / weight buffers of the forward build
+  size_t off_img = 0, off_img2 = 0;   // static split-bf16 x3: bf16 row images of M and w M per buffer
 };
 
 struct Layout {
   bool fp64 = true;
   size_t csz = 16;
   int nparts = 1, nomega = 1, mode = 0;
+  bool images = false;   // static split-bf16 x3 forward: the contraction reads split row images (mode 3)
   std::vector<ProbPlan> pp;
   size_t off_psic = 0, off_scr = 0, off_q = 0, off_part = 0, off_dx = 0, off_dn = 0, off_counter = 0, total = 0;
   size_t off_gsplit = 0;   // backward, split-bf16 mode: chibar split into bf16 row images
@@ -70,6 +72,7 @@ Layout make_layout(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nom
   L.nparts = complex_w ? 2 : 1;
   L.nomega = nomega;
   L.mode = mode_of(prec);
+  L.images = !backward && L.mode == 2 && nomega == 1 && !complex_w;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
@@ -96,7 +99,12 @@ Layout make_layout(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nom
   // range already share their rows).  Every split costs a float64 partial NG^2 per job, so
   // the splits are capped to keep the partials within 16 GB (or their unsplit size).  A
   // tuned choice overrides.
-  const long long want = 8LL * 256;
+  // The row-image contraction (static split-BF16x3) runs a static grid of two workgroups per
+  // CU and reads its operands through L2 in tile order, so it wants only about two items per
+  // workgroup and no cache-sized ranges: every split adds a float64 read-modify-write of a
+  // 256 KB partial per item (one 128^3 / NG 8000 chunk of 32k pairs: 21.1 ms unsplit, 21.8 with
+  // 4 splits, 25.6 with 32).
+  const long long want = L.images ? 4LL * 256 : 8LL * 256;
   const int ks_par = items >= want ? 1 : (int)std::min<long long>(32, (want + items - 1) / items);
   const int njobs = nomega * L.nparts;
   size_t acc1 = 0;   // partials of all problems with one split each
@@ -104,7 +112,7 @@ Layout make_layout(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nom
   const int ks_mem = (int)std::max<size_t>(1, (size_t(16) << 30) / std::max<size_t>(acc1, 1));
   for (auto& q : L.pp) {
     const size_t mbytes = (size_t)q.npair * q.p->geom->g.ngp * L.csz;
-    const int ks_cache = njobs > 1 ? 1 : (int)std::min<size_t>(32, (mbytes + (32u << 20) - 1) / (32u << 20));
+    const int ks_cache = njobs > 1 || L.images ? 1 : (int)std::min<size_t>(32, (mbytes + (32u << 20) - 1) / (32u << 20));
     int k = std::min(std::max(ks_par, ks_cache), ks_mem);
     auto it = ctx->tune.find(shape_key(q.p->geom->g, q.p->nv, q.p->ncol, prec));
     if (it != ctx->tune.end()) {
@@ -126,6 +134,10 @@ Layout make_layout(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nom
     q.off_w2 = backward ? q.off_w : take((size_t)nomega * L.nparts * q.npair * sizeof(double));
     q.acc_one = (size_t)q.ksplit * g.ngp * g.ngp * sizeof(double2);
     q.off_acc = backward ? 0 : take(q.acc_one * nomega * L.nparts);
+    if (L.images) {
+      q.off_img = take(gw::split_image_bytes(q.npair, g.ngp));
+      q.off_img2 = take(gw::split_image_bytes(q.npair, g.ngp));
+    }
     max_psic = std::max(max_psic, (size_t)q.cc * npts * L.csz);
     max_scr = std::max(max_scr, gw::band_scratch_bytes(g, kBandBatch, L.fp64));
     max_q = std::max(max_q, (size_t)q.npair * g.nd * g.K * g.K * L.csz);
@@ -295,11 +307,14 @@ gw_status enqueue_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, in
   // alone is the faster choice (96^3 / NG 4000 grouped step: 1.599 s alone, 1.632 s
   // overlapped).  The float64 and float32 contractions fill the register file, so the next
   // chunk's transforms queue behind them (no gain measured; capping the contraction at one
-  // workgroup per CU made float64 slower, 519 -> 558 ms).
+  // workgroup per CU made float64 slower, 519 -> 558 ms).  The static split-BF16x3 build reads
+  // row images with two 80 KB-LDS workgroups per CU, which leave nothing for the transforms:
+  // no gain either (72^3, 8 chunks of 32k pairs: 101.2 ms overlapped, 100.9 alone; 128^3,
+  // 4 chunks: 473 / 475 ms), so overlap is left to the register-staged form.
   int max_ngp = 0;
   for (const ProbPlan& q : L.pp) max_ngp = std::max(max_ngp, q.p->geom->g.ngp);
   const bool ovl =
-      nchunk > 1 && (ctx->overlap == 2 || (ctx->overlap == 1 && L.mode == 2 && max_ngp <= 2048));
+      nchunk > 1 && (ctx->overlap == 2 || (ctx->overlap == 1 && L.mode == 2 && !L.images && max_ngp <= 2048));
   hipStream_t cs = ovl ? ctx->side : ctx->stream;
   auto chunk = [&](int j) -> gw_status {
     const int buf = j & 1;
@@ -313,6 +328,7 @@ gw_status enqueue_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, in
       if (buf) {
         q.off_m = q.off_m2;
         q.off_w = q.off_w2;
+        q.off_img = q.off_img2;
       }
       const int c0 = j * q.cc;
       if (c0 >= q.p->ncol) continue;
@@ -328,6 +344,11 @@ gw_status enqueue_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, in
       }
       s = pair_block(ctx, L, q, ws);
       if (s != GW_OK) return s;
+      if (L.images) {
+        gw::StageScope sc(ctx, gw::kStageContract);
+        GW_HIP(ctx, gw::launch_split_ab(ws + q.off_m, (const double*)(ws + q.off_w), q.npair, q.p->geom->g.ngp,
+                                        ws + q.off_img, ctx->stream));
+      }
       active.push_back(i);
     }
     if (ovl) {
@@ -345,6 +366,10 @@ gw_status enqueue_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, in
       bt.item0[k] = item;
       bt.p[k] = gw::ContractProb{ws + q.off_m, (const double*)(ws + q.off_w), (double2*)(ws + q.off_acc), q.npair,
                                  q.p->geom->g.ngp, q.ksplit, q.ntl};
+      if (L.images) {
+        bt.p[k].aimg = ws + q.off_img;
+        bt.p[k].bimg = ws + q.off_img + (size_t)q.npair / 16 * q.p->geom->g.ngp * 8 * 16;
+      }
       item += (long long)items_per_job(q) * nomega * L.nparts;
     }
     bt.item0[bt.nprob] = item;
@@ -353,7 +378,7 @@ gw_status enqueue_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, in
     const int grid = (int)std::min<long long>(item, 256LL * 8);
     {
       gw::StageScope sc(ctx, gw::kStageContract, cs);
-      GW_HIP(ctx, gw::launch_contract_batch(L.mode, bt, counter, grid, !ovl, cs));
+      GW_HIP(ctx, gw::launch_contract_batch(L.images ? 3 : L.mode, bt, counter, grid, !ovl, cs));
     }
     if (ovl) GW_HIP(ctx, hipEventRecord(ctx->ev_free[buf], cs));
     return GW_OK;

@@ -97,6 +97,37 @@ __device__ __forceinline__ void tile_coords(int t, int* ti, int* tj) {
   *tj = t - i * (i + 1) / 2;
 }
 
+// The same lower triangle in 8 x 8 super-blocks of tiles (super-blocks in the order above,
+// tiles row by row inside each): a run of consecutive indices covers few distinct tile rows
+// and columns, so the workgroups of one XCD that take such a run share most operand rows in
+// their L2.
+__device__ __forceinline__ void tile_coords_blocked(int t, int nt, int* ti, int* tj) {
+  constexpr int S = 8;
+  const int ns = (nt + S - 1) / S;
+  for (int bi = 0; bi < ns; ++bi) {
+    const int r0 = bi * S, nr = min(S, nt - r0);
+    for (int bj = 0; bj <= bi; ++bj) {
+      const int c0 = bj * S, nc = min(S, nt - c0);
+      // tiles (i, j), j <= i, of this super-block
+      const int cnt = bi == bj ? nr * (nr + 1) / 2 : nr * nc;
+      if (t < cnt) {
+        if (bi == bj) {
+          int i = 0;
+          while ((i + 1) * (i + 2) / 2 <= t) ++i;
+          *ti = r0 + i;
+          *tj = c0 + t - i * (i + 1) / 2;
+        } else {
+          *ti = r0 + t / nc;
+          *tj = c0 + t % nc;
+        }
+        return;
+      }
+      t -= cnt;
+    }
+  }
+  *ti = *tj = 0;   // not reached for t < nt (nt + 1) / 2
+}
+
 // Tile geometry: TILE x TILE outputs per workgroup of NW waves on a WR x WC grid, each
 // wave owning (16 MI) x (16 NJ) outputs as MI x NJ MFMA blocks.
 template <int TILE> struct TileGeo;
@@ -400,16 +431,197 @@ __device__ void tile_bf16x3(const void* __restrict__ mv, const double* __restric
   store_tile<MI, NJ>(acc + (size_t)ks * ngp * ngp, ngp, g0 + 16 * MI * wr, h0 + 16 * NJ * wc, cre, cim, li, lg, false);
 }
 
+// ---------------------------------------------------------------- split-bf16 x3 from row images
+// Static jobs (one real weight per pair): the chunk's pair densities are split once per chunk
+// into bf16 row images (k_split_ab): per block of 16 pairs kb and row G,
+//   A[kb][G] = [hi re(16) | hi im(16) | lo re(16) | lo im(16)] of M      (8 units of 16 bytes)
+//   B[kb][G] = [hi br | hi bi | hi -bi | lo br | lo bi | lo -bi] of b = w M  (12 units)
+// and the tile stages both straight into LDS by 16-byte direct loads (global_load_lds_dwordx4)
+// into two buffers, as the split-bf16 adjoint does: no staging registers, no conversion and
+// one barrier per 16-pair stage.  LDS units of a stage: the 128 A rows of 8 (unit c of row r
+// at 8 r + (c ^ (r & 7))), then the 128 B rows of 12 (unit p at UA + 12 r + (p ^ 2 ((r >> 2) & 1)));
+// the XORs spread the 16 rows x 4 units of a fragment read over the bank groups.
+constexpr int IMT = 128;                       // tile
+constexpr int IUA = IMT * 8, IUB = IMT * 12;   // A and B units of a stage
+constexpr int IUS = IUA + IUB;
+constexpr int INT = 256;                       // threads: 4 waves, each 64 x 64 outputs
+constexpr int IUPL = IUS / INT;                // units per lane per stage
+static_assert(IUPL * INT == IUS && IUA % 64 == 0, "stage units must split into whole wave instructions");
+
+__device__ void tile_bf16x3_img(const uint4* __restrict__ aimg, const uint4* __restrict__ bimg, int nk, int ngp,
+                                int ksplit, double2* __restrict__ acc, int t, int ks, uint4* sa, uint4* sb) {
+  constexpr int MI = 4, NJ = 4;
+  int ti, tj;
+  tile_coords_blocked(t, ngp / IMT, &ti, &tj);
+  const int g0 = ti * IMT, h0 = tj * IMT;
+  const int per = range_len(nk, ksplit);
+  const int kb0 = ks * per / 16;
+  const int kb1 = min(nk, ks * per + per) / 16;   // nk and per are multiples of 16
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave >> 1, wc = wave & 1;
+  const int li = lane & 15, lg = lane >> 4;
+  // this lane's source unit of LDS unit 64 (4 i + wave) + lane at block 0 (block kb adds 8 ngp or
+  // 12 ngp units; the operand of a block of 64 units is wave-uniform)
+  unsigned off[IUPL];
+#pragma unroll
+  for (int i = 0; i < IUPL; ++i) {
+    const int ub = 4 * i + wave;
+    const int u = 64 * ub + lane;
+    if (ub * 64 < IUA) {
+      const int r = u / 8, c = (u % 8) ^ (r & 7);
+      off[i] = (unsigned)((g0 + r) * 8 + c);
+    } else {
+      const int u2 = u - IUA, r = u2 / 12, pc = (u2 % 12) ^ (2 * ((r >> 2) & 1));
+      off[i] = (unsigned)((h0 + r) * 12 + pc);
+    }
+  }
+  auto issue = [&](int kb, uint4* buf) {
+    const uint4* ab = aimg + (size_t)kb * ngp * 8;
+    const uint4* bbase = bimg + (size_t)kb * ngp * 12;
+#pragma unroll
+    for (int i = 0; i < IUPL; ++i) {
+      const int ub = 4 * i + wave;
+      const uint4* src = (ub * 64 < IUA ? ab : bbase) + off[i];
+      __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)&buf[64 * ub], 16,
+                                       0, 0);
+    }
+  };
+  f32x4 cre[MI][NJ], cim[MI][NJ];
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      cre[i][j] = f32x4{0, 0, 0, 0};
+      cim[i][j] = f32x4{0, 0, 0, 0};
+    }
+  // units of the two products' right operands: Re C takes [br | bi] (units 0..3), Im C takes
+  // [-bi | br] (units 4, 5, 0, 1); the lo copies are 6 units further
+  const int pre = lg;
+  const int pim = lg < 2 ? 4 + lg : lg - 2;
+  auto stage = [&](int kb, const uint4* cur, uint4* next) {
+    // this wave's direct loads of block kb have landed; the barrier makes everyone's visible
+    // and ends every wave's reads of the buffer that the next issue overwrites
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (kb + 1 < kb1) issue(kb + 1, next);
+    const uint4* sm = cur;
+    const uint4* sg = cur + IUA;
+    bf16x8 xh[MI], xl[MI];
+#pragma unroll
+    for (int i = 0; i < MI; ++i) {
+      const int r = 16 * MI * wr + 16 * i + li;
+      xh[i] = __builtin_bit_cast(bf16x8, sm[8 * r + (lg ^ (r & 7))]);
+      xl[i] = __builtin_bit_cast(bf16x8, sm[8 * r + ((4 + lg) ^ (r & 7))]);
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int r = 16 * NJ * wc + 16 * j + li;
+      const int sw = 2 * ((r >> 2) & 1);
+      const bf16x8 reh = __builtin_bit_cast(bf16x8, sg[12 * r + (pre ^ sw)]);
+      const bf16x8 rel = __builtin_bit_cast(bf16x8, sg[12 * r + ((6 + pre) ^ sw)]);
+      const bf16x8 imh = __builtin_bit_cast(bf16x8, sg[12 * r + (pim ^ sw)]);
+      const bf16x8 iml = __builtin_bit_cast(bf16x8, sg[12 * r + ((6 + pim) ^ sw)]);
+#pragma unroll
+      for (int i = 0; i < MI; ++i) {
+        cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[i], reh, cre[i][j], 0, 0, 0);
+        cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[i], rel, cre[i][j], 0, 0, 0);
+        cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl[i], reh, cre[i][j], 0, 0, 0);
+        cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[i], imh, cim[i][j], 0, 0, 0);
+        cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[i], iml, cim[i][j], 0, 0, 0);
+        cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl[i], imh, cim[i][j], 0, 0, 0);
+      }
+    }
+  };
+  if (kb0 < kb1) issue(kb0, sa);
+  for (int kb = kb0; kb < kb1; kb += 2) {
+    stage(kb, sa, sb);
+    if (kb + 1 < kb1) stage(kb + 1, sb, sa);
+  }
+  store_tile<MI, NJ>(acc + (size_t)ks * ngp * ngp, ngp, g0 + 16 * MI * wr, h0 + 16 * NJ * wc, cre, cim, li, lg, false);
+}
+
+// Static schedule over the batch's items (no item counter, so that two workgroups of 80 KB of
+// LDS share a CU).  Workgroups are dealt to the 8 XCDs round robin (workgroup b to XCD b mod 8),
+// so each pass over a grid's worth of items gives XCD x the contiguous run of items
+// [x grid / 8, (x + 1) grid / 8): with the blocked tile order, one compact group of tiles per
+// L2.  The grid is a multiple of 8.  The barrier at the top of each item ends every wave's
+// reads of the buffers before the next item's first loads.
+__global__ __launch_bounds__(INT, 2) void k_contract_img(ContractBatch bt) {
+  __shared__ __align__(16) uint4 sa[IUS];
+  __shared__ __align__(16) uint4 sb[IUS];
+  const long long n = bt.item0[bt.nprob];
+  const int per_xcd = gridDim.x / 8;
+  const int slot = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  for (long long base = 0; base + slot < n; base += gridDim.x) {
+    const long long item = base + slot;
+    __syncthreads();
+    int b = 0;
+    while (b + 1 < bt.nprob && item >= bt.item0[b + 1]) ++b;
+    const ContractProb& p = bt.p[b];
+    const long long local = item - bt.item0[b];
+    const int per_job = p.ntl * p.ksplit;
+    const int job = (int)(local / per_job);
+    const int rem = (int)(local % per_job);
+    double2* acc = p.acc + (size_t)job * p.ksplit * p.ngp * p.ngp;
+    tile_bf16x3_img((const uint4*)p.aimg, (const uint4*)p.bimg, p.nk, p.ngp, p.ksplit, acc, rem % p.ntl,
+                    rem / p.ntl, sa, sb);
+  }
+}
+
+// Row images of one chunk: one thread per (G, half h of a 16-pair block) packs whole 16-byte units
+// (8 pairs) of the row: A units h, 2 + h, 4 + h, 6 + h and B units h, 2 + h, 4 + h, 6 + h, 8 + h,
+// 10 + h.  Loads of M run along G (two lanes per G, the halves 8 rows apart); the two lanes of a G
+// together write its whole A and B rows.
+__global__ __launch_bounds__(256) void k_split_ab(const float2* __restrict__ m, const double* __restrict__ w, int ngp,
+                                                  uint4* __restrict__ aimg, uint4* __restrict__ bimg) {
+  const int kb = blockIdx.y;
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int g = t >> 1, h = t & 1;
+  if (g >= ngp) return;
+  u16x8 ahr, ahi, alr, ali, bhr, bhi, blr, bli;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int k = 16 * kb + 8 * h + e;
+    const float2 x = m[(size_t)k * ngp + g];
+    const float sw = (float)w[k];
+    const float yr = x.x * sw, yi = x.y * sw;
+    const unsigned short a0 = bf16_rne(x.x), a1 = bf16_rne(x.y);
+    ahr[e] = a0;
+    ahi[e] = a1;
+    alr[e] = bf16_rne(x.x - bf16_val(a0));
+    ali[e] = bf16_rne(x.y - bf16_val(a1));
+    const unsigned short b0 = bf16_rne(yr), b1 = bf16_rne(yi);
+    bhr[e] = b0;
+    bhi[e] = b1;
+    blr[e] = bf16_rne(yr - bf16_val(b0));
+    bli[e] = bf16_rne(yi - bf16_val(b1));
+  }
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4 sign = {0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};   // bf16 negation: -hi, -lo split -bi
+  uint4* ad = aimg + ((size_t)kb * ngp + g) * 8;
+  ad[h] = __builtin_bit_cast(uint4, ahr);
+  ad[2 + h] = __builtin_bit_cast(uint4, ahi);
+  ad[4 + h] = __builtin_bit_cast(uint4, alr);
+  ad[6 + h] = __builtin_bit_cast(uint4, ali);
+  uint4* bd = bimg + ((size_t)kb * ngp + g) * 12;
+  bd[h] = __builtin_bit_cast(uint4, bhr);
+  bd[2 + h] = __builtin_bit_cast(uint4, bhi);
+  bd[4 + h] = __builtin_bit_cast(uint4, __builtin_bit_cast(u32x4, bhi) ^ sign);
+  bd[6 + h] = __builtin_bit_cast(uint4, blr);
+  bd[8 + h] = __builtin_bit_cast(uint4, bli);
+  bd[10 + h] = __builtin_bit_cast(uint4, __builtin_bit_cast(u32x4, bli) ^ sign);
+}
+
 // ---------------------------------------------------------------- kernels
-template <int MODE, int TILE>   // MODE 0 f64, 1 f32, 2 bf16x3
-__device__ __forceinline__ void run_item(const void* m, const double* w, int nk, int ngp, int ksplit, double2* acc,
-                                         int t, int ks) {
+template <int MODE, int TILE>   // MODE 0 f64, 1 f32, 2 bf16x3 (register-staged)
+__device__ __forceinline__ void run_item(const ContractProb& p, const double* w, double2* acc, int t, int ks) {
   if constexpr (MODE == 0)
-    tile_mfma<double, TILE>((const double2*)m, w, nk, ngp, ksplit, acc, t, ks);
+    tile_mfma<double, TILE>((const double2*)p.m, w, p.nk, p.ngp, p.ksplit, acc, t, ks);
   else if constexpr (MODE == 1)
-    tile_mfma<float, TILE>((const float2*)m, w, nk, ngp, ksplit, acc, t, ks);
+    tile_mfma<float, TILE>((const float2*)p.m, w, p.nk, p.ngp, p.ksplit, acc, t, ks);
   else
-    tile_bf16x3<TILE>(m, w, nk, ngp, ksplit, acc, t, ks);
+    tile_bf16x3<TILE>(p.m, w, p.nk, p.ngp, p.ksplit, acc, t, ks);
 }
 
 // Persistent grid over all items of a batch; items of problem b occupy
@@ -438,7 +650,7 @@ __global__ __launch_bounds__(64 * TileGeo<TILE>::NW, MINW) void k_contract_batch
     const int rem = (int)(local % per_job);
     const double* w = p.w + (size_t)job * p.nk;
     double2* acc = p.acc + (size_t)job * p.ksplit * p.ngp * p.ngp;
-    run_item<MODE, TILE>(p.m, w, p.nk, p.ngp, p.ksplit, acc, rem % p.ntl, rem / p.ntl);
+    run_item<MODE, TILE>(p, w, acc, rem % p.ntl, rem / p.ntl);
   }
 }
 
@@ -515,13 +727,30 @@ hipError_t launch_check_columns(const double* e_v, int nv, const double* e_col, 
 
 int contract_tile(int mode) { return mode == 0 ? 64 : 128; }
 
+size_t split_image_bytes(int npair, int ngp) { return (size_t)npair * ngp * 20; }
+
+hipError_t launch_split_ab(const void* m, const double* w, int npair, int ngp, void* img, hipStream_t st) {
+  if (npair % 16 != 0 || ngp % 128 != 0) return hipErrorInvalidValue;
+  uint4* a = (uint4*)img;
+  uint4* b = a + (size_t)npair / 16 * ngp * 8;
+  k_split_ab<<<dim3(ngp / 128, npair / 16), 256, 0, st>>>((const float2*)m, w, ngp, a, b);
+  return hipGetLastError();
+}
+
 // Tiles per mode (contract_tile): 64 in float64, 128 in float32 and split-bf16 x3; only
 // these forms are built.
 hipError_t launch_contract_batch(int mode, const ContractBatch& bt, int* counter, int grid, bool alone,
                                  hipStream_t st) {
   for (int b = 0; b < bt.nprob; ++b)
     if (bt.p[b].ngp % contract_tile(mode) != 0) return hipErrorInvalidValue;
-  if (mode == 0)
+  if (mode == 3) {
+    for (int b = 0; b < bt.nprob; ++b)
+      if (!bt.p[b].aimg || !bt.p[b].bimg || bt.p[b].nk % 16 != 0) return hipErrorInvalidValue;
+    (void)counter;
+    long long items = bt.item0[bt.nprob];
+    const int g2 = (int)std::min<long long>((items + 7) / 8 * 8, 2LL * 256);
+    k_contract_img<<<std::max(g2, 8), INT, 0, st>>>(bt);
+  } else if (mode == 0)
     k_contract_batch<0, 64><<<grid, 64 * TileGeo<64>::NW, 0, st>>>(bt, counter);
   else if (mode == 1)
     k_contract_batch<1, 128><<<grid, 64 * TileGeo<128>::NW, 0, st>>>(bt, counter);

@@ -208,6 +208,8 @@ struct ContractProb {
   const double* w;
   double2* acc;
   int nk, ngp, ksplit, ntl;
+  const void* aimg = nullptr;   // mode 3: the bf16 row images of M and w M (launch_split_ab)
+  const void* bimg = nullptr;
 };
 constexpr int kMaxBatch = 16;
 struct ContractBatch {
@@ -228,6 +230,11 @@ hipError_t launch_copy_m(const void* m, int nvs, int ncs, int ncs_pad, int ng, i
 
 constexpr int kTile = 128;  // the dielectric-sphere padding: a multiple of every contraction tile
 int contract_tile(int mode);   // G x G' tile of the contraction in this mode (64 or 128)
+// static split-bf16 x3: the chunk's M (float, npair x ngp) and w M split into bf16 row images
+// per 16-pair block, A [npair/16][ngp][8 units] then B [npair/16][ngp][12 units] (16-byte units),
+// which mode 3 of launch_contract_batch stages by direct loads
+size_t split_image_bytes(int npair, int ngp);
+hipError_t launch_split_ab(const void* m, const double* w, int npair, int ngp, void* img, hipStream_t st);
 
 // ---------------------------------------------------------------- coefficient gradients (float64)
 // a = diag(s) m over npair rows of ngp, s_p = w_p or conj(w_p) (w as launch_weights writes it)
@@ -264,6 +271,11 @@ void* noalloc_scratch(int device);             // its device address there (null
 size_t noalloc_scratch_bytes();
 hipError_t launch_eps_inv(int n, const double* v, const double2* chi, double2* out, void* ws, int* flag,
                           hipStream_t st);
+// static chi0 (Hermitian, negative semidefinite) and v > 0: block sweeps of the positive
+// definite I - V^1/2 chi0 V^1/2 (lower triangle of chi read); a pivot block that is not
+// positive definite sets *flag.  Workspace: eps_inv_workspace(n) covers it.
+hipError_t launch_eps_inv_sweep(int n, const double* v, const double2* chi, double2* out, void* ws, int* flag,
+                                hipStream_t st);
 size_t eps_inv_backward_workspace(int n);
 hipError_t launch_eps_inv_backward(int n, const double* v, const double2* z, const double2* zbar, double2* out,
                                    void* ws, hipStream_t st);
