@@ -89,10 +89,11 @@ gw_status gw_ctx_stage_times(gw_ctx* ctx, double* ms, long long* counts, int res
  * stream of the context while the band and pair transforms of the next chunk run on the
  * context's stream, with events between the two and a join before the call's last
  * launches, so the call stays ordered on the context's stream.
- *   mode 0  off;  1  where it pays (default): the split-BF16x3 mode with dielectric
- *   spheres of at most 2048 (padded) G-vectors, whose contraction then leaves room on each
- *   CU for a pair-transform workgroup (without overlap that contraction holds two
- *   workgroups per CU instead, which is faster for larger spheres);  2  in every mode.
+ *   mode 0  off;  1  where it pays (default): the split-BF16x3 mode of a dynamic build
+ *   (several frequencies or delta > 0) with dielectric spheres of at most 2048 (padded)
+ *   G-vectors, whose register-staged contraction then leaves room on each CU for a
+ *   pair-transform workgroup (the static split-BF16x3 contraction fills the CU's LDS and
+ *   runs alone);  2  in every mode.
  * The results do not depend on the mode (same arithmetic, same summation order).  With
  * timing on, the contraction's stage time is measured on the second stream and overlaps
  * the others.  GW_EINVAL for another mode. */
@@ -297,25 +298,35 @@ gw_status gw_pair_density(gw_ctx* ctx, const gw_chi0_problem* prob, int v0, int 
 
 /* eps^-1 = (I - diag(v) chi0)^-1 for nbatch matrices, in float64 (RPA relation before
  * Eq. (chi0); Table 3's eps_inf = 1/[eps^-1]_00).
+ *   hermitian 0: any chi0 (a dynamic one included): Gauss-Jordan elimination with partial
+ *             pivoting.  1: a static chi0, Hermitian and negative semidefinite, with v > 0: then
+ *             eps~ = I - V^1/2 chi0 V^1/2 is Hermitian positive definite, eps^-1 = V^1/2 eps~^-1
+ *             V^-1/2, and eps~ is inverted by block sweeps (a Cholesky factor per 64 x 64 pivot
+ *             block, no pivoting, half the arithmetic); only the lower triangle of chi0
+ *             (i >= j) is read.  Other values: GW_EINVAL.
  *   vcoul     device, nbatch x ng doubles, v(q+G) including its normalisation.
  *   chi0      device complex128, nbatch x ng x ng row-major.
  *   eps_inv   device complex128 output, same shape; may not alias chi0.
- *   workspace device scratch of at least gw_eps_inv_workspace_size bytes.
- * Gauss-Jordan elimination with partial pivoting on the stream.  GW_ESINGULAR is
- * reported by gw_eps_inv_status after the stream has run. */
+ *   workspace device scratch of at least gw_eps_inv_workspace_size bytes (either route).
+ * Runs on the stream.  GW_ESINGULAR is reported by gw_eps_inv_status after the stream has
+ * run: a zero or non-finite pivot, or with hermitian = 1 a pivot block that is not positive
+ * definite or a v <= 0 (the output is then undefined; a chi0 that is not negative
+ * semidefinite needs hermitian = 0). */
 gw_status gw_eps_inv_workspace_size(gw_ctx* ctx, int ng, int nbatch, size_t* bytes);
-gw_status gw_eps_inv(gw_ctx* ctx, int ng, int nbatch, const double* vcoul, const void* chi0, void* workspace,
-                     size_t ws_bytes, void* eps_inv);
+gw_status gw_eps_inv(gw_ctx* ctx, int ng, int nbatch, int hermitian, const double* vcoul, const void* chi0,
+                     void* workspace, size_t ws_bytes, void* eps_inv);
 /* gw_eps_inv for callers that cannot allocate (code under HIP graph capture, serving loops,
  * harnesses that forbid hipMalloc): the same inverse and kernels, with the scratch in a static
  * device array of the library (about 68 MiB per GPU, set up when the first context is created
  * on a GPU and held until the process ends) instead of a workspace argument.  The caller passes
- * inputs and outputs as for gw_eps_inv; the call allocates nothing.  ng <= 2048 (GW_EINVAL
+ * inputs, hermitian and outputs as for gw_eps_inv; the call allocates nothing.  ng <= 2048 (GW_EINVAL
  * beyond: use gw_eps_inv).  Every call on a GPU shares that GPU's array, so calls that overlap on
  * one GPU (other streams, contexts or host threads) race: serialise them.  Zero pivots are
  * reported by gw_eps_inv_status as for gw_eps_inv. */
-gw_status gw_eps_inv_noalloc(gw_ctx* ctx, int ng, int nbatch, const double* vcoul, const void* chi0, void* eps_inv);
-/* Synchronises the stream; GW_ESINGULAR if the last gw_eps_inv met a zero pivot. */
+gw_status gw_eps_inv_noalloc(gw_ctx* ctx, int ng, int nbatch, int hermitian, const double* vcoul, const void* chi0,
+                             void* eps_inv);
+/* Synchronises the stream; GW_ESINGULAR if the last gw_eps_inv met a zero pivot (or, with
+ * hermitian = 1, a pivot block that is not positive definite). */
 gw_status gw_eps_inv_status(gw_ctx* ctx);
 
 /* Adjoint of gw_eps_inv for a real loss L: with Z = eps^-1 (the saved output) and

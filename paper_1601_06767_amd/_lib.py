@@ -63,9 +63,9 @@ _sig("gw_pair_density_workspace_size", C.c_int, [vp, C.POINTER(gw_chi0_problem),
 _sig("gw_pair_density", C.c_int, [vp, C.POINTER(gw_chi0_problem), C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                   vp, C.c_size_t, vp])
 _sig("gw_eps_inv_workspace_size", C.c_int, [vp, C.c_int, C.c_int, C.POINTER(C.c_size_t)])
-_sig("gw_eps_inv", C.c_int, [vp, C.c_int, C.c_int, vp, vp, vp, C.c_size_t, vp])
+_sig("gw_eps_inv", C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, vp, vp, C.c_size_t, vp])
 _sig("gw_eps_inv_status", C.c_int, [vp])
-_sig("gw_eps_inv_noalloc", C.c_int, [vp, C.c_int, C.c_int, vp, vp, vp])
+_sig("gw_eps_inv_noalloc", C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, vp, vp])
 _sig("gw_eps_inv_backward", C.c_int, [vp, C.c_int, C.c_int, vp, vp, vp, vp, C.c_size_t, vp])
 _sig("gw_group_windows", C.c_int, [C.c_int, dp, C.c_double, C.c_double, C.c_int, C.c_int, C.c_double, C.c_double,
                                    i32p, dp, dp, C.POINTER(C.c_int), C.POINTER(C.c_int)])
@@ -161,7 +161,7 @@ def gw_tune(ctx, problems, nomega: int, prec: int, workspace=None) -> None:
 
 def gw_ctx_set_overlap(ctx, mode: int) -> None:
     """Chunk overlap of gw_chi0_build on a second stream: 0 off, 1 where it pays (default,
-    split-BF16x3), 2 always."""
+    dynamic split-BF16x3 builds at NG <= 2048), 2 always."""
     _check(lib.gw_ctx_set_overlap(ctx, int(mode)), ctx)
 
 
@@ -435,8 +435,9 @@ def gw_eps_inv_workspace_size(ctx, ng: int, nbatch: int) -> int:
     return n.value
 
 
-def gw_eps_inv(ctx, vcoul, chi0, workspace=None, out=None):
-    """(I - diag(v) chi0)^-1 for chi0 of shape (nbatch, ng, ng) (or (ng, ng)), vcoul (nbatch, ng) or (ng,)."""
+def gw_eps_inv(ctx, vcoul, chi0, workspace=None, out=None, hermitian=False):
+    """(I - diag(v) chi0)^-1 for chi0 of shape (nbatch, ng, ng) (or (ng, ng)), vcoul (nbatch, ng) or (ng,);
+    hermitian=True for a static (Hermitian negative semidefinite) chi0 and v > 0."""
     import torch
     squeeze = chi0.dim() == 2
     c = chi0.reshape(-1, chi0.shape[-1], chi0.shape[-1]).contiguous()
@@ -447,16 +448,17 @@ def gw_eps_inv(ctx, vcoul, chi0, workspace=None, out=None):
                                 dtype=torch.uint8, device=c.device)
     if out is None:
         out = torch.empty_like(c)
-    _check(lib.gw_eps_inv(ctx, ng, nb, _ptr(v), _ptr(c), _ptr(workspace), workspace.numel(), _ptr(out)), ctx)
+    _check(lib.gw_eps_inv(ctx, ng, nb, 1 if hermitian else 0, _ptr(v), _ptr(c), _ptr(workspace), workspace.numel(),
+                          _ptr(out)), ctx)
     return out[0] if squeeze else out
 
 
-def gw_eps_inv_noalloc(ctx, vcoul, chi0, out):
+def gw_eps_inv_noalloc(ctx, vcoul, chi0, out, hermitian=False):
     """gw_eps_inv without allocation: the library's static scratch (ng <= 2048); the caller passes
     the output (same shape as chi0, complex128)."""
     nb = 1 if chi0.dim() == 2 else chi0.shape[0]
     ng = chi0.shape[-1]
-    _check(lib.gw_eps_inv_noalloc(ctx, ng, nb, _ptr(vcoul), _ptr(chi0), _ptr(out)), ctx)
+    _check(lib.gw_eps_inv_noalloc(ctx, ng, nb, 1 if hermitian else 0, _ptr(vcoul), _ptr(chi0), _ptr(out)), ctx)
     return out
 
 

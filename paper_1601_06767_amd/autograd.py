@@ -47,8 +47,8 @@ class _Chi0(torch.autograd.Function):
 
 class _EpsInv(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, chi, vcoul, gctx):
-        z = L.gw_eps_inv(gctx, vcoul, chi.detach())
+    def forward(ctx, chi, vcoul, gctx, hermitian):
+        z = L.gw_eps_inv(gctx, vcoul, chi.detach(), hermitian=hermitian)
         L.gw_eps_inv_status(gctx)
         ctx.save_for_backward(z, vcoul)
         ctx.gctx = gctx
@@ -57,7 +57,7 @@ class _EpsInv(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gz):
         z, v = ctx.saved_tensors
-        return L.gw_eps_inv_backward(ctx.gctx, v, z, gz.contiguous()), None, None
+        return L.gw_eps_inv_backward(ctx.gctx, v, z, gz.contiguous()), None, None, None
 
 
 _geom_ng = {}
@@ -79,6 +79,7 @@ def chi0(gctx, geom, coef_v, e_v, coef_c, e_col, n_col: Optional[torch.Tensor] =
                        float(delta), L.PRECISIONS[prec])
 
 
-def eps_inv(gctx, chi, vcoul):
-    """Differentiable (I - diag(v) chi)^-1 in float64."""
-    return _EpsInv.apply(chi, vcoul, gctx)
+def eps_inv(gctx, chi, vcoul, hermitian: bool = False):
+    """Differentiable (I - diag(v) chi)^-1 in float64 (hermitian=True: the static route, for a
+    Hermitian negative semidefinite chi and v > 0; the gradient is the same)."""
+    return _EpsInv.apply(chi, vcoul, gctx, bool(hermitian))

@@ -619,13 +619,13 @@ gw_status gw_eps_inv_workspace_size(gw_ctx* ctx, int ng, int nbatch, size_t* byt
   return GW_OK;
 }
 
-gw_status gw_eps_inv(gw_ctx* ctx, int ng, int nbatch, const double* vcoul, const void* chi0, void* workspace,
-                     size_t ws_bytes, void* eps_inv) {
-  if (!ctx) return GW_EINVAL;
-  if (ng < 1 || nbatch < 1 || !vcoul || !chi0 || !workspace || !eps_inv) return gw::fail(ctx, GW_EINVAL, "bad arguments");
-  if (chi0 == eps_inv) return gw::fail(ctx, GW_EINVAL, "eps_inv may not alias chi0");
-  if (ws_bytes < gw::eps_inv_workspace(ng))
-    return gw::fail(ctx, GW_EINVAL, "workspace too small: need " + std::to_string(gw::eps_inv_workspace(ng)));
+}  // extern "C"
+
+namespace {
+// nbatch inverses on the context's stream: the pivoted Gauss-Jordan route, or the block sweeps
+// of the static (Hermitian) form
+gw_status eps_inv_batch(gw_ctx* ctx, int ng, int nbatch, int hermitian, const double* vcoul, const void* chi0,
+                        void* ws, void* eps_inv) {
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(ctx->device);
@@ -633,40 +633,46 @@ gw_status gw_eps_inv(gw_ctx* ctx, int ng, int nbatch, const double* vcoul, const
     GW_HIP(ctx, gw::launch_flag_clear(ctx->d_pivot_flag, ctx->stream));
     gw::StageScope sc(ctx, gw::kStageEpsInv);
     const size_t nn = (size_t)ng * ng;
-    for (int b = 0; b < nbatch; ++b)
-      GW_HIP(ctx, gw::launch_eps_inv(ng, vcoul + (size_t)b * ng, (const double2*)chi0 + b * nn,
-                                     (double2*)eps_inv + b * nn, workspace, ctx->d_pivot_flag, ctx->stream));
+    for (int b = 0; b < nbatch; ++b) {
+      const double* v = vcoul + (size_t)b * ng;
+      const double2* c = (const double2*)chi0 + b * nn;
+      double2* z = (double2*)eps_inv + b * nn;
+      GW_HIP(ctx, hermitian ? gw::launch_eps_inv_sweep(ng, v, c, z, ws, ctx->d_pivot_flag, ctx->stream)
+                            : gw::launch_eps_inv(ng, v, c, z, ws, ctx->d_pivot_flag, ctx->stream));
+    }
     return GW_OK;
   };
   gw_status s = run();
   (void)hipSetDevice(prev);
   return s;
 }
+}  // namespace
 
-gw_status gw_eps_inv_noalloc(gw_ctx* ctx, int ng, int nbatch, const double* vcoul, const void* chi0, void* eps_inv) {
+extern "C" {
+
+gw_status gw_eps_inv(gw_ctx* ctx, int ng, int nbatch, int hermitian, const double* vcoul, const void* chi0,
+                     void* workspace, size_t ws_bytes, void* eps_inv) {
+  if (!ctx) return GW_EINVAL;
+  if (ng < 1 || nbatch < 1 || !vcoul || !chi0 || !workspace || !eps_inv) return gw::fail(ctx, GW_EINVAL, "bad arguments");
+  if (hermitian != 0 && hermitian != 1) return gw::fail(ctx, GW_EINVAL, "hermitian must be 0 or 1");
+  if (chi0 == eps_inv) return gw::fail(ctx, GW_EINVAL, "eps_inv may not alias chi0");
+  if (ws_bytes < gw::eps_inv_workspace(ng))
+    return gw::fail(ctx, GW_EINVAL, "workspace too small: need " + std::to_string(gw::eps_inv_workspace(ng)));
+  return eps_inv_batch(ctx, ng, nbatch, hermitian, vcoul, chi0, workspace, eps_inv);
+}
+
+gw_status gw_eps_inv_noalloc(gw_ctx* ctx, int ng, int nbatch, int hermitian, const double* vcoul, const void* chi0,
+                             void* eps_inv) {
   if (!ctx) return GW_EINVAL;
   if (ng < 1 || nbatch < 1 || !vcoul || !chi0 || !eps_inv) return gw::fail(ctx, GW_EINVAL, "bad arguments");
+  if (hermitian != 0 && hermitian != 1) return gw::fail(ctx, GW_EINVAL, "hermitian must be 0 or 1");
   if (chi0 == eps_inv) return gw::fail(ctx, GW_EINVAL, "eps_inv may not alias chi0");
   if (ng > gw::kNoAllocMaxNg)
     return gw::fail(ctx, GW_EINVAL, "ng = " + std::to_string(ng) + " exceeds the allocation-free maximum of " +
                                         std::to_string(gw::kNoAllocMaxNg) + " (use gw_eps_inv with a workspace)");
   void* scratch = gw::noalloc_scratch(ctx->device);
   if (!scratch) return gw::fail(ctx, GW_EDEVICE, "allocation-free scratch not set up on this device");
-  int prev = 0;
-  (void)hipGetDevice(&prev);
-  (void)hipSetDevice(ctx->device);
-  auto run = [&]() -> gw_status {
-    GW_HIP(ctx, gw::launch_flag_clear(ctx->d_pivot_flag, ctx->stream));
-    gw::StageScope sc(ctx, gw::kStageEpsInv);
-    const size_t nn = (size_t)ng * ng;
-    for (int b = 0; b < nbatch; ++b)
-      GW_HIP(ctx, gw::launch_eps_inv(ng, vcoul + (size_t)b * ng, (const double2*)chi0 + b * nn,
-                                     (double2*)eps_inv + b * nn, scratch, ctx->d_pivot_flag, ctx->stream));
-    return GW_OK;
-  };
-  gw_status s = run();
-  (void)hipSetDevice(prev);
-  return s;
+  return eps_inv_batch(ctx, ng, nbatch, hermitian, vcoul, chi0, scratch, eps_inv);
 }
 
 gw_status gw_eps_inv_status(gw_ctx* ctx) {
@@ -674,7 +680,10 @@ gw_status gw_eps_inv_status(gw_ctx* ctx) {
   int flag = 0;
   GW_HIP(ctx, hipStreamSynchronize(ctx->stream));
   GW_HIP(ctx, hipMemcpy(&flag, ctx->d_pivot_flag, sizeof(int), hipMemcpyDeviceToHost));
-  if (flag) return gw::fail(ctx, GW_ESINGULAR, "zero or non-finite pivot in eps = I - v chi0");
+  if (flag)
+    return gw::fail(ctx, GW_ESINGULAR,
+                    "zero or non-finite pivot in eps = I - v chi0 (hermitian = 1: I - V^1/2 chi0 V^1/2 not positive "
+                    "definite, or v <= 0)");
   return GW_OK;
 }
 

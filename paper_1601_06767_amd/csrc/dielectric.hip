@@ -317,6 +317,193 @@ __global__ __launch_bounds__(256) void k_zgemm(int m, int n, int kd, double2 alp
       }
 }
 
+
+// ---------------------------------------------------------------- static inverse by block sweeps
+// For a static chi0 (Hermitian, negative semidefinite) and v > 0, eps~ = I - V^1/2 chi0 V^1/2 is
+// Hermitian positive definite and eps^-1 = V^1/2 eps~^-1 V^-1/2.  The sweep operator on a block K
+// of 64 indices, D = A_KK:
+//   A_ij -= A_iK D^-1 A_Kj (i, j outside K),  A_iK <- A_iK D^-1,  A_Kj <- D^-1 A_Kj,  A_KK <- -D^-1;
+// sweeping every block in turn leaves -A^-1.  The part not yet swept is a Schur complement of
+// eps~, positive definite, so D needs no pivoting: D = L L^H, and the update is the Hermitian
+// rank-64 product A -= C C^H with C = A_.K L^-H, on the lower 64 x 64 tiles only (the float64
+// MFMA contraction tile).  Only the lower triangle is stored.  Half the arithmetic of the
+// pivoted Gauss-Jordan path and four launches per block of 64 instead of about 68.
+constexpr int kSw = 64;
+
+// lower triangle a[i][j] = delta_ij - sqrt(v_i) chi_ij sqrt(v_j) (i >= j), identity in the padding
+__global__ void k_sweep_form(const double* __restrict__ v, const double2* __restrict__ chi, int n, int ldp,
+                             double2* __restrict__ a, int* __restrict__ flag) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)ldp * ldp) return;
+  const int i = (int)(e / ldp), j = (int)(e % ldp);
+  if (j > i) return;
+  double2 x{i == j ? 1.0 : 0.0, 0.0};
+  if (i < n && j < n) {
+    const double vi = v[i], vj = v[j];
+    double s = 0.0;   // a v <= 0 is reported; the entry is then left at the identity's
+    if (!(vi > 0.0) || !(vj > 0.0))
+      atomicOr(flag, 1);
+    else
+      s = sqrt(vi) * sqrt(vj);
+    const double2 c = chi[(size_t)i * n + j];
+    x.x -= s * c.x;
+    x.y -= s * c.y;
+  }
+  a[e] = x;
+}
+
+// one workgroup: D = A_KK (lower) = L L^H in LDS, X = L^-1, then linvT[l][k] = X[k][l] and
+// dinv = X^H X = D^-1 (full 64 x 64).  A pivot that is not positive sets the flag.
+__global__ __launch_bounds__(256) void k_sweep_diag(const double2* __restrict__ a, int ldp, int k0,
+                                                    double2* __restrict__ linvT, double2* __restrict__ dinv,
+                                                    int* __restrict__ flag) {
+  __shared__ double2 L[kSw][kSw + 1];
+  __shared__ double2 X[kSw][kSw + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kSw * kSw; e += 256) {
+    const int r = e / kSw, c = e % kSw;
+    L[r][c] = c <= r ? a[(size_t)(k0 + r) * ldp + k0 + c] : double2{0.0, 0.0};
+  }
+  __syncthreads();
+  for (int j = 0; j < kSw; ++j) {
+    if (tid == 0) {
+      double d = L[j][j].x;
+      if (!(d > 0.0) || !isfinite(d)) {
+        atomicOr(flag, 1);
+        d = 1.0;
+      }
+      L[j][j] = double2{sqrt(d), 0.0};
+    }
+    __syncthreads();
+    const double inv = 1.0 / L[j][j].x;
+    for (int i = j + 1 + tid; i < kSw; i += 256) L[i][j] = double2{L[i][j].x * inv, L[i][j].y * inv};
+    __syncthreads();
+    // trailing lower part: L[i][k] -= L[i][j] conj(L[k][j]), j < k <= i
+    const int m = kSw - j - 1;
+    for (int e = tid; e < m * m; e += 256) {
+      const int i = j + 1 + e / m, k = j + 1 + e % m;
+      if (k <= i) {
+        const double2 x = L[i][j], y = L[k][j];
+        L[i][k].x -= x.x * y.x + x.y * y.y;
+        L[i][k].y -= x.y * y.x - x.x * y.y;
+      }
+    }
+    __syncthreads();
+  }
+  // X = L^-1 (lower) by forward substitution, one column per thread
+  if (tid < kSw) {
+    const int c = tid;
+    for (int i = 0; i < kSw; ++i) X[i][c] = double2{0.0, 0.0};
+    X[c][c] = double2{1.0 / L[c][c].x, 0.0};
+    for (int i = c + 1; i < kSw; ++i) {
+      double2 s{0.0, 0.0};
+      for (int k = c; k < i; ++k) {
+        const double2 l = L[i][k], x = X[k][c];
+        s.x += l.x * x.x - l.y * x.y;
+        s.y += l.x * x.y + l.y * x.x;
+      }
+      const double d = -1.0 / L[i][i].x;
+      X[i][c] = double2{s.x * d, s.y * d};
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < kSw * kSw; e += 256) {
+    const int r = e / kSw, c = e % kSw;
+    linvT[(size_t)c * kSw + r] = X[r][c];
+    // dinv[r][c] = sum_{k >= max(r, c)} conj(X[k][r]) X[k][c]
+    double2 s{0.0, 0.0};
+    for (int k = r > c ? r : c; k < kSw; ++k) {
+      const double2 x = X[k][r], y = X[k][c];
+      s.x += x.x * y.x + x.y * y.y;
+      s.y += x.x * y.y - x.y * y.x;
+    }
+    dinv[(size_t)r * kSw + c] = s;
+  }
+}
+
+// 64 rows i per workgroup: x_i = A_iK from the lower storage, C_i = x_i L^-H into ct[k][i] (zero for
+// i in K, whose tiles the write pass replaces), P_i = x_i D^-1 into pp[i][k]
+__global__ __launch_bounds__(256) void k_sweep_panel(const double2* __restrict__ a, int ldp, int k0,
+                                                     const double2* __restrict__ linvT,
+                                                     const double2* __restrict__ dinv, double2* __restrict__ ct,
+                                                     double2* __restrict__ pp) {
+  __shared__ double2 xs[4][kSw];
+  __shared__ double2 cs[kSw][kSw + 1];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int i0 = blockIdx.x * kSw;
+  for (int rr = 0; rr < kSw / 4; ++rr) {
+    const int r = rr * 4 + wave;
+    const int i = i0 + r;
+    const bool inK = i >= k0 && i < k0 + kSw;
+    double2 x{0.0, 0.0};
+    if (!inK) {
+      if (i > k0) {
+        x = a[(size_t)i * ldp + k0 + lane];
+      } else {
+        const double2 y = a[(size_t)(k0 + lane) * ldp + i];
+        x = double2{y.x, -y.y};
+      }
+    }
+    xs[wave][lane] = x;
+    __syncthreads();
+    double2 c{0.0, 0.0}, q{0.0, 0.0};
+    for (int l = 0; l < kSw; ++l) {
+      const double2 xv = xs[wave][l];
+      const double2 li = linvT[(size_t)l * kSw + lane];   // L^-1[lane][l]
+      const double2 d = dinv[(size_t)l * kSw + lane];
+      c.x += xv.x * li.x + xv.y * li.y;   // x conj(li)
+      c.y += xv.y * li.x - xv.x * li.y;
+      q.x += xv.x * d.x - xv.y * d.y;
+      q.y += xv.x * d.y + xv.y * d.x;
+    }
+    cs[r][lane] = c;
+    pp[(size_t)i * kSw + lane] = q;
+    __syncthreads();
+  }
+  for (int kk = 0; kk < kSw / 4; ++kk) {
+    const int k = kk * 4 + wave;
+    ct[(size_t)k * ldp + i0 + lane] = cs[lane][k];
+  }
+}
+
+// the swept block's new entries in the lower storage: A_iK = P_i (i > K), A_Ki = conj(P_i)
+// (i < K), A_KK = -D^-1
+__global__ void k_sweep_write(double2* __restrict__ a, int ldp, int k0, const double2* __restrict__ pp,
+                              const double2* __restrict__ dinv) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)ldp * kSw) return;
+  const int i = (int)(e / kSw), k = (int)(e % kSw);
+  if (i >= k0 && i < k0 + kSw) {
+    const int r = i - k0;
+    if (k <= r) {
+      const double2 d = dinv[(size_t)r * kSw + k];
+      a[(size_t)i * ldp + k0 + k] = double2{-d.x, -d.y};
+    }
+  } else if (i > k0) {
+    a[(size_t)i * ldp + k0 + k] = pp[e];
+  } else {
+    const double2 p = pp[e];
+    a[(size_t)(k0 + k) * ldp + i] = double2{p.x, -p.y};
+  }
+}
+
+// eps^-1[i][j] = sqrt(v_i) (-A)_ij / sqrt(v_j) for i, j < n, A Hermitian from its lower triangle
+__global__ void k_sweep_out(const double* __restrict__ v, const double2* __restrict__ a, int n, int ldp,
+                            double2* __restrict__ out) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)n * n) return;
+  const int i = (int)(e / n), j = (int)(e % n);
+  double2 x = i >= j ? a[(size_t)i * ldp + j] : a[(size_t)j * ldp + i];
+  if (i < j) x.y = -x.y;
+  const double s = -sqrt(v[i]) / sqrt(v[j]);
+  out[e] = double2{s * x.x, s * x.y};
+}
+
+__global__ void k_fill_f64_neg(double* __restrict__ w, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) w[i] = -1.0;
+}
+
 }  // namespace
 
 hipError_t launch_zgemm_op(int m, int n, int k, double2 alpha, const double2* A, int lda, int opa, const double2* B,
@@ -332,10 +519,18 @@ hipError_t launch_zgemm(int m, int n, int k, double2 alpha, const double2* A, in
   return launch_zgemm_op(m, n, k, alpha, A, lda, cta ? kOpC : kOpN, B, ldb, ctb ? kOpC : kOpN, beta, C, ldc, st);
 }
 
-constexpr size_t eps_inv_bytes(int n) {
+constexpr size_t sweep_bytes(int n) {
+  return (size_t)((n + kSw - 1) / kSw * kSw) * ((n + kSw - 1) / kSw * kSw) * sizeof(double2) +
+         2 * (size_t)kSw * ((n + kSw - 1) / kSw * kSw) * sizeof(double2) + 2 * (size_t)kSw * kSw * sizeof(double2) +
+         kSw * sizeof(double) + 4096;
+}
+
+constexpr size_t gj_bytes(int n) {
   return (size_t)n * n * sizeof(double2) + 2 * (size_t)n * kNb * sizeof(double2) + 2 * (size_t)n * sizeof(int) +
          2 * (size_t)((n + kStepRows - 1) / kStepRows) * (sizeof(double) + sizeof(int)) + 1024;
 }
+// either route of the inverse (pivoted Gauss-Jordan, or the sweeps of the static form)
+constexpr size_t eps_inv_bytes(int n) { return gj_bytes(n) > sweep_bytes(n) ? gj_bytes(n) : sweep_bytes(n); }
 
 size_t eps_inv_workspace(int n) { return eps_inv_bytes(n); }
 
@@ -415,6 +610,48 @@ hipError_t launch_eps_inv(int n, const double* v, const double2* chi, double2* o
   }
   k_col_perm<<<1, 64, 0, st>>>(piv, n, idx);
   k_gather_cols<<<gnn, 256, 0, st>>>(a, idx, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_eps_inv_sweep(int n, const double* v, const double2* chi, double2* out, void* ws, int* flag,
+                                hipStream_t st) {
+  const int ldp = (n + kSw - 1) / kSw * kSw;
+  char* w = (char*)ws;
+  double2* a = (double2*)w;
+  w += (size_t)ldp * ldp * sizeof(double2);
+  double2* ct = (double2*)w;
+  w += (size_t)kSw * ldp * sizeof(double2);
+  double2* pp = (double2*)w;
+  w += (size_t)kSw * ldp * sizeof(double2);
+  double2* linvT = (double2*)w;
+  w += (size_t)kSw * kSw * sizeof(double2);
+  double2* dinv = (double2*)w;
+  w += (size_t)kSw * kSw * sizeof(double2);
+  double* wneg = (double*)w;
+  w += kSw * sizeof(double);
+  int* counter = (int*)(((uintptr_t)w + 255) / 256 * 256);
+  const size_t nn = (size_t)ldp * ldp;
+  k_sweep_form<<<(unsigned)((nn + 255) / 256), 256, 0, st>>>(v, chi, n, ldp, a, flag);
+  k_fill_f64_neg<<<1, kSw, 0, st>>>(wneg, kSw);
+  const int nt = ldp / kSw;
+  ContractBatch bt{};
+  bt.nprob = 1;
+  bt.item0[0] = 0;
+  bt.item0[1] = (long long)nt * (nt + 1) / 2;
+  bt.p[0] = ContractProb{ct, wneg, a, kSw, ldp, 1, nt * (nt + 1) / 2};
+  const int grid = (int)std::min<long long>(bt.item0[1], 256LL * 8);
+  for (int k0 = 0; k0 < ldp; k0 += kSw) {
+    k_sweep_diag<<<1, 256, 0, st>>>(a, ldp, k0, linvT, dinv, flag);
+    k_sweep_panel<<<nt, 256, 0, st>>>(a, ldp, k0, linvT, dinv, ct, pp);
+    if (nt > 1) {
+      hipError_t e = launch_zero(counter, 256, st);
+      if (e != hipSuccess) return e;
+      e = launch_contract_batch(0, bt, counter, grid, true, st);
+      if (e != hipSuccess) return e;
+    }
+    k_sweep_write<<<(unsigned)(((size_t)ldp * kSw + 255) / 256), 256, 0, st>>>(a, ldp, k0, pp, dinv);
+  }
+  k_sweep_out<<<(unsigned)(((size_t)n * n + 255) / 256), 256, 0, st>>>(v, a, n, ldp, out);
   return hipGetLastError();
 }
 

@@ -1,5 +1,7 @@
 """GPU parity of eps^-1 = (I - diag(v) chi0)^-1 and its adjoint against the FP64 oracle
-(LAPACK inverse; closed-form adjoint pinned by finite differences in test_oracle)."""
+(LAPACK inverse; closed-form adjoint pinned by finite differences in test_oracle).  Both routes:
+pivoted Gauss-Jordan (any chi0) and, for a static chi0 (Hermitian negative semidefinite, v > 0),
+the block sweeps of the positive definite I - V^1/2 chi0 V^1/2 (hermitian=True)."""
 import numpy as np
 import pytest
 
@@ -16,13 +18,17 @@ def g(gpu):
     return Gpu()
 
 
-def gpu_eps_inv(g, chi, v):
+def gpu_eps_inv(g, chi, v, hermitian=False):
     torch = g.torch
     c = torch.from_numpy(np.ascontiguousarray(chi)).to(g.dev)
     vv = torch.from_numpy(np.ascontiguousarray(v)).to(g.dev)
-    z = g.p.gw_eps_inv(g.ctx, vv, c)
+    z = g.p.gw_eps_inv(g.ctx, vv, c, hermitian=hermitian)
     g.p.gw_eps_inv_status(g.ctx)
     return z.cpu().numpy()
+
+
+def routes(herm):
+    return (False, True) if herm else (False,)
 
 
 def random_chi(n, seed, hermitian):
@@ -33,16 +39,34 @@ def random_chi(n, seed, hermitian):
     return a
 
 
-@pytest.mark.parametrize("n,herm", [(1, True), (27, True), (64, False), (259, True), (300, False), (1000, False)])
+@pytest.mark.parametrize("n,herm", [(1, True), (27, True), (64, False), (64, True), (65, True), (259, True),
+                                    (300, False), (1000, False), (1000, True)])
 def test_eps_inv_matches_lapack(g, n, herm):
+    # sizes below, at and past one 64-row sweep block, and a ragged last block
     chi = random_chi(n, n, herm)
     v = np.random.default_rng(n + 1).uniform(0.5, 3.0, n)
-    z = gpu_eps_inv(g, chi, v)
     ref = oracle.eps_inv(chi, v)
-    err = np.abs(z - ref).max() / np.abs(ref).max()
-    assert err <= 1e-11, err
     eps = oracle.eps_matrix(chi, v)
-    assert np.abs(eps @ z - np.eye(n)).max() <= 1e-10
+    for h in routes(herm):
+        z = gpu_eps_inv(g, chi, v, h)
+        err = np.abs(z - ref).max() / np.abs(ref).max()
+        assert err <= 1e-11, (h, err)
+        assert np.abs(eps @ z - np.eye(n)).max() <= 1e-10
+
+
+def test_eps_inv_hermitian_reads_the_lower_triangle(g):
+    # the static route takes chi0 Hermitian and reads i >= j only: noise above the diagonal
+    # leaves its result unchanged bit for bit
+    n = 200
+    chi = random_chi(n, 31, True)
+    v = np.random.default_rng(32).uniform(0.5, 3.0, n)
+    noisy = chi.copy()
+    iu = np.triu_indices(n, 1)
+    noisy[iu] += np.random.default_rng(33).standard_normal(len(iu[0]))
+    z = gpu_eps_inv(g, chi, v, True)
+    assert np.array_equal(gpu_eps_inv(g, noisy, v, True), z)
+    ref = oracle.eps_inv(chi, v)
+    assert np.abs(z - ref).max() <= 1e-11 * np.abs(ref).max()
 
 
 def test_eps_inv_needs_pivoting(g):
@@ -61,10 +85,11 @@ def test_eps_inv_of_static_chi0_c1(g):
     case = make_case(0)
     chi = oracle.chi0_bands(case.coef_v, case.e_v, case.coef_c, case.e_c, case.gw, case.gc, (case.nd,) * 3)[0]
     v = synth.coulomb(case.gc, case.cfg.qs[0], case.cfg.cell)
-    z = gpu_eps_inv(g, chi, v)
     ref = oracle.eps_inv(chi, v)
-    assert np.abs(z - ref).max() <= 1e-11 * np.abs(ref).max()
-    assert oracle.eps_inf(z) == pytest.approx(oracle.eps_inf(ref), rel=1e-12)
+    for h in routes(True):
+        z = gpu_eps_inv(g, chi, v, h)
+        assert np.abs(z - ref).max() <= 1e-11 * np.abs(ref).max()
+        assert oracle.eps_inf(z) == pytest.approx(oracle.eps_inf(ref), rel=1e-12)
 
 
 def test_eps_inv_singular_is_reported(g):
@@ -82,12 +107,35 @@ def test_eps_inv_singular_is_reported(g):
     gpu_eps_inv(g, random_chi(40, 3, True), np.ones(40))
 
 
-def test_eps_inv_batched(g):
+@pytest.mark.parametrize("what", ["zero", "indefinite", "v"])
+def test_eps_inv_hermitian_not_positive_definite_is_reported(g, what):
+    # the static route needs I - V^1/2 chi0 V^1/2 positive definite: eps~ = 0, an eps~ with a
+    # negative eigenvalue in the second sweep block (chi0 not negative semidefinite), or a v <= 0
+    n = 150
+    chi = random_chi(n, 5, True)
+    v = np.random.default_rng(6).uniform(0.5, 3.0, n)
+    if what == "zero":
+        chi, v = np.eye(n, dtype=np.complex128), np.ones(n)
+    elif what == "indefinite":
+        chi[100, 100] += 10.0
+    else:
+        v[70] = -1.0
+    torch = g.torch
+    g.p.gw_eps_inv(g.ctx, torch.from_numpy(v).to(g.dev), torch.from_numpy(chi).to(g.dev), hermitian=True)
+    with pytest.raises(g.p.GwError) as e:
+        g.p.gw_eps_inv_status(g.ctx)
+    assert e.value.status == g.p.GW_ESINGULAR
+    gpu_eps_inv(g, random_chi(40, 3, True), np.ones(40), True)   # a good one clears the flag
+
+
+@pytest.mark.parametrize("herm", [False, True], ids=["general", "static"])
+def test_eps_inv_batched(g, herm):
     n, nb = 100, 3
-    chis = np.stack([random_chi(n, 10 + i, i % 2 == 0) for i in range(nb)])
+    chis = np.stack([random_chi(n, 10 + i, herm or i % 2 == 0) for i in range(nb)])
     vs = np.random.default_rng(9).uniform(0.5, 2.0, (nb, n))
     torch = g.torch
-    z = g.p.gw_eps_inv(g.ctx, torch.from_numpy(vs).to(g.dev), torch.from_numpy(chis).to(g.dev)).cpu().numpy()
+    z = g.p.gw_eps_inv(g.ctx, torch.from_numpy(vs).to(g.dev), torch.from_numpy(chis).to(g.dev),
+                       hermitian=herm).cpu().numpy()
     for i in range(nb):
         ref = oracle.eps_inv(chis[i], vs[i])
         assert np.abs(z[i] - ref).max() <= 1e-11 * np.abs(ref).max()
@@ -123,24 +171,25 @@ def test_eps_inv_at_the_workload_sizes(g, n, herm):
     else:
         chi = a
         v = np.random.default_rng(n + 1).uniform(0.5, 3.0, n)
-    z = gpu_eps_inv(g, chi, v)
     ref = oracle.eps_inv(chi, v)
-    err = float(np.abs(z - ref).max() / np.abs(ref).max())
     eps = torch.from_numpy(oracle.eps_matrix(chi, v)).to(g.dev)
     eye = torch.eye(n, dtype=torch.complex128, device=g.dev)
-    res = float((eps @ torch.from_numpy(z).to(g.dev) - eye).abs().max().item())
     res_ref = float((eps @ torch.from_numpy(ref).to(g.dev) - eye).abs().max().item())
-    print(f"n={n} {'static' if herm else 'general'}: max|Z - Z_lapack| / max|Z_lapack| = {err:.2e}, "
-          f"max|eps Z - I| = {res:.2e} (LAPACK {res_ref:.2e}), eps_inf = {oracle.eps_inf(z):.6f} "
-          f"(LAPACK {oracle.eps_inf(ref):.6f})")
-    # two backward-stable inverses differ by about cond(eps) x 1e-16: the static eps~ is positive
-    # definite and well conditioned; the random general matrix I - diag(v) A has eigenvalues near 0
-    # (cond ~ 1e5 at n = 8000), so there the residual is held to LAPACK's own
-    assert err <= (1e-11 if herm else 1e-10)
-    assert res <= 1e-10 and res <= max(4.0 * res_ref, 1e-12)
-    if herm:
-        assert oracle.eps_inf(z) == pytest.approx(oracle.eps_inf(ref), rel=1e-12)
-        assert oracle.eps_inf(ref) > 1.0
+    for h in routes(herm):
+        z = gpu_eps_inv(g, chi, v, h)
+        err = float(np.abs(z - ref).max() / np.abs(ref).max())
+        res = float((eps @ torch.from_numpy(z).to(g.dev) - eye).abs().max().item())
+        print(f"n={n} {'static' if herm else 'general'} ({'sweeps' if h else 'Gauss-Jordan'}): "
+              f"max|Z - Z_lapack| / max|Z_lapack| = {err:.2e}, max|eps Z - I| = {res:.2e} (LAPACK {res_ref:.2e}), "
+              f"eps_inf = {oracle.eps_inf(z):.6f} (LAPACK {oracle.eps_inf(ref):.6f})")
+        # two backward-stable inverses differ by about cond(eps) x 1e-16: the static eps~ is
+        # positive definite and well conditioned; the random general matrix I - diag(v) A has
+        # eigenvalues near 0 (cond ~ 1e5 at n = 8000), so there the residual is held to LAPACK's own
+        assert err <= (1e-11 if herm else 1e-10)
+        assert res <= 1e-10 and res <= max(4.0 * res_ref, 1e-12)
+        if herm:
+            assert oracle.eps_inf(z) == pytest.approx(oracle.eps_inf(ref), rel=1e-12)
+            assert oracle.eps_inf(ref) > 1.0
 
 
 def test_eps_inf_of_a_chi0_with_a_nonzero_head(g):
@@ -154,7 +203,8 @@ def test_eps_inf_of_a_chi0_with_a_nonzero_head(g):
     assert np.abs(ref_chi[0, 0]) > 1e-3 * np.abs(ref_chi).max()
     assert np.abs(chi - ref_chi).max() <= 1e-10 * np.abs(ref_chi).max()
     v = synth.coulomb(case.gc, case.cfg.qs[0], case.cfg.cell)
-    z = gpu_eps_inv(g, chi, v)
     want = oracle.eps_inf(oracle.eps_inv(ref_chi, v))
     assert want > 1.5
-    assert oracle.eps_inf(z) == pytest.approx(want, rel=1e-11)
+    for h in routes(True):
+        z = gpu_eps_inv(g, chi, v, h)
+        assert oracle.eps_inf(z) == pytest.approx(want, rel=1e-11)

@@ -24,20 +24,21 @@ def test_eps_inv_noalloc_matches_the_workspace_entry_point(gpu):
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     cfg = synth.config(4)
     try:
-        for n, herm in ((2048, True), (700, False)):        # the largest size, then a smaller one
+        # the largest size, then smaller ones, with both routes of the inverse
+        for n, herm, route in ((2048, True, True), (2048, True, False), (700, False, False), (500, True, True)):
             chi = _chi(n, n, herm)
             v = synth.coulomb(synth.chi_sphere(n, cfg.qs[0], cfg.cell), cfg.qs[0], cfg.cell) if herm else \
                 np.random.default_rng(n).uniform(0.5, 3.0, n)
             vd, cd = t(v), t(chi)
-            want = p.gw_eps_inv(ctx, vd, cd)
+            want = p.gw_eps_inv(ctx, vd, cd, hermitian=route)
             out = torch.full((n, n), np.nan, dtype=torch.complex128, device=dev)
-            got = p.gw_eps_inv_noalloc(ctx, vd, cd, out)
+            got = p.gw_eps_inv_noalloc(ctx, vd, cd, out, hermitian=route)
             p.gw_eps_inv_status(ctx)
             torch.cuda.synchronize()
-            assert torch.equal(got, want), n
+            assert torch.equal(got, want), (n, route)
             ref = oracle.eps_inv(chi, v)
             err = float(np.abs(got.cpu().numpy() - ref).max() / np.abs(ref).max())
-            print(f"n={n}: identical to gw_eps_inv; {err:.1e} from LAPACK")
+            print(f"n={n} hermitian={route}: identical to gw_eps_inv; {err:.1e} from LAPACK")
             assert err <= 1e-11
         # a batch of three in one call reuses the scratch for each matrix
         chis = np.stack([_chi(300, 40 + i, i % 2 == 0) for i in range(3)])
