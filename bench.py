@@ -1,17 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the chi0 band sum on one MI355X.
 
-Workload: the 64-atom-MgO-shaped static polarizability -- 72^3 FFT grid, 24,405-plane-wave
-wavefunction sphere, 128 valence x 4,000 conduction bands (512,000 band pairs), 2,000
-G-vectors in the dielectric sphere, q = (0.01, 0, 0), exact band sum (Eq. (chi0) at w = 0).
-Seeded synthetic inputs (orthonormal random coefficients, sqrt(E) conduction spectrum)
-stand in for the paper's MgO wavefunctions.
+Default workload (the largest configuration that fits one GPU): the 256-atom-MgO-shaped
+polarizability -- 128^3 FFT grid, 137,065-plane-wave wavefunction sphere, 512 valence bands and
+25,000 conduction bands of which those above E0 = 30 eV are grouped into 1 eV windows (Eqs. (chi02)
+and (energyintegration): 8,451 explicit columns + 30 window representatives, 4.34 M band pairs),
+8,000 G-vectors in the dielectric sphere, q = (0.01, 0, 0), static.  Seeded synthetic inputs
+(orthonormal random coefficients, sqrt(E) conduction spectrum) stand in for the paper's MgO
+wavefunctions.
 
-One step = one gw_chi0_build (band transforms, pair transforms, weights, contraction)
-followed by gw_eps_inv of the result (float64), with every input already in HBM.  The float64 path is the headline
-(`value`); the float32 path is timed the same way and its error against float64 is
-reported.  A bounded sample of the same workload runs through the CPU oracle as a
-reported baseline.  Prints one JSON line on stdout; progress goes to stderr.
+One step = one gw_chi0_build (band transforms, pair transforms, weights, contraction) followed by
+gw_eps_inv of the result (float64), every input already in HBM.  The headline (`value`) is the
+mixed-precision path (split-BF16x3 contraction with float32 accumulation on float32 pair
+densities; float64 weights, accumulation across chunks and eps^-1); one float64 step is timed
+beside it and gives the error of the mixed path.  A bounded sample of the same workload runs
+through the CPU oracle as a reported baseline (its full-size time extrapolated linearly in band
+pairs, and labelled so).  The 64-atom workload (72^3, 128 x 4,000, NG 2,000) is reported beside it
+in float64, float32 and split-BF16x3.  Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
 import json
@@ -30,21 +35,35 @@ PEAK = {"fp64_vec": 78.6, "fp64_mfma": 78.6, "fp32_mfma": 157.3, "fp32_vec_nopk"
         "hbm": 8000.0}
 
 
+T_START = time.time()
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def within_budget(args, seconds, what):
+    """True if a leg of about `seconds` still ends inside the run's time budget (the timed steps
+    are never cut; only the legs reported beside them are skipped, and say so)."""
+    left = args.budget_s - (time.time() - T_START)
+    if seconds <= left:
+        return True
+    log(f"{what}: skipped, about {seconds:.0f} s needed and {left:.0f} s of the {args.budget_s:.0f} s budget left")
+    return False
 
 
 def flops_model(nd, k, ng, npair, nband, with_inverse=True):
     """Algorithmic flop counts: pruned forward transform per pair (three passes over
     N, N K/N_d and N K^2/N_d^2 points at 5 n log2 n), the product (6 N), the band
-    transforms (5 N log2 N each) and the Hermitian contraction (4 NG^2 per pair)."""
+    transforms (5 N log2 N each), the Hermitian contraction (4 NG^2 per pair) and the static
+    inverse by Hermitian sweeps (a rank-64 update of the lower triangle per 64 pivots, 4 NG^3)."""
     n = nd ** 3
     lg = math.log2(nd)
     planes = 5.0 * n * lg * (1.0 + k / nd) + 6.0 * n
     finish = 5.0 * n * lg * (k * k / nd ** 2)
     band = 5.0 * n * math.log2(n)
     contract = 4.0 * ng * ng
-    inverse = 8.0 * ng ** 3 if with_inverse else 0.0    # complex Gauss-Jordan inversion
+    inverse = 4.0 * ng ** 3 if with_inverse else 0.0
     return {"planes": planes * npair, "finish": finish * npair, "band": band * nband, "contract": contract * npair,
             "eps_inv": inverse, "total": (planes + finish + contract) * npair + band * nband + inverse}
 
@@ -78,6 +97,258 @@ def measured_traffic(stage, mode):
     return None
 
 
+def traffic_for(prefixes, src):
+    """HBM bytes per dispatch of the first kernel in profiles/traffic.json whose name starts with
+    one of the prefixes, or None when its source file changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+            tr = json.load(f)
+        with open(os.path.join(ROOT, "paper_1601_06767_amd", "csrc", src), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != tr["sources"][src]:
+                return None
+        for k, v in tr["kernels"].items():
+            if k.startswith(tuple(prefixes)):
+                return {"read_bytes": v["read_bytes_per_dispatch"], "write_bytes": v["write_bytes_per_dispatch"],
+                        "bytes": v["read_bytes_per_dispatch"] + v["write_bytes_per_dispatch"],
+                        "kernel": k, "source": v.get("profile", "profiles/traffic.json")}
+    except (OSError, KeyError, ValueError):
+        pass
+    return None
+
+
+def timed_steps(p, ctx, torch, run, steps, warmup, label):
+    """warmup untimed calls, then steps timed between two events on the current stream with the
+    library's stage timers on: (ms per step, wall seconds, stage ms per step, launches per step)."""
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    p.gw_ctx_stage_times(ctx, reset=True)
+    p.gw_ctx_set_timing(ctx, True)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    tw = time.perf_counter()
+    e0.record(stream)
+    for i in range(steps):
+        run()
+        log(f"{label}: step {i + 1}/{steps} enqueued")
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - tw
+    p.gw_ctx_set_timing(ctx, False)
+    stages = p.gw_ctx_stage_times(ctx, reset=True)
+    ms = e0.elapsed_time(e1) / steps
+    return (ms, wall, {k: v[0] / steps for k, v in stages.items() if v[1]},
+            {k: v[1] / steps for k, v in stages.items() if v[1]})
+
+
+def run_headline(args, torch, synth, p, dev):
+    """The 256-atom-shaped grouped workload in mixed precision (timed steps), one float64 step,
+    the oracle on a bounded sample, and the 64-atom workload beside it."""
+    cfg = synth.config(4)
+    hev = synth.HARTREE_EV
+    nd = cfg.nd
+    gw = synth.wf_sphere(nd)
+    gc = synth.chi_sphere(cfg.ng[0], cfg.qs[0], cfg.cell)
+    e_all = synth.conduction_energies(cfg)
+    nwin = int(round((cfg.emax_ev - cfg.e0_ev) / cfg.de_ev))
+    col, e_col, n_col, n0 = p.gw_group_windows(e_all, cfg.e0_ev / hev, cfg.de_ev / hev, nwin)
+    t0 = time.time()
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    bands_idx = np.concatenate([np.arange(cfg.nv), cfg.nv + np.asarray(col)])
+    rows = synth.gaussian_columns_threaded(cfg.index, 0, bands_idx, len(gw), workers)
+    log(f"headline: {len(bands_idx)} coefficient rows of {len(gw)} plane waves in {time.time() - t0:.1f}s")
+    qd = synth.orthonormalize_on_device(rows, "cuda")
+    del rows
+    cv = qd[:cfg.nv].contiguous()
+    cc = qd[cfg.nv:].contiguous()
+    del qd
+    torch.cuda.synchronize()
+    ev_host = synth.valence_energies(cfg, 0)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    ev, ecol, ncol = t(ev_host), t(e_col), t(n_col)
+    log(f"headline inputs: {nd}^3, npw={len(gw)}, nv={cfg.nv}, {cfg.nc} bands -> {len(col)} columns ({n0} explicit "
+        f"+ {len(col) - n0} windows), NG={len(gc)}, ready in {time.time() - t0:.1f}s")
+    ctx = p.gw_ctx_create(0)
+    p.gw_ctx_set_overlap(ctx, 0 if args.no_overlap else 1)
+    geom = p.gw_geom_create(ctx, (nd,) * 3, gw, gc, cfg.cell, cfg.qs[0])
+    prob = p.make_problem(geom, cv, ev, cc, ecol, ncol)
+    ng = len(gc)
+    vcoul = t(synth.coulomb(gc, cfg.qs[0], cfg.cell))
+    k = 2 * int(np.abs(gc).max()) + 1
+    npair = cfg.nv * len(col)
+    fl = flops_model(nd, k, ng, npair, cfg.nv + len(col))
+    head = args.head_mode
+    modes = [head] + ([] if args.no_fp64_step or head == "fp64" else ["fp64"])
+    wsb = max(p.gw_chi0_workspace_size(ctx, [prob], 1, p.PRECISIONS[m]) for m in modes)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    ws_inv = torch.empty(p.gw_eps_inv_workspace_size(ctx, ng, 1), dtype=torch.uint8, device=dev)
+    log(f"workspace {wsb / 2**30:.1f} GiB")
+    results, chis, zs = {}, {}, {}
+    skipped = {}
+    for m in modes:
+        if m != head and not within_budget(args, 3.2 * results[head]["ms_per_step"] * 1e-3 + 10, f"{m} step"):
+            skipped[m] = "time budget"
+            continue
+        out = torch.empty(ng * ng, dtype=torch.complex128, device=dev)     # one output per mode
+        zout = torch.empty((ng, ng), dtype=torch.complex128, device=dev)
+
+        def run():
+            p.gw_chi0_build(ctx, [prob], [ng], [0.0], 0.0, p.PRECISIONS[m], workspace=ws, out=out)
+            p.gw_eps_inv(ctx, vcoul, out.view(ng, ng), workspace=ws_inv, out=zout, hermitian=True)
+        steps, warm = (args.steps, args.warmup) if m == head else (1, 0)
+        ms, wall, st, nl = timed_steps(p, ctx, torch, run, steps, warm, m)
+        p.gw_eps_inv_status(ctx)
+        chis[m], zs[m] = out.view(ng, ng), zout
+        results[m] = {"ms_per_step": ms, "steps": steps, "warmup": warm, "wall_s": wall,
+                      "tflops": fl["total"] / (ms * 1e-3) / 1e12, "band_pairs_per_s": npair / (ms * 1e-3),
+                      "stages_ms_per_step": st, "stage_launches_per_step": nl}
+        log(f"{m}: {ms:.1f} ms/step, {results[m]['tflops']:.2f} TFLOP/s, stages {st}")
+    if "fp64" in chis:
+        ref, zref = chis["fp64"], zs["fp64"]
+        rmax, zmax = ref.abs().max(), zref.abs().max()
+        for m in chis:
+            d = chis[m] - ref
+            dz = zs[m] - zref
+            results[m]["err_vs_fp64"] = float(torch.linalg.norm(d) / torch.linalg.norm(ref))
+            results[m]["max_err_vs_fp64"] = float(d.abs().max() / rmax)
+            results[m]["eps_inv_max_err_vs_fp64"] = float(dz.abs().max() / zmax)
+            # without the head row and column: at q -> 0 the head of chi0 is zero in exact
+            # arithmetic (orthogonal bands), and the float32 pair densities leave <v|c> ~ 1e-7 there,
+            # which v(q) of the head multiplies
+            results[m]["eps_inv_max_err_vs_fp64_wings_excluded"] = float(dz[1:, 1:].abs().max() / zmax)
+            results[m]["eps_inf"] = float(1.0 / zs[m][0, 0].real)
+            del d, dz
+        results["fp64"]["hermitian_residual"] = float((ref - ref.conj().T).abs().max() / rmax)
+        if head != "fp64":
+            results[head]["speedup_vs_fp64"] = results["fp64"]["ms_per_step"] / results[head]["ms_per_step"]
+    del chis, zs
+    hr = results[head]
+    # dominant kernel of the timed mode against its roofline
+    st = hr["stages_ms_per_step"]
+    dom = max(st, key=st.get)
+    launches = hr["stage_launches_per_step"][dom]
+    avg_ms = st[dom] / launches
+    fp = "double" if head == "fp64" else "float"
+    if dom == "contract":
+        bound = "mfma"
+        peak = {"fp64": PEAK["fp64_mfma"], "fp32": PEAK["fp32_mfma"], "bf16x3": PEAK["bf16_mfma"]}[head]
+        work = fl["contract"] / launches
+        traffic = traffic_for([f"k_contract_batch<{ {'fp64': 0, 'fp32': 1, 'bf16x3': 2}[head] },"], "contract.hip")
+        basis = f"{head} matrix-core peak (split products not counted as work)"
+    else:
+        bound = "alu"
+        peak = PEAK["fp64_vec"] if head == "fp64" else PEAK["fp32_vec_nopk"]
+        work = fl[dom] / launches
+        kern = {"planes": ["k_pair_planes"], "finish": ["k_pair_finish"], "band": ["k_band"]}.get(dom, [dom])
+        traffic = traffic_for([f"{x}<{fp}, {nd}, " for x in kern] + [f"{x}_split<{fp}, {nd}, " for x in kern],
+                              "pair_transform.hip" if dom in ("planes", "finish") else "band_fft.hip")
+        basis = ("256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz: the float64 vector rate, and the float32 "
+                 "rate without packed instructions, which this build does not use")
+    achieved = work / (avg_ms * 1e-3) / 1e12
+    roofline = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": traffic, "avg_launch_ms": avg_ms,
+                "algorithmic_work_per_launch": work, "peak_basis": basis}
+    # the oracle on a bounded sample of the same workload (full grid and sphere)
+    cpu = None
+    nvs, ncs = (int(x) for x in args.cpu_pairs.split("x"))
+    want_cpu = args.cpu_sample > 0 and nvs > 0 and ncs > 0
+    if want_cpu and not within_budget(args, 20, "oracle sample"):
+        skipped["cpu_baseline"] = "time budget"
+        want_cpu = False
+    if want_cpu:
+        import oracle
+        cores = len(os.sched_getaffinity(0))
+        vs = np.linspace(0, cfg.nv - 1, nvs).astype(int)
+        cs = np.linspace(0, len(col) - 1, ncs).astype(int)
+        cv_s = cv[torch.from_numpy(vs).to(dev)].cpu().numpy()
+        cc_s = cc[torch.from_numpy(cs).to(dev)].cpu().numpy()
+        t1 = time.perf_counter()
+        ref_s = oracle.chi0_bands(cv_s, ev_host[vs], cc_s, e_col[cs], gw, gc, (nd,) * 3, n_col=n_col[cs])[0]
+        dt = time.perf_counter() - t1
+        sp = len(vs) * len(cs)
+        fs = flops_model(nd, k, ng, sp, len(vs) + len(cs), with_inverse=False)
+        sub = p.make_problem(geom, t(cv_s), t(ev_host[vs]), t(cc_s), t(e_col[cs]), t(n_col[cs]))
+        gchi = p.gw_chi0_build(ctx, [sub], [ng], [0.0], 0.0, p.GW_FP64)[0][0].cpu().numpy()
+        rate = (fs["total"] - fs["eps_inv"]) / dt / 1e12
+        cpu = {"value": rate, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+               "band_pairs_per_s": sp / dt, "seconds": dt,
+               "sample": f"{len(vs)} valence x {len(cs)} columns ({sp} pairs) of the same workload, full 128^3 grid "
+                         f"and 8000-G sphere, scipy.fft workers={cores}",
+               "full_build_s_extrapolated": npair / (sp / dt),
+               "extrapolation": "linear in band pairs (the sum's cost is per pair plus per band)",
+               "gpu_fp64_err_on_sample": float(np.linalg.norm(gchi - ref_s) / np.linalg.norm(ref_s))}
+        log(f"oracle sample: {sp} pairs in {dt:.1f}s ({cpu['value'] * 1e3:.3f} GFLOP/s); GPU fp64 on the sample "
+            f"{cpu['gpu_fp64_err_on_sample']:.1e} from it")
+    c2 = None
+    if not args.no_c2:
+        if within_budget(args, 40, "72^3 workload"):
+            c2 = run_c2_beside(args, torch, synth, p, dev, ctx)
+        else:
+            skipped["mgo64_static_72cube"] = "time budget"
+    line = {"metric": METRIC, "value": hr["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": hr["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[head],
+            "data": "synthetic",
+            "config": {"workload": cfg.name, "grid": nd, "npw": len(gw), "nv": cfg.nv, "nc_generated": cfg.nc,
+                       "ncol": len(col), "explicit": n0, "windows": len(col) - n0, "ng": ng, "pairs": npair,
+                       "q": list(cfg.qs[0]), "omega": 0.0, "e0_ev": cfg.e0_ev, "de_ev": cfg.de_ev,
+                       "precision": head},
+            "band_pairs_per_s": hr["band_pairs_per_s"], "modes": results, "roofline": roofline,
+            "cpu_baseline": cpu, "mgo64_static_72cube": c2, "skipped": skipped or None,
+            "run_s": time.time() - T_START}
+    print(json.dumps(line))
+
+
+def run_c2_beside(args, torch, synth, p, dev, ctx):
+    """The 64-atom workload (72^3, 128 x 4000, NG 2000, exact sum) in float64, float32 and
+    split-BF16x3, a few timed steps each, errors against float64."""
+    cfg = synth.config(1)
+    nd = cfg.nd
+    gw = synth.wf_sphere(nd)
+    gc = synth.chi_sphere(cfg.ng[0], cfg.qs[0], cfg.cell)
+    t0 = time.time()
+    rows = synth.gaussian_columns_threaded(cfg.index, 0, np.arange(cfg.nv + cfg.nc), len(gw),
+                                           max(1, min(16, len(os.sched_getaffinity(0)))))
+    qd = synth.orthonormalize_on_device(rows, "cuda")
+    del rows
+    cv, cc = qd[:cfg.nv].contiguous(), qd[cfg.nv:].contiguous()
+    del qd
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    ev, ec = t(synth.valence_energies(cfg, 0)), t(synth.conduction_energies(cfg))
+    geom = p.gw_geom_create(ctx, (nd,) * 3, gw, gc, cfg.cell, cfg.qs[0])
+    prob = p.make_problem(geom, cv, ev, cc, ec)
+    ng = len(gc)
+    vcoul = t(synth.coulomb(gc, cfg.qs[0], cfg.cell))
+    k = 2 * int(np.abs(gc).max()) + 1
+    npair = cfg.nv * cfg.nc
+    fl = flops_model(nd, k, ng, npair, cfg.nv + cfg.nc)
+    modes = ["fp64", "fp32", "bf16x3"]
+    ws = torch.empty(max(p.gw_chi0_workspace_size(ctx, [prob], 1, p.PRECISIONS[m]) for m in modes), dtype=torch.uint8,
+                     device=dev)
+    ws_inv = torch.empty(p.gw_eps_inv_workspace_size(ctx, ng, 1), dtype=torch.uint8, device=dev)
+    out = torch.empty(ng * ng, dtype=torch.complex128, device=dev)
+    zout = torch.empty((ng, ng), dtype=torch.complex128, device=dev)
+    log(f"72^3 workload beside: inputs in {time.time() - t0:.1f}s")
+    steps = max(1, min(args.steps, 3))
+    res, chis = {}, {}
+    for m in modes:
+        def run():
+            p.gw_chi0_build(ctx, [prob], [ng], [0.0], 0.0, p.PRECISIONS[m], workspace=ws, out=out)
+            p.gw_eps_inv(ctx, vcoul, out.view(ng, ng), workspace=ws_inv, out=zout, hermitian=True)
+        ms, _, st, _ = timed_steps(p, ctx, torch, run, steps, 1, f"72^3 {m}")
+        chis[m] = out.view(ng, ng).cpu().numpy()
+        res[m] = {"ms_per_step": ms, "tflops": fl["total"] / (ms * 1e-3) / 1e12, "band_pairs_per_s": npair / (ms * 1e-3),
+                  "stages_ms_per_step": st}
+    ref = chis["fp64"]
+    for m in modes:
+        res[m]["err_vs_fp64"] = float(np.linalg.norm(chis[m] - ref) / np.linalg.norm(ref))
+    p.gw_geom_destroy(geom)
+    log("72^3: " + ", ".join(f"{m} {res[m]['ms_per_step']:.1f} ms" for m in modes))
+    return {"workload": cfg.name, "steps": steps, "warmup": 1, "pairs": npair, "ng": ng, "modes": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,10 +360,12 @@ def main():
     ap.add_argument("--tune", action="store_true", help="run the launch-shape tuner before timing each mode")
     ap.add_argument("--inputs-cache", default=None,
                     help="npz file for the generated inputs: loaded if present, written otherwise")
-    ap.add_argument("--workload", default="static",
-                    choices=["static", "batched", "grouped", "adjoint", "grouping-study", "extensions",
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "static", "batched", "grouped", "adjoint", "grouping-study", "extensions",
                              "reduced-box"],
-                    help="static: the 72^3 / 128x4000 / NG 2000 build (default); batched: 8 q-points x 16 "
+                    help="headline (default): the 128^3 / 512 x 25000 grouped / NG 8000 build, mixed precision "
+                         "with a float64 step and the 72^3 workload beside it; "
+                         "static: the 72^3 / 128x4000 / NG 2000 build; batched: 8 q-points x 16 "
                          "frequencies, 128x6000 bands, NG 800..3000, one persistent launch per chunk; grouped: "
                          "96^3, 256 x 16000 bands grouped above 30 eV into 1 eV windows, NG 4000, with eps^-1; "
                          "adjoint: 128^3, 512 x 25000 bands grouped the same way, NG 8000, build + eps^-1 + "
@@ -111,6 +384,15 @@ def main():
                     help="run every conduction chunk's contraction on the context's stream (no second stream)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
+    ap.add_argument("--head-mode", default="bf16x3", choices=["bf16x3", "fp32", "fp64"],
+                    help="headline workload: the precision of the timed steps")
+    ap.add_argument("--no-fp64-step", action="store_true", help="headline workload: skip the float64 step")
+    ap.add_argument("--no-c2", action="store_true", help="headline workload: skip the 72^3 workload beside it")
+    ap.add_argument("--budget-s", type=float, default=540.0,
+                    help="headline workload: wall-clock budget of the whole run; the legs beside the timed steps "
+                         "(float64 step, oracle sample, 72^3 workload) are skipped when they would overrun it")
+    ap.add_argument("--cpu-pairs", default="2x40",
+                    help="headline workload: oracle sample, valence x columns of the full-size workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the band sum shards over "
@@ -123,6 +405,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.workload == "headline":
+        run_headline(args, torch, synth, p, dev)
+        return
     if args.workload == "batched":
         run_batched(args, torch, synth, p, dev)
         return
@@ -156,7 +441,7 @@ def main():
 
     ctx = p.gw_ctx_create(0)
     p.gw_ctx_set_overlap(ctx, 0 if args.no_overlap else 1)
-    geom = p.gw_geom_create(ctx, (nd,) * 3, gw, gc)
+    geom = p.gw_geom_create(ctx, (nd,) * 3, gw, gc, cfg.cell, cfg.qs[0])
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     cv, ev, cc, ec = t(bands.coef_v), t(bands.e_v), t(bands.coef_c), t(bands.e_c)
     prob = p.make_problem(geom, cv, ev, cc, ec)
@@ -182,7 +467,7 @@ def main():
 
         def run():
             p.gw_chi0_build(ctx, [prob], [ng], [0.0], 0.0, p.PRECISIONS[m], workspace=ws, out=out)
-            p.gw_eps_inv(ctx, vcoul, out.view(ng, ng), workspace=ws_inv, out=zout)
+            p.gw_eps_inv(ctx, vcoul, out.view(ng, ng), workspace=ws_inv, out=zout, hermitian=True)
         for _ in range(args.warmup):
             run()
         torch.cuda.synchronize()
@@ -231,7 +516,7 @@ def main():
 
         def run_s():
             p.gw_chi0_build(ctx, [prob_s], [ng], [0.0], 0.0, p.PRECISIONS[head], workspace=ws_s, out=out_s)
-            p.gw_eps_inv(ctx, vcoul, out_s.view(ng, ng), workspace=ws_inv, out=zout)
+            p.gw_eps_inv(ctx, vcoul, out_s.view(ng, ng), workspace=ws_inv, out=zout, hermitian=True)
         for _ in range(max(1, args.warmup)):
             run_s()
         torch.cuda.synchronize()
@@ -257,10 +542,11 @@ def main():
     launches = hr["stage_launches_per_step"][dom]
     avg_ms = st[dom] / launches
     if dom == "contract":
-        bound, peak = "mfma", (PEAK["fp64_mfma"] if head == "fp64" else PEAK["fp32_mfma"])
+        bound = "mfma"
+        peak = {"fp64": PEAK["fp64_mfma"], "fp32": PEAK["fp32_mfma"], "bf16x3": PEAK["bf16_mfma"]}[head]
         work = fl["contract"] / launches
     else:
-        bound, peak = "alu", PEAK["fp64_vec"]
+        bound, peak = "alu", (PEAK["fp64_vec"] if head == "fp64" else PEAK["fp32_vec_nopk"])
         work = fl[dom if dom in fl else "planes"] / launches
     achieved = work / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
@@ -299,7 +585,7 @@ def main():
 
     line = {"metric": METRIC, "value": hr["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": hr["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-            "vs_baseline": None, "dtype": "f64" if head == "fp64" else "f32", "data": "synthetic",
+            "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[head], "data": "synthetic",
             "config": {"workload": cfg.name, "grid": nd, "npw": len(gw), "nv": cfg.nv, "ncol": cfg.nc, "ng": ng,
                        "pairs": npair, "q": list(cfg.qs[0]), "omega": 0.0},
             "band_pairs_per_s": hr["band_pairs_per_s"], "modes": results, "roofline": roofline,
@@ -326,7 +612,7 @@ def run_batched(args, torch, synth, p, dev):
         b = synth.make_bands(cfg, gvec_wf=gw, iq=iq, device="cuda")
         if cc is None:   # the conduction set (at k) is the same for every q-point
             cc, ec = t(b.coef_c), t(b.e_c)
-        geom = p.gw_geom_create(ctx, (nd,) * 3, gw, gc)
+        geom = p.gw_geom_create(ctx, (nd,) * 3, gw, gc, cfg.cell, cfg.qs[iq])
         cv, ev = t(b.coef_v), t(b.e_v)
         keep += [cv, ev]
         probs.append(p.make_problem(geom, cv, ev, cc, ec))
@@ -436,7 +722,7 @@ def run_grouped(args, torch, synth, p, dev, backward):
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     ctx = p.gw_ctx_create(0)
     p.gw_ctx_set_overlap(ctx, 0 if args.no_overlap else 1)
-    geom = p.gw_geom_create(ctx, (nd,) * 3, gw, gc)
+    geom = p.gw_geom_create(ctx, (nd,) * 3, gw, gc, cfg.cell, cfg.qs[0])
     cv, ev, cc = t(bands.coef_v), t(bands.e_v), t(bands.coef_c)
     del bands
     ecol, ncol = t(e_col), t(n_col)
@@ -470,7 +756,7 @@ def run_grouped(args, torch, synth, p, dev, backward):
 
         def run():
             p.gw_chi0_build(ctx, [prob], [ng], [0.0], 0.0, p.PRECISIONS[m], workspace=ws, out=out)
-            p.gw_eps_inv(ctx, vcoul, out.view(ng, ng), workspace=ws_inv, out=zout)
+            p.gw_eps_inv(ctx, vcoul, out.view(ng, ng), workspace=ws_inv, out=zout, hermitian=True)
             if backward:
                 p.gw_eps_inv_backward(ctx, vcoul, zout, zbar, workspace=ws_inv, out=gchi)
                 g[:] = p.gw_chi0_backward(ctx, [prob], [0.0], 0.0, p.PRECISIONS[m], gchi.view(1, ng, ng),
@@ -556,7 +842,7 @@ def run_grouping_study(args, torch, synth, p, dev):
         f"{time.time() - t0:.1f}s")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     ctx = p.gw_ctx_create(0)
-    geom = p.gw_geom_create(ctx, (nd,) * 3, gw, gc)
+    geom = p.gw_geom_create(ctx, (nd,) * 3, gw, gc, cfg.cell, cfg.qs[0])
     cv, ev, cc = t(bands.coef_v), t(bands.e_v), t(bands.coef_c)
     del bands
     ng = len(gc)
@@ -598,7 +884,7 @@ def run_grouping_study(args, torch, synth, p, dev):
         p.gw_chi0_build(ctx, [prob], [ng], [0.0], 0.0, prec, workspace=ws, out=out)
         torch.cuda.synchronize()
         dt = time.perf_counter() - a
-        p.gw_eps_inv(ctx, vcoul, out.view(ng, ng), workspace=ws_inv, out=z)
+        p.gw_eps_inv(ctx, vcoul, out.view(ng, ng), workspace=ws_inv, out=z, hermitian=True)
         p.gw_eps_inv_status(ctx)
         return dt, out.view(ng, ng).clone(), float(z[head, head].real.sum().item())
 
@@ -681,14 +967,14 @@ def run_reduced_box(args, torch, synth, p, dev):
         res[m] = {}
         chis = {}
         for nd in (cfg.nd, 48):
-            geom = p.gw_geom_create(ctx, (nd,) * 3, gw, gc)
+            geom = p.gw_geom_create(ctx, (nd,) * 3, gw, gc, cfg.cell, cfg.qs[0])
             prob = p.make_problem(geom, cv, ev, cc, ec)
             ws = torch.empty(p.gw_chi0_workspace_size(ctx, [prob], 1, p.PRECISIONS[m]), dtype=torch.uint8, device=dev)
             out = torch.empty(ng * ng, dtype=torch.complex128, device=dev)
 
             def run():
                 p.gw_chi0_build(ctx, [prob], [ng], [0.0], 0.0, p.PRECISIONS[m], workspace=ws, out=out)
-                p.gw_eps_inv(ctx, vcoul, out.view(ng, ng), workspace=ws_inv, out=zout)
+                p.gw_eps_inv(ctx, vcoul, out.view(ng, ng), workspace=ws_inv, out=zout, hermitian=True)
             for _ in range(max(1, args.warmup)):
                 run()
             torch.cuda.synchronize()
@@ -790,7 +1076,7 @@ def run_extensions(args, torch, synth, p, dev):
     prob = p.make_problem(geom, cv, t(bands.e_v), cc, t(bands.e_c))
     chi0 = p.gw_chi0_build(ctx, [prob], [ng], [0.0], 0.0, p.GW_FP64)[0][0]
     vc = t(synth.coulomb(gc0, cfg.qs[0], cfg.cell))
-    z = p.gw_eps_inv(ctx, vc, chi0)
+    z = p.gw_eps_inv(ctx, vc, chi0, hermitian=True)
     call = torch.cat([cv, cc])
     states = torch.cat([cv[-4:], cc[:4]]).contiguous()
     ncols = cfg.nv + cfg.nc
