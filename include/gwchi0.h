@@ -274,11 +274,15 @@ gw_status gw_tune(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, int nome
  * per workgroup, 5 = lean split-line form with 2 valence bands, which keeps the stage-2
  * items beyond one per thread in LDS; it exists where the dielectric sphere spans 17 or 19
  * frequencies along x3 on the 72^3 grid, and in float32 also from 17 on the 96^3 grid and
- * from 23 on the 128^3 grid; elsewhere form 5 runs form 1) and the number of pair-range
- * splits of the contraction; both 0 if the shape was not tuned. */
+ * from 23 on the 128^3 grid; elsewhere form 5 runs form 1; 6 / 7 = direct-load split-line form
+ * with 4 valence bands and four step buffers / 2 valence bands and two step buffers, which
+ * streams the band rows from memory straight into LDS; it exists where a radix-R chunk row is
+ * 128 bytes (float32 on 64^3, 96^3 and 128^3 grids, float64 on radix-8 grids) and its LDS
+ * fits, elsewhere it runs form 1) and the number of pair-range splits of the contraction;
+ * both 0 if the shape was not tuned. */
 gw_status gw_tune_get(gw_ctx* ctx, const gw_chi0_problem* prob, gw_precision prec, int* pair_variant, int* ksplit);
 /* Sets the shapes for prob's problem shape, e.g. to restore what gw_tune_get reported in
- * an earlier process: pair_variant 0..5 (0 = automatic), ksplit 0..32 (0 = automatic);
+ * an earlier process: pair_variant 0..7 (0 = automatic), ksplit 0..32 (0 = automatic);
  * both 0 forgets the shape.  GW_EINVAL outside those ranges. */
 gw_status gw_tune_set(gw_ctx* ctx, const gw_chi0_problem* prob, gw_precision prec, int pair_variant, int ksplit);
 

@@ -157,10 +157,11 @@ hipError_t launch_gpp_coh_sum(const void* part, int ngp, int ne, int ns, int sa,
 // plasmon-pole extension (gpp.hip)
 hipError_t launch_gpp(const void* eps0, int ng, const double* kvec, const int32_t* gvec, const void* rho, int half,
                       const double* omega, int nomega, double eta, void* modes, void* out, hipStream_t st);
-constexpr int kPairVariants = 5;   // forms of the pair kernel a tuned shape may name
+constexpr int kPairVariants = 7;   // forms of the pair kernel a tuned shape may name
 // minb: 0 = automatic, 1 or 2 = 256-thread kernel with that many resident workgroups per CU,
-// 3 / 4 = split-line kernel with 4 / 2 valence bands per workgroup (falls back to the
-// 256-thread kernel where its LDS does not fit).
+// 3 / 4 = split-line kernel with 4 / 2 valence bands per workgroup, 5 = its lean form,
+// 6 / 7 = its direct-load form with 4 / 2 valence bands (a form not built for the instance
+// falls back to the 256-thread kernel).
 template <typename T>
 hipError_t launch_pair_planes(const Geom& g, const void* psi_v, const void* psi_c, int nvs, int ncs, void* q,
                               int minb, hipStream_t st);

@@ -227,6 +227,55 @@ constexpr bool lean_fits() {
   return L::nover > 0 && L::nover <= 256 && 2 * L::bytes <= 160 * 1024;
 }
 
+// Direct-load form of the split-line kernel.  The chunk rows go from global memory straight
+// into LDS by 16-byte direct loads (global_load_lds_dwordx4, one wave instruction per block of
+// 8 rows of one kind and half), NBUF - 1 steps ahead of their use, into NBUF separate LDS
+// arrays (separate objects, so that the compiler does not wait for the loads in flight into
+// one buffer before reading another).  No registers hold the staged chunks and no LDS stores
+// are issued for them.  A chunk row is R x sizeof(V) = 128 bytes, eight 16-byte units; a
+// block keeps them unit-major (unit u of row r in slot 8 u + r), so that the 8 lanes that
+// read unit u of the block's 8 rows read 128 contiguous bytes, and the second block of each
+// pair starts 1152 bytes after the first, so that the two blocks read by one 16-lane group
+// fall on different banks.
+template <typename T, int R, int K, int TV, int NBUF>
+struct DlLds {
+  static constexpr int UR = R * (int)sizeof(cx<T>) / 16;   // 16-byte units per chunk row
+  static constexpr int nblk = 2 * (kTC + TV);               // 8-row blocks of one step
+  static constexpr int units = nblk / 2 * 136;              // block pairs of 64 + 64 + 8 units
+  static constexpr size_t bytes = NBUF * (size_t)units * 16 + (size_t)TV * kTC * kRows * K * sizeof(cx<T>) +
+                                  (size_t)32 * K * sizeof(cx<T>);   // twiddles of up to 32 chunk rows
+};
+
+template <typename T, int R, int K, int TV, int NBUF>
+constexpr bool dl_fits() {
+  using L = DlLds<T, R, K, TV, NBUF>;
+  return L::UR == 8 && L::nblk % (2 * TV) == 0 && L::bytes <= 160 * 1024;
+}
+
+// first unit of block qb of a step buffer
+__device__ __forceinline__ int dl_block(int qb) { return (qb >> 1) * 136 + (qb & 1) * 72; }
+
+// s_waitcnt with vmcnt = n (0..63) and no wait on the other counters
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
+
+// Workgroup barrier for LDS data only: this wave's LDS operations complete (lgkmcnt 0), then
+// all waves meet; the empty asm statements keep the compiler from moving memory accesses
+// across it.  Unlike __syncthreads (whose fence also covers the LDS writes of direct loads,
+// hence waits for every one in flight) it leaves the direct loads of later steps in flight;
+// the wait for a step's own direct loads is explicit (wait_vm).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4));   // lgkmcnt(0); vmcnt, expcnt not waited
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // Automatic form (measured per 32k-pair launch on one MI355X).  float64: the lean
 // two-valence kernel where it is built (72^3 K 17: 19.9 against 34.3 ms for the plain
 // two-valence form; K 19: 21.2 against 36.5 ms), else the two-valence split-line kernel
@@ -234,10 +283,12 @@ constexpr bool lean_fits() {
 // K 25: 176 against 402 ms), since it halves the per-lane state that otherwise costs the
 // 256-thread kernel its second resident workgroup or spills.  float32: on radix-8 grids
 // the lean kernel where it is built (72^3 K 17: 10.7 against 12.9 ms for the 256-thread
-// one; K 19: 12.1 against 13.6 ms), else the 256-thread kernel up to K = 21 (72^3 K 15:
-// 8.7 ms; 96^3 K 17: 21.7 against 26.4 for the lean form; K 19: 22.9), and the
-// four-valence split-line kernel from K = 23 on (128^3 K 25: 74.2 ms, against 77.1 for
-// the lean form and 114 for the 256-thread one).
+// one; K 19: 12.1 against 13.6 ms), else the 256-thread kernel up to K = 17 (72^3 K 15:
+// 8.7 ms; 96^3 K 17: 21.8 against 23.9 for the direct-load form and 26.4 for the lean one),
+// and from K = 19 on the four-valence direct-load kernel where its rows are 128 bytes
+// (96^3 K 19: 25.0 against 42.4 ms for the 256-thread kernel; 128^3 K 23: 59.5 against 70.7
+// for the four-valence split-line kernel; K 25: 62.0 against 74.7), else the four-valence
+// split-line kernel from K = 23 on.
 template <typename T, int R, int K>
 constexpr int auto_variant() {
   if constexpr (std::is_same<T, double>::value) {
@@ -245,6 +296,7 @@ constexpr int auto_variant() {
     if constexpr (split_fits<T, R, K, 2>()) return 4;
   } else {
     if constexpr (R <= 8 && lean_fits<T, R, K>()) return 5;
+    if constexpr (K >= 19 && dl_fits<T, R, K, 4, 4>()) return 6;
     if constexpr (K >= 23 && split_fits<T, R, K, 4>()) return 3;
   }
   return planes_min_blocks<T, R, K>();
@@ -461,6 +513,199 @@ __global__ __launch_bounds__(128 * TV, LEAN ? 2 : 1) void k_pair_planes_split(co
   }
 }
 
+template <typename T, int ND, int R, int K, int TV, int NBUF>
+__global__ __launch_bounds__(128 * TV, 1) void k_pair_planes_dl(const cx<T>* __restrict__ psi_v,
+                                                                const cx<T>* __restrict__ psi_c, int nvs, int ncs,
+                                                                const cx<T>* __restrict__ twk,
+                                                                cx<T>* __restrict__ q) {
+  using V = cx<T>;
+  using L = DlLds<T, R, K, TV, NBUF>;
+  constexpr int NT = 128 * TV;
+  constexpr int NW = NT / 64;
+  constexpr int S = ND / R;
+  constexpr int SL = (S + 1) / 2;
+  constexpr int SH = S - SL;
+  constexpr int S2 = ND / kRows;
+  constexpr int NSTEP = S2 * SL;
+  constexpr int RCH = (K - 1) / 2;
+  constexpr int NPAIR = TV * kTC;
+  constexpr int NITEM = NPAIR * K;
+  constexpr int IPL = (NITEM + NT - 1) / NT;
+  constexpr int UR = L::UR;
+  constexpr int EPU = 16 / (int)sizeof(V);       // elements per unit
+  constexpr int IPW = L::nblk / NW;              // load instructions per wave and step
+  static_assert(NBUF >= 2 && NBUF <= 4 && IPW * (NBUF - 2) < 64, "load pipeline");
+  constexpr size_t NPL = (size_t)ND * ND;
+  __shared__ __align__(16) uint4 sb0[L::units];
+  __shared__ __align__(16) uint4 sb1[L::units];
+  __shared__ __align__(16) uint4 sb2[NBUF > 2 ? L::units : 1];
+  __shared__ __align__(16) uint4 sb3[NBUF > 3 ? L::units : 1];
+  __shared__ V s_z[NPAIR * kRows * K];
+  constexpr int NTW = (S > S2 ? S : S2) * K;
+  __shared__ V s_tw[NTW];   // twiddles of both stages, read as LDS broadcasts (scalar loads of
+                            // every unrolled step's twiddles would not fit the scalar registers)
+
+  const int nbc = ncs / kTC;
+  const int nbv = nvs / TV;
+  const int pb = blockIdx.x % (nbc * nbv);
+  const int x1 = blockIdx.x / (nbc * nbv);
+  const int c0 = (pb % nbc) * kTC;
+  const int v0 = (pb / nbc) * TV;
+
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wv = wave % TV;
+  const int hf = wave / TV;
+  const int lane = tid & 63;
+  const int cl = lane / kRows;
+  const int a2 = lane % kRows;
+
+  // Load block qb = NW i + wave of a step: conduction blocks h kTC + column, then valence
+  // blocks 2 kTC + h TV + band; lane l loads unit l / 8 of x2 row l % 8.
+  const char* pc_base = (const char*)(psi_c + ((size_t)c0 * ND + x1) * NPL);
+  const char* pv_base = (const char*)(psi_v + ((size_t)v0 * ND + x1) * NPL);
+  unsigned loff[IPW];
+#pragma unroll
+  for (int i = 0; i < IPW; ++i) {
+    const int qb = NW * i + wave;
+    const bool isc = qb < 2 * kTC;
+    const int band = isc ? qb % kTC : (qb - 2 * kTC) % TV;
+    loff[i] = (unsigned)(((size_t)band * ND * NPL + (size_t)(lane % 8) * ND) * sizeof(V) + 16 * (lane / 8));
+  }
+  auto issue = [&](int st, uint4* buf) {
+    const int g2 = st / SL, t = st % SL;
+#pragma unroll
+    for (int i = 0; i < IPW; ++i) {
+      const int qb = NW * i + wave;
+      const bool isc = qb < 2 * kTC;
+      const int h = isc ? qb / kTC : (qb - 2 * kTC) / TV;
+      const int b = min(h ? SL + t : t, S - 1);   // a missing last chunk of the second half: any valid row
+      const char* src = (isc ? pc_base : pv_base) + ((size_t)g2 * kRows * ND + (size_t)b * R) * sizeof(V) + loff[i];
+      __builtin_amdgcn_global_load_lds((const void*)src,
+                                       (__attribute__((address_space(3))) void*)&buf[dl_block(qb)], 16, 0, 0);
+    }
+  };
+
+  for (int e = tid; e < NTW; e += NT) s_tw[e] = twk[e];   // visible after the first step's barrier
+  V qacc[IPL][K];
+#pragma unroll
+  for (int r = 0; r < IPL; ++r)
+#pragma unroll
+    for (int j = 0; j < K; ++j) qacc[r][j] = V{T(0), T(0)};
+  V acc[K];
+
+  // this lane's rows: conduction (half hf, column cl, x2 row a2), valence (half hf, band wv);
+  // unit u is 8 u further
+  const int cbase = dl_block(hf * kTC + cl) + a2;
+  const int vbase = dl_block(2 * kTC + hf * TV + wv) + a2;
+
+  // Every step issues the loads of step st + NBUF - 1 (past the end: the last step's rows
+  // again, into a buffer that is not read), so that exactly (NBUF - 2) IPW loads of this
+  // wave are issued after step st's: the wait count is one constant, and the step has no
+  // branches (across which the compiler would sink every step's arithmetic into the last).
+  auto step = [&](int st, const uint4* cur, uint4* nxt) {
+    wait_vm<(NBUF - 2) * IPW>();
+    lds_barrier();   // everyone's loads of this step landed; everyone is done with step st - 1
+    issue(min(st + NBUF - 1, NSTEP - 1), nxt);
+    const int t = st % SL;
+    // the second half has one chunk fewer for odd S: that step computes on the clamped rows
+    // with zero twiddles
+    const bool live = hf == 0 || t < SH;
+    const int b = hf ? min(SL + t, S - 1) : t;
+    {
+      V x[R];
+#pragma unroll
+      for (int u = 0; u < UR; ++u) {
+        const uint4 cu = cur[cbase + 8 * u];
+        const uint4 vu = cur[vbase + 8 * u];
+        V cv[EPU], vv[EPU];
+        __builtin_memcpy(cv, &cu, 16);
+        __builtin_memcpy(vv, &vu, 16);
+#pragma unroll
+        for (int e = 0; e < EPU; ++e) x[u * EPU + e] = cmulc(vv[e], cv[e]);
+      }
+      dft<R>(x);
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const int n = j - RCH;
+        const V tw = s_tw[b * K + j];
+        const V tv = live ? tw : V{T(0), T(0)};
+        cmac(acc[j], tv, x[((n % R) + R) % R]);
+      }
+    }
+  };
+  // end of x2 group b2: the two halves' Z into LDS, then stage 2
+  auto group_end = [&](int b2) {
+    V* z = s_z + ((wv * kTC + cl) * kRows + a2) * K;
+    if (hf == 1) {
+#pragma unroll
+      for (int j = 0; j < K; ++j) z[j] = acc[j];
+    }
+    lds_barrier();
+    if (hf == 0) {
+#pragma unroll
+      for (int j = 0; j < K; ++j) z[j] = cadd(z[j], acc[j]);
+    }
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < IPL; ++r) {
+      const int it = tid + NT * r;
+      if (it < NITEM) {
+        const int pair = it / K, j3 = it % K;
+        V y[kRows];
+#pragma unroll
+        for (int a = 0; a < kRows; ++a) y[a] = s_z[(pair * kRows + a) * K + j3];
+        dft<kRows>(y);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const int n = j - RCH;
+          const V tv = s_tw[b2 * K + j];
+          cmac(qacc[r][j], tv, y[((n % kRows) + kRows) % kRows]);
+        }
+      }
+    }
+    // s_z is rewritten only after the barriers of the next group's steps
+  };
+
+  // groups are unrolled GU at a time, so that every step's buffer is a fixed array
+  constexpr int GU = NBUF / gcd_c(SL, NBUF);
+  uint4* const bufs[4] = {sb0, sb1, sb2, sb3};
+#pragma unroll
+  for (int k = 0; k < NBUF - 1; ++k)
+    if (k < NSTEP) issue(k, bufs[k]);
+  for (int b20 = 0; b20 < S2; b20 += GU) {
+#pragma unroll
+    for (int gg = 0; gg < GU; ++gg) {
+      const int b2 = b20 + gg;
+      if (b2 < S2) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) acc[j] = V{T(0), T(0)};
+#pragma unroll
+        for (int t = 0; t < SL; ++t) {
+          const int k = (gg * SL + t) % NBUF;
+          step(b2 * SL + t, bufs[k], bufs[(k + NBUF - 1) % NBUF]);
+        }
+        group_end(b2);
+      }
+    }
+  }
+  wait_vm<0>();   // no direct load may still be writing this workgroup's LDS when it ends
+
+  const int p1 = (x1 % S) * R + x1 / S;
+#pragma unroll
+  for (int r = 0; r < IPL; ++r) {
+    const int it = tid + NT * r;
+    if (it < NITEM) {
+      const int pair = it / K, j3 = it % K;
+      const int pv = pair / kTC, pc = pair % kTC;
+      const size_t pg = (size_t)(v0 + pv) * ncs + (c0 + pc);
+      V* dst = q + (pg * ND + p1) * (K * K) + j3;
+#pragma unroll
+      for (int j = 0; j < K; ++j) dst[j * K] = qacc[r][j];
+    }
+  }
+}
+
 template <typename T, int ND, int R, int K>
 __global__ __launch_bounds__(256) void k_pair_finish(const cx<T>* __restrict__ q, const int32_t* __restrict__ chi_map,
                                                      int ng, int ngp, T scale, const cx<T>* __restrict__ twk,
@@ -510,9 +755,24 @@ hipError_t run_planes(const Geom& g, const void* psi_v, const void* psi_c, int n
   const cx<T>* pc = (const cx<T>*)psi_c;
   // variant: 1 / 2 = 256-thread kernel with one / two resident workgroups per CU,
   // 3 / 4 = split-line kernel with 4 / 2 valence bands per workgroup, 5 = lean split-line
-  // kernel with 2 valence bands, 0 = automatic
+  // kernel with 2 valence bands, 6 / 7 = direct-load split-line kernel with 4 valence bands
+  // and four buffers / 2 valence bands and two buffers, 0 = automatic
   int variant = minb;
   if (variant == 0) variant = auto_variant<T, R, K>();
+  if constexpr (dl_fits<T, R, K, 4, 4>()) {
+    if (variant == 6) {
+      const int nblk = ND * (nvs / 4) * (ncs / kTC);
+      k_pair_planes_dl<T, ND, R, K, 4, 4><<<nblk, 512, 0, st>>>(pv, pc, nvs, ncs, tw, (cx<T>*)q);
+      return hipGetLastError();
+    }
+  }
+  if constexpr (dl_fits<T, R, K, 2, 2>()) {
+    if (variant == 7) {
+      const int nblk = ND * (nvs / 2) * (ncs / kTC);
+      k_pair_planes_dl<T, ND, R, K, 2, 2><<<nblk, 256, 0, st>>>(pv, pc, nvs, ncs, tw, (cx<T>*)q);
+      return hipGetLastError();
+    }
+  }
   if constexpr (lean_fits<T, R, K>()) {
     if (variant == 5) {
       const int nblk = ND * (nvs / 2) * (ncs / kTC);

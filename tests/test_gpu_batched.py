@@ -100,13 +100,14 @@ def test_tuner_choices_keep_parity(g):
 
 
 # 72^3 with NG 2600 / 3600 gives K = 17 / 19, where the lean split-line form (5) is built;
-# the last three run a workload's spheres on its smaller alias-free grid (the instances
-# (48, K 15), (64, K 19) and (96, K 25)) against the oracle on the stated grid
+# 128^3 with NG 8000 is the 256-atom workload's K = 25 (the direct-load forms 6 and 7); the
+# last three run a workload's spheres on its smaller alias-free grid (the instances (48, K 15),
+# (64, K 19) and (96, K 25)) against the oracle on the stated grid
 @pytest.mark.parametrize("cfg,ng,grid", [(0, None, None), (1, 300, None), (1, 2600, None), (1, 3600, None),
-                                         (2, 2600, None), (4, 6500, None), (1, 2000, 48), (2, 4000, 64),
-                                         (4, 8000, 96)],
-                         ids=["24cube", "72cube", "72cube-K17", "72cube-K19", "96cube", "128cube", "72cube-on-48",
-                              "96cube-on-64", "128cube-on-96"])
+                                         (2, 2600, None), (4, 6500, None), (4, 8000, None), (1, 2000, 48),
+                                         (2, 4000, 64), (4, 8000, 96)],
+                         ids=["24cube", "72cube", "72cube-K17", "72cube-K19", "96cube", "128cube", "128cube-K25",
+                              "72cube-on-48", "96cube-on-64", "128cube-on-96"])
 def test_every_pair_kernel_form_matches_oracle(g, cfg, ng, grid):
     # each form of the pair kernel forced through gw_tune_set, float64 and float32, on a
     # conduction count that is not a multiple of the workgroup's 8 columns
@@ -118,7 +119,7 @@ def test_every_pair_kernel_form_matches_oracle(g, cfg, ng, grid):
         case = dataclasses.replace(case, nd=grid)
     prob = g.problem(case)
     for prec, tol in (("fp64", 1e-10), ("fp32", 2e-5)):
-        for form in (1, 2, 3, 4, 5):
+        for form in (1, 2, 3, 4, 5, 6, 7):
             p.gw_tune_set(g.ctx, prob, p.PRECISIONS[prec], form, 0)
             assert p.gw_tune_get(g.ctx, prob, p.PRECISIONS[prec]) == (form, 0)
             chi = g.chi0(case, prec=prec)[0]
@@ -127,7 +128,7 @@ def test_every_pair_kernel_form_matches_oracle(g, cfg, ng, grid):
         p.gw_tune_set(g.ctx, prob, p.PRECISIONS[prec], 0, 0)
         assert p.gw_tune_get(g.ctx, prob, p.PRECISIONS[prec]) == (0, 0)
     with pytest.raises(p.GwError):
-        p.gw_tune_set(g.ctx, prob, p.GW_FP64, 6, 0)
+        p.gw_tune_set(g.ctx, prob, p.GW_FP64, 8, 0)
     with pytest.raises(p.GwError):
         p.gw_tune_set(g.ctx, prob, p.GW_FP64, 1, 33)
 
