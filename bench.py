@@ -87,11 +87,13 @@ def measured_traffic(stage, mode):
         pats = pat if isinstance(pat, tuple) else (pat,)
         keys = tuple(p.format(t="double" if mode == "fp64" else "float", m={"fp64": 0, "fp32": 1, "bf16x3": 2}[mode])
                      for p in pats)
+        if stage == "contract" and mode == "bf16x3":
+            keys = ("k_contract_img",)   # the static split-BF16x3 contraction
         for k, v in tr["kernels"].items():
             if k.startswith(keys):
                 return {"read_bytes": v["read_bytes_per_dispatch"], "write_bytes": v["write_bytes_per_dispatch"],
                         "bytes": v["read_bytes_per_dispatch"] + v["write_bytes_per_dispatch"],
-                        "source": "profiles/chi0_build_72cube_512kpairs_hbm_counters.md"}
+                        "kernel": k, "source": v.get("profile", "profiles/traffic.json")}
     except (OSError, KeyError, ValueError):
         pass
     return None
@@ -235,14 +237,15 @@ def run_headline(args, torch, synth, p, dev):
         bound = "mfma"
         peak = {"fp64": PEAK["fp64_mfma"], "fp32": PEAK["fp32_mfma"], "bf16x3": PEAK["bf16_mfma"]}[head]
         work = fl["contract"] / launches
-        traffic = traffic_for([f"k_contract_batch<{ {'fp64': 0, 'fp32': 1, 'bf16x3': 2}[head] },"], "contract.hip")
+        traffic = traffic_for(["k_contract_img" if head == "bf16x3" else
+                               f"k_contract_batch<{ {'fp64': 0, 'fp32': 1}[head] },"], "contract.hip")
         basis = f"{head} matrix-core peak (split products not counted as work)"
     else:
         bound = "alu"
         peak = PEAK["fp64_vec"] if head == "fp64" else PEAK["fp32_vec_nopk"]
         work = fl[dom] / launches
         kern = {"planes": ["k_pair_planes"], "finish": ["k_pair_finish"], "band": ["k_band"]}.get(dom, [dom])
-        traffic = traffic_for([f"{x}<{fp}, {nd}, " for x in kern] + [f"{x}_split<{fp}, {nd}, " for x in kern],
+        traffic = traffic_for([f"{x}{v}<{fp}, {nd}, " for x in kern for v in ("", "_split", "_dl")],
                               "pair_transform.hip" if dom in ("planes", "finish") else "band_fft.hip")
         basis = ("256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz: the float64 vector rate, and the float32 "
                  "rate without packed instructions, which this build does not use")
@@ -299,6 +302,52 @@ def run_headline(args, torch, synth, p, dev):
             "cpu_baseline": cpu, "mgo64_static_72cube": c2, "skipped": skipped or None,
             "run_s": time.time() - T_START}
     print(json.dumps(line))
+
+
+def run_chunk(args, torch, synth, p, dev):
+    """One conduction chunk of a configuration's shape for profiler and counter runs: random
+    coefficient rows (the kernels' cost does not depend on their values), one build (or backward)
+    per call, chunk overlap off so that every kernel runs on the context's stream."""
+    if args.copy_calibration:
+        x = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        torch.mul(x, 2.0, out=y)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written by one elementwise kernel")
+        del x, y
+    parts = args.chunk.split(":")
+    cfg_i, mode, nv, ncol = int(parts[0]), parts[1], int(parts[2]), int(parts[3])
+    backward = len(parts) > 4 and parts[4] == "backward"
+    cfg = synth.config(cfg_i)
+    gw = synth.wf_sphere(cfg.nd)
+    gc = synth.chi_sphere(cfg.ng[0], cfg.qs[0], cfg.cell)
+    g = torch.Generator(device=dev)
+    g.manual_seed(1)
+    cv = torch.randn((nv, len(gw)), dtype=torch.complex128, device=dev, generator=g) / np.sqrt(len(gw))
+    cc = torch.randn((ncol, len(gw)), dtype=torch.complex128, device=dev, generator=g) / np.sqrt(len(gw))
+    ev = torch.linspace(-0.4, -0.01, nv, dtype=torch.float64, device=dev)
+    ec = torch.linspace(0.2, 2.0, ncol, dtype=torch.float64, device=dev)
+    ctx = p.gw_ctx_create(0)
+    p.gw_ctx_set_overlap(ctx, 0)
+    geom = p.gw_geom_create(ctx, (cfg.nd,) * 3, gw, gc, cfg.cell, cfg.qs[0])
+    prob = p.make_problem(geom, cv, ev, cc, ec)
+    ng = len(gc)
+    prec = p.PRECISIONS[mode]
+    ws = torch.empty(p.gw_chi0_workspace_size(ctx, [prob], 1, prec), dtype=torch.uint8, device=dev)
+    if backward:
+        gb = torch.randn((1, ng, ng), dtype=torch.complex128, device=dev, generator=g)
+        gb = (gb + gb.conj().transpose(1, 2)).contiguous()
+    log(f"chunk: {cfg.name}, {mode}, {nv} x {ncol} pairs, NG {ng}, {'backward' if backward else 'build'}")
+    for r in range(args.reps):
+        t0 = time.time()
+        if backward:
+            p.gw_chi0_backward(ctx, [prob], [0.0], 0.0, prec, gb, workspace=ws)
+        else:
+            p.gw_chi0_build(ctx, [prob], [ng], [0.0], 0.0, prec, workspace=ws)
+        torch.cuda.synchronize()
+        log(f"call {r + 1}/{args.reps}: {time.time() - t0:.3f} s")
+    p.gw_geom_destroy(geom)
+    p.gw_ctx_destroy(ctx)
 
 
 def run_c2_beside(args, torch, synth, p, dev, ctx):
@@ -362,7 +411,7 @@ def main():
                     help="npz file for the generated inputs: loaded if present, written otherwise")
     ap.add_argument("--workload", default="headline",
                     choices=["headline", "static", "batched", "grouped", "adjoint", "grouping-study", "extensions",
-                             "reduced-box"],
+                             "reduced-box", "chunk"],
                     help="headline (default): the 128^3 / 512 x 25000 grouped / NG 8000 build, mixed precision "
                          "with a float64 step and the 72^3 workload beside it; "
                          "static: the 72^3 / 128x4000 / NG 2000 build; batched: 8 q-points x 16 "
@@ -373,7 +422,9 @@ def main():
                          "exactly and grouped on several energy grids (accuracy and time against the exact sum); "
                          "extensions: the k-point sum, the static COH self-energy and the plasmon-pole "
                          "eps^-1(w); reduced-box: the static inputs on the stated 72^3 grid and on the smallest "
-                         "supported alias-free grid (48^3), reported beside the metric, never as it")
+                         "supported alias-free grid (48^3), reported beside the metric, never as it; chunk: "
+                         "one conduction chunk of a configuration's shape (--chunk), a short driver for "
+                         "profiler and counter runs, no JSON line")
     ap.add_argument("--grid", type=int, default=0,
                     help="grouped / adjoint workloads: FFT grid N^3 to run on instead of the stated one (an "
                          "alias-free smaller box gives the same chi0: 64 for the 96^3 workload, 96 for the "
@@ -391,6 +442,11 @@ def main():
     ap.add_argument("--budget-s", type=float, default=540.0,
                     help="headline workload: wall-clock budget of the whole run; the legs beside the timed steps "
                          "(float64 step, oracle sample, 72^3 workload) are skipped when they would overrun it")
+    ap.add_argument("--chunk", default="4:bf16x3:64:512",
+                    help="chunk workload: CONFIG:MODE:NV:NCOL[:backward], configuration index (0..4), precision, "
+                         "valence rows and columns (one chunk: NV x NCOL <= 32768 pairs), and the adjoint "
+                         "instead of the build")
+    ap.add_argument("--reps", type=int, default=1, help="chunk workload: calls")
     ap.add_argument("--cpu-pairs", default="2x40",
                     help="headline workload: oracle sample, valence x columns of the full-size workload")
     args = ap.parse_args()
@@ -407,6 +463,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "headline":
         run_headline(args, torch, synth, p, dev)
+        return
+    if args.workload == "chunk":
+        run_chunk(args, torch, synth, p, dev)
         return
     if args.workload == "batched":
         run_batched(args, torch, synth, p, dev)

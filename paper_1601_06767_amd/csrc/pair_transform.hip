@@ -252,6 +252,13 @@ constexpr bool dl_fits() {
   return L::UR == 8 && L::nblk % (2 * TV) == 0 && L::bytes <= 160 * 1024;
 }
 
+// buffers of the four-valence direct-load form: as many as fit (three or four), none if
+// fewer than three fit
+template <typename T, int R, int K>
+constexpr int dl4_nbuf() {
+  return dl_fits<T, R, K, 4, 4>() ? 4 : dl_fits<T, R, K, 4, 3>() ? 3 : 0;
+}
+
 // first unit of block qb of a step buffer
 __device__ __forceinline__ int dl_block(int qb) { return (qb >> 1) * 136 + (qb & 1) * 72; }
 
@@ -296,7 +303,7 @@ constexpr int auto_variant() {
     if constexpr (split_fits<T, R, K, 2>()) return 4;
   } else {
     if constexpr (R <= 8 && lean_fits<T, R, K>()) return 5;
-    if constexpr (K >= 19 && dl_fits<T, R, K, 4, 4>()) return 6;
+    if constexpr (K >= 19 && dl4_nbuf<T, R, K>() > 0) return 6;
     if constexpr (K >= 23 && split_fits<T, R, K, 4>()) return 3;
   }
   return planes_min_blocks<T, R, K>();
@@ -756,13 +763,13 @@ hipError_t run_planes(const Geom& g, const void* psi_v, const void* psi_c, int n
   // variant: 1 / 2 = 256-thread kernel with one / two resident workgroups per CU,
   // 3 / 4 = split-line kernel with 4 / 2 valence bands per workgroup, 5 = lean split-line
   // kernel with 2 valence bands, 6 / 7 = direct-load split-line kernel with 4 valence bands
-  // and four buffers / 2 valence bands and two buffers, 0 = automatic
+  // and four (or three) buffers / 2 valence bands and two buffers, 0 = automatic
   int variant = minb;
   if (variant == 0) variant = auto_variant<T, R, K>();
-  if constexpr (dl_fits<T, R, K, 4, 4>()) {
+  if constexpr (dl4_nbuf<T, R, K>() > 0) {
     if (variant == 6) {
       const int nblk = ND * (nvs / 4) * (ncs / kTC);
-      k_pair_planes_dl<T, ND, R, K, 4, 4><<<nblk, 512, 0, st>>>(pv, pc, nvs, ncs, tw, (cx<T>*)q);
+      k_pair_planes_dl<T, ND, R, K, 4, dl4_nbuf<T, R, K>()><<<nblk, 512, 0, st>>>(pv, pc, nvs, ncs, tw, (cx<T>*)q);
       return hipGetLastError();
     }
   }
