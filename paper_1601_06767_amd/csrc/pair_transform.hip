@@ -290,12 +290,12 @@ __device__ __forceinline__ void lds_barrier() {
 // K 25: 176 against 402 ms), since it halves the per-lane state that otherwise costs the
 // 256-thread kernel its second resident workgroup or spills.  float32: on radix-8 grids
 // the lean kernel where it is built (72^3 K 17: 10.7 against 12.9 ms for the 256-thread
-// one; K 19: 12.1 against 13.6 ms), else the 256-thread kernel up to K = 17 (72^3 K 15:
-// 8.7 ms; 96^3 K 17: 21.8 against 23.9 for the direct-load form and 26.4 for the lean one),
-// and from K = 19 on the four-valence direct-load kernel where its rows are 128 bytes
-// (96^3 K 19: 25.0 against 42.4 ms for the 256-thread kernel; 128^3 K 23: 59.5 against 70.7
-// for the four-valence split-line kernel; K 25: 62.0 against 74.7), else the four-valence
-// split-line kernel from K = 23 on.
+// one; K 19: 12.1 against 13.6 ms), else the 256-thread kernel up to K = 21 (72^3 K 15:
+// 8.7 ms; 96^3 K 17: 21.7 against 23.7 for the direct-load form and 26.4 for the lean one;
+// K 19: 23.0 against 24.8, both with two workgroups per CU, 42.4 with one), and from K = 23 on
+// the four-valence direct-load kernel where its rows are 128 bytes (128^3 K 23: 59.5 against
+// 70.7 for the four-valence split-line kernel and 74.4 for the 256-thread one; K 25: 62.0
+// against 74.7 and 123), else the four-valence split-line kernel.
 template <typename T, int R, int K>
 constexpr int auto_variant() {
   if constexpr (std::is_same<T, double>::value) {
@@ -303,7 +303,7 @@ constexpr int auto_variant() {
     if constexpr (split_fits<T, R, K, 2>()) return 4;
   } else {
     if constexpr (R <= 8 && lean_fits<T, R, K>()) return 5;
-    if constexpr (K >= 19 && dl4_nbuf<T, R, K>() > 0) return 6;
+    if constexpr (K >= 23 && dl4_nbuf<T, R, K>() > 0) return 6;
     if constexpr (K >= 23 && split_fits<T, R, K, 4>()) return 3;
   }
   return planes_min_blocks<T, R, K>();
