@@ -102,8 +102,8 @@ gw_status gw_ctx_set_overlap(gw_ctx* ctx, int mode);
 /* ---------------------------------------------------------------- geometry */
 
 /* Plane-wave geometry of one q-point (set-up; synchronises the stream).
- *   n_fft[3]   FFT grid N1, N2, N3 (host).  The kernels need N1 = N2 = N3 in
- *              {24, 32, 48, 64, 72, 96, 128}; other grids give GW_EUNSUPPORTED.
+ *   n_fft[3]   FFT grid N1, N2, N3 (host).  The kernels need N1 = N2 = N3, a multiple
+ *              of 8 from 16 to 128; other grids give GW_EUNSUPPORTED.
  *   cell, q    host, or both NULL: the lattice vectors a1, a2, a3 as rows (9 doubles, bohr)
  *              and q in reciprocal-lattice units (3 doubles).  With them the dielectric
  *              sphere is checked to be the first ng G-vectors in the order
@@ -123,9 +123,11 @@ gw_status gw_ctx_set_overlap(gw_ctx* ctx, int mode);
  * (reading of Eq. (chi0)'s matrix element, whose exponent is printed without ".r").
  * Every grid that meets the bound gives the same chi0 up to rounding, so the smallest
  * supported one is the cheapest (the 72^3 workload's spheres, 2 x 18 + 7 = 43, are exact on
- * 48^3).  The pair kernels are built for these (grid, K = 2 max|n_chi| + 1): 24^3 with K 5,
- * 7, 9, 11; 48^3 with 15; 64^3 with 19; 72^3 with 9 ... 19 (odd); 96^3 with 17, 19, 21, 25;
- * 128^3 with 23, 25, 27.  Another combination gives GW_EUNSUPPORTED.  The geometry keeps
+ * 48^3).  Tuned pair kernels are compiled for these (grid, K = 2 max|n_chi| + 1): 24^3 with
+ * K 5, 7, 9, 11; 48^3 with 15; 64^3 with 19; 72^3 with 9 ... 19 (odd); 96^3 with 17, 19, 21,
+ * 25; 128^3 with 23, 25, 27.  Any other grid and K <= 31 runs a generic pair kernel (run-time
+ * N and K, slower); K > 31 gives GW_EUNSUPPORTED, and so do the coefficient gradients of
+ * gw_chi0_backward on a shape without a compiled kernel.  The geometry keeps
  * its own device copies of the index tables.  Destroying a geometry also drops the graphs
  * that graph mode captured with it (gw_ctx_set_graph); a geometry may outlive its context
  * (it is then only destroyed). */
@@ -226,7 +228,8 @@ gw_status gw_chi0_build_ksum(gw_ctx* ctx, const gw_chi0_problem* probs, int nk, 
  *   grad_n_col  device, same length: dL/dn_col, the derivative with respect to the
  *               weight g(E_i) dE_i of Eq. (energyintegration) (nullable).
  *   grad_coef_v  device complex128, sum over problems of nv x npw: dL/dRe + i dL/dIm of
- *               coef_v (nullable = skip).  GW_FP64 only (GW_EUNSUPPORTED otherwise).
+ *               coef_v (nullable = skip).  GW_FP64 only, and only for (grid, K) shapes with a
+ *               compiled pair kernel (gw_geom_create; GW_EUNSUPPORTED otherwise).
  *   grad_coef_c  device complex128, sum over problems of nband x npw, per coefficient row
  *               of coef_c: the columns that use one row (col_band) add up; rows no column
  *               uses get zero (nullable = skip; GW_FP64 only).

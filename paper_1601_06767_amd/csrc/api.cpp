@@ -124,17 +124,14 @@ std::string check_sphere_order(const double* cell, const double* q, int ng, cons
 
 namespace gw {
 
+// Line split N = R S of the band and pair transforms: radix 16 from N = 64 on where 16 divides N
+// (64, 80, 96, 112, 128), else radix 8; N a multiple of 8 (the pair kernel's x2 row groups) from
+// 16 to 128 (the band transform's LDS line buffer).
 bool line_split(int nd, LineSplit* out) {
-  switch (nd) {
-    case 24: *out = {8, 3}; return true;
-    case 32: *out = {8, 4}; return true;
-    case 48: *out = {8, 6}; return true;
-    case 64: *out = {16, 4}; return true;
-    case 72: *out = {8, 9}; return true;
-    case 96: *out = {16, 6}; return true;
-    case 128: *out = {16, 8}; return true;
-    default: return false;
-  }
+  if (nd < 16 || nd > 128 || nd % 8 != 0) return false;
+  const int R = nd >= 64 && nd % 16 == 0 ? 16 : 8;
+  *out = {R, nd / R};
+  return true;
 }
 
 }  // namespace gw
@@ -239,7 +236,7 @@ gw_status gw_geom_create(gw_ctx* ctx, const int n_fft[3], const double* cell, co
   const int nd = n_fft[0];
   gw::LineSplit ls;
   if (n_fft[1] != nd || n_fft[2] != nd || !gw::line_split(nd, &ls))
-    return gw::fail(ctx, GW_EUNSUPPORTED, "FFT grid must be cubic with N in {24,32,48,64,72,96,128}");
+    return gw::fail(ctx, GW_EUNSUPPORTED, "FFT grid must be cubic with N a multiple of 8 from 16 to 128");
   int rw = 0, rc = 0;
   std::unordered_set<long long> seen;
   auto key = [nd](const int32_t* n) {
@@ -284,7 +281,8 @@ gw_status gw_geom_create(gw_ctx* ctx, const int n_fft[3], const double* cell, co
   if (!gw::pair_supported(nd, g.K))
     return gw::fail(ctx, GW_EUNSUPPORTED,
                 "no pair kernel for N = " + std::to_string(nd) + ", K = " + std::to_string(g.K) +
-                    " (dielectric sphere half-width " + std::to_string(rc) + ")");
+                    " (dielectric sphere half-width " + std::to_string(rc) + "; at most " +
+                    std::to_string((gw::kPairGenKMax - 1) / 2) + ")");
   std::vector<int32_t> wf_map((size_t)g.W * g.W * g.W, -1);
   for (int i = 0; i < npw; ++i) {
     const int32_t* n = gvec_wf + 3 * i;

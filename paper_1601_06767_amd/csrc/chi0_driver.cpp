@@ -608,6 +608,12 @@ gw_status backward_entry(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, i
   const bool want_coef = grad_coef_v || grad_coef_c;
   if (want_coef && prec != GW_FP64)
     return gw::fail(ctx, GW_EUNSUPPORTED, "coefficient gradients are computed in the float64 mode only");
+  if (want_coef)
+    for (int i = 0; i < nprob; ++i)
+      if (probs && probs[i].geom && !gw::pair_instance(probs[i].geom->g.nd, probs[i].geom->g.K))
+        return gw::fail(ctx, GW_EUNSUPPORTED,
+                        "coefficient gradients need a compiled pair-transform instance for N = " +
+                            std::to_string(probs[i].geom->g.nd) + ", K = " + std::to_string(probs[i].geom->g.K));
   DeviceScope dev(ctx->device);
   st = check_values(ctx, probs, nprob);
   if (st != GW_OK) return st;

@@ -168,8 +168,10 @@ hipError_t launch_pair_planes(const Geom& g, const void* psi_v, const void* psi_
 // Pair finish: x1 transforms, 1/N, gather to the chi sphere: m[pair][ngp] (zero padded).
 template <typename T>
 hipError_t launch_pair_finish(const Geom& g, const void* q, int npair, void* m, hipStream_t st);
-bool pair_supported(int nd, int K);
-int pair_radix(int nd, int K);   // line radix R of the (nd, K) instance (0 if none); must equal Geom::line.R
+bool pair_instance(int nd, int K);    // a compiled (N, R, K) instance exists
+bool pair_supported(int nd, int K);   // an instance, or the generic kernel (K <= kPairGenKMax, N split by line_split)
+int pair_radix(int nd, int K);   // line radix R of the (nd, K) instance, else line_split's (0 if none); must equal Geom::line.R
+constexpr int kPairGenKMax = 31;   // widest dielectric sphere (outputs per axis) of the generic pair kernel
 // (grid N, line radix R, pruned outputs K) of the compiled pair-transform instances
 #define GW_PAIR_CASES(X) \
   X(24, 8, 5)            \

@@ -713,6 +713,215 @@ __global__ __launch_bounds__(128 * TV, 1) void k_pair_planes_dl(const cx<T>* __r
   }
 }
 
+// Generic form, for grids and dielectric spheres without a compiled instance: the two-valence
+// split-line kernel with the grid N = R S and the output count K taken at run time, K <= KMAX.
+// The per-lane state is sized for KMAX and indexed by the output frequency n + (KMAX - 1) / 2,
+// |n| <= (K - 1) / 2 active, so every register index stays a compile-time constant (only the
+// twiddle table and Z are indexed at run time, in memory).  It is slower than the instances
+// (unused outputs still hold registers) and serves any grid the band transform splits.
+template <typename T, int R, int KMAX>
+__global__ __launch_bounds__(256, 1) void k_pair_planes_gen(const cx<T>* __restrict__ psi_v,
+                                                            const cx<T>* __restrict__ psi_c, int nvs, int ncs,
+                                                            int nd, int K, const cx<T>* __restrict__ twk,
+                                                            cx<T>* __restrict__ q) {
+  using V = cx<T>;
+  constexpr int TV = 2;
+  constexpr int NT = 128 * TV;
+  using L = SplitLds<T, R, KMAX, TV, false>;
+  constexpr int RMAX = (KMAX - 1) / 2;
+  constexpr int NPAIR = TV * kTC;
+  constexpr int IPL = (NPAIR * KMAX + NT - 1) / NT;
+  constexpr int CH = kTC * kRows * R;
+  constexpr int CV = TV * kRows * R;
+  constexpr int PER = 2 * (CH + CV) / NT;
+  static_assert(PER * NT == 2 * (CH + CV), "chunk elements must divide evenly");
+  const int S = nd / R;
+  const int SL = (S + 1) / 2;
+  const int SH = S - SL;
+  const int S2 = nd / kRows;
+  const int NSTEP = S2 * SL;
+  const int RCH = (K - 1) / 2;
+  const int NITEM = NPAIR * K;
+  const size_t NPL = (size_t)nd * nd;
+  __shared__ V s_c[2 * 2 * L::chunk];   // [buffer][half][row][rp]
+  __shared__ V s_v[2 * 2 * L::vchunk];
+  __shared__ V s_z[NPAIR * kRows * KMAX];
+
+  const int nbc = ncs / kTC;
+  const int nbv = nvs / TV;
+  const int pb = blockIdx.x % (nbc * nbv);
+  const int x1 = blockIdx.x / (nbc * nbv);
+  const int c0 = (pb % nbc) * kTC;
+  const int v0 = (pb / nbc) * TV;
+
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wv = wave % TV;
+  const int hf = wave / TV;
+  const int lane = tid & 63;
+  const int cl = lane / kRows;
+  const int a2 = lane % kRows;
+
+  const V* pc_base = psi_c + ((size_t)c0 * nd + x1) * NPL;
+  const V* pv_base = psi_v + ((size_t)v0 * nd + x1) * NPL;
+  unsigned voff[PER];
+  int slot[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + NT * i;
+    const int h = e / (CH + CV), e1 = e % (CH + CV);
+    const int e2 = e1 < CH ? e1 : e1 - CH;
+    const int row = e2 / R, a = e2 % R;
+    voff[i] = (unsigned)(((size_t)(row / kRows) * nd * NPL + (size_t)(row % kRows) * nd + a) * sizeof(V));
+    slot[i] = h * (e1 < CH ? (int)L::chunk : (int)L::vchunk) + row * L::rp + a;
+  }
+  V pf[PER];
+  auto fetch = [&](int st) {
+    const int g2 = st / SL, t = st % SL;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int ew = wave * 64 + NT * i;
+      const int h = ew / (CH + CV);
+      const bool isc = ew % (CH + CV) < CH;
+      const int b = h ? SL + t : t;
+      V x{T(0), T(0)};
+      if (b < S) {
+        const char* sb = (const char*)(isc ? pc_base : pv_base) + ((size_t)g2 * kRows * nd + (size_t)b * R) * sizeof(V);
+        x = *(const V*)(sb + voff[i]);
+      }
+      pf[i] = x;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int ew = wave * 64 + NT * i;
+      if (ew % (CH + CV) < CH)
+        s_c[buf * 2 * L::chunk + slot[i]] = pf[i];
+      else
+        s_v[buf * 2 * L::vchunk + slot[i]] = pf[i];
+    }
+  };
+
+  V qacc[IPL][KMAX];
+#pragma unroll
+  for (int r = 0; r < IPL; ++r)
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) qacc[r][j] = V{T(0), T(0)};
+
+  fetch(0);
+  stash(0);
+  __syncthreads();
+
+  for (int b2 = 0; b2 < S2; ++b2) {
+    V acc[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) acc[j] = V{T(0), T(0)};
+#pragma unroll 1
+    for (int t = 0; t < SL; ++t) {
+      const int st = b2 * SL + t;
+      if (st + 1 < NSTEP) fetch(st + 1);
+      const int b = hf ? SL + t : t;
+      const int buf = st & 1;
+      if (hf == 0 || t < SH) {
+        const V* rc = s_c + (buf * 2 + hf) * L::chunk + (cl * kRows + a2) * L::rp;
+        const V* rv = s_v + (buf * 2 + hf) * L::vchunk + (wv * kRows + a2) * L::rp;
+        V x[R];
+#pragma unroll
+        for (int a = 0; a < R; ++a) x[a] = cmulc(rv[a], rc[a]);
+        dft<R>(x);
+#pragma unroll
+        for (int n = -RMAX; n <= RMAX; ++n)
+          if (n >= -RCH && n <= RCH) cmac(acc[n + RMAX], twk[b * K + n + RCH], x[((n % R) + R) % R]);
+      }
+      if (st + 1 < NSTEP) stash((st + 1) & 1);
+      __syncthreads();
+    }
+    V* z = s_z + ((wv * kTC + cl) * kRows + a2) * K;
+    if (hf == 1) {
+#pragma unroll
+      for (int n = -RMAX; n <= RMAX; ++n)
+        if (n >= -RCH && n <= RCH) z[n + RCH] = acc[n + RMAX];
+    }
+    __syncthreads();
+    if (hf == 0) {
+#pragma unroll
+      for (int n = -RMAX; n <= RMAX; ++n)
+        if (n >= -RCH && n <= RCH) z[n + RCH] = cadd(z[n + RCH], acc[n + RMAX]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < IPL; ++r) {
+      const int it = tid + NT * r;
+      if (it < NITEM) {
+        const int pair = it / K, j3 = it % K;
+        V y[kRows];
+#pragma unroll
+        for (int a = 0; a < kRows; ++a) y[a] = s_z[(pair * kRows + a) * K + j3];
+        dft<kRows>(y);
+#pragma unroll
+        for (int n = -RMAX; n <= RMAX; ++n)
+          if (n >= -RCH && n <= RCH)
+            cmac(qacc[r][n + RMAX], twk[b2 * K + n + RCH], y[((n % kRows) + kRows) % kRows]);
+      }
+    }
+    // s_z is rewritten only after the SL barriers of the next group's stage 1
+  }
+  const int p1 = (x1 % S) * R + x1 / S;
+#pragma unroll
+  for (int r = 0; r < IPL; ++r) {
+    const int it = tid + NT * r;
+    if (it < NITEM) {
+      const int pair = it / K, j3 = it % K;
+      const int pv = pair / kTC, pc = pair % kTC;
+      const size_t pg = (size_t)(v0 + pv) * ncs + (c0 + pc);
+      V* dst = q + (pg * nd + p1) * ((size_t)K * K) + j3;
+#pragma unroll
+      for (int n = -RMAX; n <= RMAX; ++n)
+        if (n >= -RCH && n <= RCH) dst[(size_t)(n + RCH) * K] = qacc[r][n + RMAX];
+    }
+  }
+}
+
+// Generic finish (runtime N and K <= KMAX, outputs indexed by frequency as above).
+template <typename T, int R, int KMAX>
+__global__ __launch_bounds__(256) void k_pair_finish_gen(const cx<T>* __restrict__ q,
+                                                         const int32_t* __restrict__ chi_map, int ng, int ngp,
+                                                         int nd, int K, T scale, const cx<T>* __restrict__ twk,
+                                                         cx<T>* __restrict__ m) {
+  using V = cx<T>;
+  constexpr int RMAX = (KMAX - 1) / 2;
+  const int S = nd / R;
+  const int RCH = (K - 1) / 2;
+  const int KK = K * K;
+  const size_t pair = blockIdx.x;
+  const V* src = q + pair * nd * (size_t)KK;
+  V* dst = m + pair * ngp;
+  for (int l = threadIdx.x; l < KK; l += blockDim.x) {
+    V acc[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) acc[j] = V{T(0), T(0)};
+#pragma unroll 1
+    for (int b = 0; b < S; ++b) {
+      V x[R];
+#pragma unroll
+      for (int a = 0; a < R; ++a) x[a] = src[(size_t)(b * R + a) * KK + l];
+      dft<R>(x);
+#pragma unroll
+      for (int n = -RMAX; n <= RMAX; ++n)
+        if (n >= -RCH && n <= RCH) cmac(acc[n + RMAX], twk[b * K + n + RCH], x[((n % R) + R) % R]);
+    }
+#pragma unroll
+    for (int n = -RMAX; n <= RMAX; ++n) {
+      if (n >= -RCH && n <= RCH) {
+        const int ig = chi_map[(n + RCH) * KK + l];
+        if (ig >= 0) dst[ig] = V{acc[n + RMAX].x * scale, acc[n + RMAX].y * scale};
+      }
+    }
+  }
+  for (int i = ng + threadIdx.x; i < ngp; i += blockDim.x) dst[i] = V{T(0), T(0)};
+}
+
 template <typename T, int ND, int R, int K>
 __global__ __launch_bounds__(256) void k_pair_finish(const cx<T>* __restrict__ q, const int32_t* __restrict__ chi_map,
                                                      int ng, int ngp, T scale, const cx<T>* __restrict__ twk,
@@ -822,7 +1031,7 @@ hipError_t run_finish(const Geom& g, const void* q, int npair, void* m, hipStrea
 
 }  // namespace
 
-bool pair_supported(int nd, int K) {
+bool pair_instance(int nd, int K) {
 #define X(nd_, r_, k_) \
   if (nd == nd_ && K == k_) return true;
   GW_PAIR_CASES(X)
@@ -830,13 +1039,48 @@ bool pair_supported(int nd, int K) {
   return false;
 }
 
+bool pair_supported(int nd, int K) {
+  LineSplit ls;
+  return pair_instance(nd, K) || (K >= 1 && K <= kPairGenKMax && K % 2 == 1 && line_split(nd, &ls));
+}
+
 int pair_radix(int nd, int K) {
 #define X(nd_, r_, k_) \
   if (nd == nd_ && K == k_) return r_;
   GW_PAIR_CASES(X)
 #undef X
-  return 0;
+  LineSplit ls;
+  return line_split(nd, &ls) ? ls.R : 0;
 }
+
+namespace {
+template <typename T, int R>
+hipError_t run_planes_gen(const Geom& g, const void* psi_v, const void* psi_c, int nvs, int ncs, void* q,
+                          hipStream_t st) {
+  const cx<T>* tw = std::is_same<T, double>::value ? (const cx<T>*)g.d_twk64 : (const cx<T>*)g.d_twk32;
+  const int nblk = g.nd * (nvs / 2) * (ncs / kTC);
+  if (g.K <= 15)
+    k_pair_planes_gen<T, R, 15><<<nblk, 256, 0, st>>>((const cx<T>*)psi_v, (const cx<T>*)psi_c, nvs, ncs, g.nd, g.K,
+                                                      tw, (cx<T>*)q);
+  else
+    k_pair_planes_gen<T, R, kPairGenKMax><<<nblk, 256, 0, st>>>((const cx<T>*)psi_v, (const cx<T>*)psi_c, nvs, ncs,
+                                                                g.nd, g.K, tw, (cx<T>*)q);
+  return hipGetLastError();
+}
+
+template <typename T, int R>
+hipError_t run_finish_gen(const Geom& g, const void* q, int npair, void* m, hipStream_t st) {
+  const cx<T>* tw = std::is_same<T, double>::value ? (const cx<T>*)g.d_twk64 : (const cx<T>*)g.d_twk32;
+  const T scale = T(1.0 / ((double)g.nd * g.nd * g.nd));
+  if (g.K <= 15)
+    k_pair_finish_gen<T, R, 15><<<npair, 256, 0, st>>>((const cx<T>*)q, g.d_chi_map, g.ng, g.ngp, g.nd, g.K, scale,
+                                                       tw, (cx<T>*)m);
+  else
+    k_pair_finish_gen<T, R, kPairGenKMax><<<npair, 256, 0, st>>>((const cx<T>*)q, g.d_chi_map, g.ng, g.ngp, g.nd,
+                                                                 g.K, scale, tw, (cx<T>*)m);
+  return hipGetLastError();
+}
+}  // namespace
 
 template <typename T>
 hipError_t launch_pair_planes(const Geom& g, const void* psi_v, const void* psi_c, int nvs, int ncs, void* q, int minb,
@@ -845,6 +1089,10 @@ hipError_t launch_pair_planes(const Geom& g, const void* psi_v, const void* psi_
   if (g.nd == nd_ && g.K == k_) return run_planes<T, nd_, r_, k_>(g, psi_v, psi_c, nvs, ncs, q, minb, st);
   GW_PAIR_CASES(X)
 #undef X
+  // no compiled instance: the generic kernel (the geometry admitted only shapes it serves)
+  if (g.K > kPairGenKMax || nvs % 2 != 0) return hipErrorInvalidValue;
+  if (g.line.R == 8) return run_planes_gen<T, 8>(g, psi_v, psi_c, nvs, ncs, q, st);
+  if (g.line.R == 16) return run_planes_gen<T, 16>(g, psi_v, psi_c, nvs, ncs, q, st);
   return hipErrorInvalidValue;
 }
 
@@ -854,6 +1102,9 @@ hipError_t launch_pair_finish(const Geom& g, const void* q, int npair, void* m, 
   if (g.nd == nd_ && g.K == k_) return run_finish<T, nd_, r_, k_>(g, q, npair, m, st);
   GW_PAIR_CASES(X)
 #undef X
+  if (g.K > kPairGenKMax) return hipErrorInvalidValue;
+  if (g.line.R == 8) return run_finish_gen<T, 8>(g, q, npair, m, st);
+  if (g.line.R == 16) return run_finish_gen<T, 16>(g, q, npair, m, st);
   return hipErrorInvalidValue;
 }
 

@@ -254,3 +254,29 @@ def test_values_and_spheres_are_checked(g):
         p.gw_geom_create(g.ctx, (24,) * 3, case.gw, case.gc, case.cfg.cell, (0.5, 0.0, 0.0))
     geom = p.gw_geom_create(g.ctx, (24,) * 3, case.gw, swapped)     # no cell and q: not checked
     p.gw_geom_destroy(geom)
+
+
+# Grids and dielectric spheres without a compiled pair-transform instance run the generic
+# kernel (run-time N and K): N = 40 and 56 split 8 x 5 and 8 x 7 (odd S: the second half of
+# each line has one chunk fewer), 48 with K = 17 (the instance there is K = 15), 80 = 16 x 5.
+@pytest.mark.parametrize("nd,ng", [(40, 500), (56, 1500), (48, 2600), (80, 3000)],
+                         ids=["40cube-K11", "56cube-K15", "48cube-K17", "80cube-K19"])
+def test_generic_pair_kernel_shapes_match_oracle(g, nd, ng):
+    cfg = synth.config(1)
+    gw = synth.wf_sphere(nd)
+    gc = synth.chi_sphere(ng, cfg.qs[0], cfg.cell)
+    assert 2 * int(np.abs(gw).max()) + int(np.abs(gc).max()) < nd
+    b = synth.make_bands(cfg, v_index=np.arange(4), c_index=np.arange(13), gvec_wf=gw)
+    case = Case(cfg, nd, gw, gc, b.coef_v, b.e_v, b.coef_c, b.e_c, q=tuple(cfg.qs[0]))
+    ref = ref_chi0(case)[0]
+    for prec, tol in (("fp64", 1e-10), ("fp32", 2e-5), ("bf16x3", 1e-4)):
+        chi = g.chi0(case, prec=prec)[0]
+        fro, mx = rel_err(chi, ref)
+        print(f"N = {nd}, NG = {ng}, {prec}: {fro:.2e} / {mx:.2e}")
+        assert fro <= tol and mx <= tol, (prec, fro, mx)
+    # the coefficient gradients need a compiled instance: refused, not approximated
+    p = g.p
+    gb = g.torch.zeros((1, len(gc), len(gc)), dtype=g.torch.complex128, device=g.dev)
+    with pytest.raises(p.GwError) as e:
+        p.gw_chi0_backward(g.ctx, [g.problem(case)], [0.0], 0.0, p.GW_FP64, gb, coef=(True, False))
+    assert e.value.status == p.GW_EUNSUPPORTED
