@@ -257,7 +257,7 @@ def run_headline(args, torch, synth, p, dev):
     cpu = None
     nvs, ncs = (int(x) for x in args.cpu_pairs.split("x"))
     want_cpu = args.cpu_sample > 0 and nvs > 0 and ncs > 0
-    if want_cpu and not within_budget(args, 20, "oracle sample"):
+    if want_cpu and not within_budget(args, 45, "oracle sample"):
         skipped["cpu_baseline"] = "time budget"
         want_cpu = False
     if want_cpu:
@@ -447,7 +447,7 @@ def main():
                          "valence rows and columns (one chunk: NV x NCOL <= 32768 pairs), and the adjoint "
                          "instead of the build")
     ap.add_argument("--reps", type=int, default=1, help="chunk workload: calls")
-    ap.add_argument("--cpu-pairs", default="2x40",
+    ap.add_argument("--cpu-pairs", default="8x160",
                     help="headline workload: oracle sample, valence x columns of the full-size workload")
     args = ap.parse_args()
     if args.gpus != 1:
