@@ -248,7 +248,7 @@ def run_headline(args, torch, synth, p, dev):
         traffic = traffic_for([f"{x}{v}<{fp}, {nd}, " for x in kern for v in ("", "_split", "_dl")],
                               "pair_transform.hip" if dom in ("planes", "finish") else "band_fft.hip")
         basis = ("256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz: the float64 vector rate, and the float32 "
-                 "rate without packed instructions, which this build does not use")
+                 "rate without packed instructions, which the library is compiled without")
     achieved = work / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": traffic, "avg_launch_ms": avg_ms,
@@ -451,7 +451,7 @@ def main():
                     help="headline workload: oracle sample, valence x columns of the full-size workload")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the band sum shards over "
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 (the band sum shards over "
                                    "pairs, see the design notes)"}))
         sys.exit(2)
 
