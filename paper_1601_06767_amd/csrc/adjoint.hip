@@ -210,10 +210,12 @@ __global__ void k_split_m(const float2* __restrict__ m, int npair, int ng, int n
 }
 
 // Both operands are staged straight from their split images into LDS by 16-byte direct loads
-// (one wave instruction fills 64 consecutive 16-byte LDS units) into two buffers, so the
-// staging takes no registers and no LDS store pass.  The buffers are separate arrays and the
-// stage loop is unrolled by two, so that the compiler sees that a stage's LDS reads cannot
-// alias the direct loads in flight into the other buffer and does not wait for them.  LDS units of one stage: the 128 M rows
+// (one wave instruction fills 64 consecutive 16-byte LDS units), two stages ahead, into three
+// buffers, so the staging takes no registers and no LDS store pass.  The buffers are separate
+// arrays and the stage loop is unrolled by three, so that the compiler sees that a stage's LDS
+// reads cannot alias the direct loads in flight into the other buffers and does not wait for
+// them; the stage barrier orders LDS only (lds_barrier), so the loads of the next stage stay in
+// flight across it, and each stage waits for its own loads explicitly.  LDS units of one stage: the 128 M rows
 // of 8 pieces (piece c of row r at unit 8 r + (c ^ (r & 7))), then the 128 chibar rows of 12
 // (piece p of row r at UM + 12 r + (p ^ 2 ((r >> 2) & 1))); the XORs give every MFMA fragment
 // read of 16 rows x 4 pieces four accesses per bank group, the minimum.  Rows past npair or
@@ -221,9 +223,7 @@ __global__ void k_split_m(const float2* __restrict__ m, int npair, int ng, int n
 // One workgroup per CU.  Measured with register staging (the former form), per 32k-pair
 // launch at NG 2000: 5.4 ms converting chibar in every tile, 4.2 ms with it pre-split;
 // capped at 128 registers for a second workgroup it spilled (9.4 ms); stages of 32 G' were
-// no faster (5.6 ms).  A third buffer (loads two stages ahead) gains nothing as written: the
-// compiler counts the direct loads as pending LDS writes and waits for all of them at every
-// workgroup barrier, even one fenced for LDS only.
+// no faster (5.6 ms).
 constexpr int UM = BT * 8, UG = BT * 12, UST = UM + UG;   // 16-byte LDS units per stage
 constexpr int UPL = UST / 512;                            // units per lane per stage
 static_assert(UPL * 512 == UST && UM % 64 == 0, "stage units must split into whole wave instructions");
@@ -233,6 +233,7 @@ __global__ __launch_bounds__(512) void k_adjoint_bf16x3(const float2* __restrict
                                                            double2* __restrict__ part) {
   __shared__ __align__(16) uint4 sa[UST];
   __shared__ __align__(16) uint4 sb[UST];
+  __shared__ __align__(16) uint4 sc[UST];
   __shared__ double2 sred[4][BT];
   const int ntg = ngp / BT;
   const int p0 = (blockIdx.x / ntg) * BT;
@@ -281,11 +282,13 @@ __global__ __launch_bounds__(512) void k_adjoint_bf16x3(const float2* __restrict
   const int pre = lg < 2 ? lg : 2 + lg;
   const int pim = lg < 2 ? 2 + lg : lg - 2;
   auto stage = [&](int kb, const uint4* cur, uint4* next) {
-    // this wave's direct loads of stage kb have landed; the barrier makes everyone's visible
-    // and ends every wave's reads of the buffer that the next issue overwrites
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (kb + 1 < nkb) issue(kb + 1, next);
+    // this wave's direct loads of stage kb have landed (only stage kb + 1's, issued after them,
+    // may still be in flight); the barrier makes everyone's visible and ends every wave's reads
+    // of the buffer that the next issue overwrites (stage kb - 1's).  Every stage issues (past
+    // the end: the last stage again, into a buffer not read), so the wait count is a constant.
+    wait_vm<UPL>();
+    lds_barrier();
+    issue(min(kb + 2, nkb - 1), next);
     const uint4* sm = cur;
     const uint4* sg = cur + UM;
     bf16x8 xh[BMI], xl[BMI], reh[BNJ], rel[BNJ], imh[BNJ], iml[BNJ];
@@ -317,10 +320,13 @@ __global__ __launch_bounds__(512) void k_adjoint_bf16x3(const float2* __restrict
       }
   };
   issue(0, sa);
-  for (int kb = 0; kb < nkb; kb += 2) {
-    stage(kb, sa, sb);
+  issue(min(1, nkb - 1), sb);
+  for (int kb = 0; kb < nkb; kb += 3) {
+    stage(kb, sa, sc);
     if (kb + 1 < nkb) stage(kb + 1, sb, sa);
+    if (kb + 2 < nkb) stage(kb + 2, sc, sb);
   }
+  wait_vm<0>();   // no direct load may still be writing LDS when the epilogue's barrier passes
   // epilogue: per pair row, sum over this tile's G of conj(M[p][G]) Y[p][G]; result rows of
   // the bf16 16x16x32 MFMA are 4 (lane / 16) + r, columns lane % 16
   // (one block row i at a time, to keep few registers live beside the accumulators)

@@ -131,6 +131,26 @@ template <int R, typename V> __device__ __forceinline__ void dft(V* x) {
   }
 }
 
+// ---------------------------------------------------------------- direct-load pipelines
+// s_waitcnt with vmcnt = n (0..63) and no wait on the other counters
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// Workgroup barrier for LDS data only: this wave's LDS operations complete (lgkmcnt 0), then
+// all waves meet; the empty asm statements keep the compiler from moving memory accesses
+// across it.  Unlike __syncthreads (whose fence also covers the LDS writes of direct loads,
+// hence waits for every one in flight) it leaves the direct loads of later steps in flight;
+// the wait for a step's own direct loads is explicit (wait_vm).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4));   // lgkmcnt(0); vmcnt, expcnt not waited
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // Wrap n into [0, m).
 __host__ __device__ __forceinline__ int wrap(int n, int m) {
   int r = n % m;

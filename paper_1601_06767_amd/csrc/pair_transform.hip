@@ -262,26 +262,8 @@ constexpr int dl4_nbuf() {
 // first unit of block qb of a step buffer
 __device__ __forceinline__ int dl_block(int qb) { return (qb >> 1) * 136 + (qb & 1) * 72; }
 
-// s_waitcnt with vmcnt = n (0..63) and no wait on the other counters
-template <int N>
-__device__ __forceinline__ void wait_vm() {
-  static_assert(N >= 0 && N < 64, "vmcnt");
-  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
-}
-
 constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
 
-// Workgroup barrier for LDS data only: this wave's LDS operations complete (lgkmcnt 0), then
-// all waves meet; the empty asm statements keep the compiler from moving memory accesses
-// across it.  Unlike __syncthreads (whose fence also covers the LDS writes of direct loads,
-// hence waits for every one in flight) it leaves the direct loads of later steps in flight;
-// the wait for a step's own direct loads is explicit (wait_vm).
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4));   // lgkmcnt(0); vmcnt, expcnt not waited
-  asm volatile("" ::: "memory");
-  __builtin_amdgcn_s_barrier();
-  asm volatile("" ::: "memory");
-}
 
 // Automatic form (measured per 32k-pair launch on one MI355X).  float64: the lean
 // two-valence kernel where it is built (72^3 K 17: 19.9 against 34.3 ms for the plain
