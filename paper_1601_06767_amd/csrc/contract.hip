@@ -445,37 +445,43 @@ __device__ void tile_bf16x3(const void* __restrict__ mv, const double* __restric
 // into bf16 row images (k_split_ab): per block of 16 pairs kb and row G,
 //   A[kb][G] = [hi re(16) | hi im(16) | lo re(16) | lo im(16)] of M      (8 units of 16 bytes)
 //   B[kb][G] = [hi br | hi bi | hi -bi | lo br | lo bi | lo -bi] of b = w M  (12 units)
-// and the tile stages both straight into LDS by 16-byte direct loads (global_load_lds_dwordx4)
-// into two buffers, as the split-bf16 adjoint does: no staging registers, no conversion and
-// one barrier per 16-pair stage.  LDS units of a stage: the 128 A rows of 8 (unit c of row r
+// and the tile stages both straight into LDS by 16-byte direct loads (global_load_lds_dwordx4),
+// as the split-bf16 adjoint does: no staging registers, no conversion and one barrier per
+// 16-pair stage.  LDS units of a stage: the 128 A rows of 8 (unit c of row r
 // at 8 r + (c ^ (r & 7))), then the 128 B rows of 12 (unit p at UA + 12 r + (p ^ 2 ((r >> 2) & 1)));
 // the XORs spread the 16 rows x 4 units of a fragment read over the bank groups.
 constexpr int IMT = 128;                       // tile
 constexpr int IUA = IMT * 8, IUB = IMT * 12;   // A and B units of a stage
 constexpr int IUS = IUA + IUB;
-constexpr int INT = 256;                       // threads: 4 waves, each 64 x 64 outputs
+// 8 waves (each 64 x 32 outputs), one workgroup per CU, and loads two stages ahead through
+// three LDS buffers: the stage barrier orders LDS only (lds_barrier) and each stage waits for
+// its own direct loads, so the next stages' loads stay in flight across it.  Every stage
+// issues (past the range end: its last stage again, into a buffer not read), so the wait count
+// is one constant.  Measured per chunk against four waves of 64 x 64 outputs, two workgroups
+// per CU and two buffers: 19.5 against 20.1 ms at NG 8000 (32k pairs), 1.69 against 1.98 ms
+// at NG 2000.
+constexpr int INT = 512;
 constexpr int IUPL = IUS / INT;                // units per lane per stage
 static_assert(IUPL * INT == IUS && IUA % 64 == 0, "stage units must split into whole wave instructions");
 
 __device__ void tile_bf16x3_img(const uint4* __restrict__ aimg, const uint4* __restrict__ bimg, int nk, int ngp,
-                                int ksplit, double2* __restrict__ acc, int t, int ks, uint4* sa, uint4* sb) {
-  constexpr int MI = 4, NJ = 4;
+                                 int ksplit, double2* __restrict__ acc, int t, int ks, uint4* sa, uint4* sb,
+                                 uint4* sc) {
+  constexpr int MI = 4, NJ = 2;
   int ti, tj;
   tile_coords_blocked(t, ngp / IMT, &ti, &tj);
   const int g0 = ti * IMT, h0 = tj * IMT;
   const int per = range_len(nk, ksplit);
   const int kb0 = ks * per / 16;
-  const int kb1 = min(nk, ks * per + per) / 16;   // nk and per are multiples of 16
+  const int kb1 = min(nk, ks * per + per) / 16;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave >> 2, wc = wave & 3;
   const int li = lane & 15, lg = lane >> 4;
-  // this lane's source unit of LDS unit 64 (4 i + wave) + lane at block 0 (block kb adds 8 ngp or
-  // 12 ngp units; the operand of a block of 64 units is wave-uniform)
   unsigned off[IUPL];
 #pragma unroll
   for (int i = 0; i < IUPL; ++i) {
-    const int ub = 4 * i + wave;
+    const int ub = 8 * i + wave;
     const int u = 64 * ub + lane;
     if (ub * 64 < IUA) {
       const int r = u / 8, c = (u % 8) ^ (r & 7);
@@ -490,7 +496,7 @@ __device__ void tile_bf16x3_img(const uint4* __restrict__ aimg, const uint4* __r
     const uint4* bbase = bimg + (size_t)kb * ngp * 12;
 #pragma unroll
     for (int i = 0; i < IUPL; ++i) {
-      const int ub = 4 * i + wave;
+      const int ub = 8 * i + wave;
       const uint4* src = (ub * 64 < IUA ? ab : bbase) + off[i];
       __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)&buf[64 * ub], 16,
                                        0, 0);
@@ -504,16 +510,12 @@ __device__ void tile_bf16x3_img(const uint4* __restrict__ aimg, const uint4* __r
       cre[i][j] = f32x4{0, 0, 0, 0};
       cim[i][j] = f32x4{0, 0, 0, 0};
     }
-  // units of the two products' right operands: Re C takes [br | bi] (units 0..3), Im C takes
-  // [-bi | br] (units 4, 5, 0, 1); the lo copies are 6 units further
   const int pre = lg;
   const int pim = lg < 2 ? 4 + lg : lg - 2;
   auto stage = [&](int kb, const uint4* cur, uint4* next) {
-    // this wave's direct loads of block kb have landed; the barrier makes everyone's visible
-    // and ends every wave's reads of the buffer that the next issue overwrites
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (kb + 1 < kb1) issue(kb + 1, next);
+    wait_vm<IUPL>();
+    lds_barrier();
+    issue(min(kb + 2, kb1 - 1), next);
     const uint4* sm = cur;
     const uint4* sg = cur + IUA;
     bf16x8 xh[MI], xl[MI];
@@ -545,20 +547,29 @@ __device__ void tile_bf16x3_img(const uint4* __restrict__ aimg, const uint4* __r
   // The diagonal G = G' sums w |M(G)|^2 terms of one sign, so float32 accumulation there errs
   // in proportion to the number of pairs (one 32k-pair range: 7.6e-6 of max |chi| against
   // 1.5e-7 off the diagonal); diagonal tiles add their sum into the float64 output every
-  // kFlush stages (1024 pairs) and start again from zero.
-  constexpr int kFlush = 64;
+  // kFlush stages (1056 pairs) and start again from zero.  Segments are whole multiples of
+  // three stages, so that each starts on buffer sa; the loop runs whole triples and the
+  // remainder after it (with the second and third stages conditional, the compiler's wait
+  // tracking would merge paths on which another buffer's loads are the newest and wait for
+  // every load before the LDS reads).
+  constexpr int kFlush = 66;
   double2* out = acc + (size_t)ks * ngp * ngp;
-  // segments of an even number of stages, so that each starts on buffer sa; the next stage's
-  // loads are issued across a segment's end
-  const int seg = ti == tj ? kFlush : (kb1 - kb0 + 1) / 2 * 2;
-  if (kb0 < kb1) issue(kb0, sa);
+  const int seg = ti == tj ? kFlush : (kb1 - kb0 + 2) / 3 * 3;
+  if (kb0 < kb1) {
+    issue(kb0, sa);
+    issue(min(kb0 + 1, kb1 - 1), sb);
+  }
   int s0 = kb0;
   do {
     const int s1 = min(kb1, s0 + seg);
-    for (int kb = s0; kb < s1; kb += 2) {
-      stage(kb, sa, sb);
-      if (kb + 1 < s1) stage(kb + 1, sb, sa);
+    int kb = s0;
+    for (; kb + 3 <= s1; kb += 3) {
+      stage(kb, sa, sc);
+      stage(kb + 1, sb, sa);
+      stage(kb + 2, sc, sb);
     }
+    if (kb < s1) stage(kb, sa, sc);
+    if (kb + 1 < s1) stage(kb + 1, sb, sa);
     store_tile<MI, NJ>(out, ngp, g0 + 16 * MI * wr, h0 + 16 * NJ * wc, cre, cim, li, lg, false);
 #pragma unroll
     for (int i = 0; i < MI; ++i)
@@ -569,17 +580,18 @@ __device__ void tile_bf16x3_img(const uint4* __restrict__ aimg, const uint4* __r
       }
     s0 = s1;
   } while (s0 < kb1);
+  wait_vm<0>();   // no direct load may still be writing LDS when the next item starts
 }
 
-// Static schedule over the batch's items (no item counter, so that two workgroups of 80 KB of
-// LDS share a CU).  Workgroups are dealt to the 8 XCDs round robin (workgroup b to XCD b mod 8),
-// so each pass over a grid's worth of items gives XCD x the contiguous run of items
-// [x grid / 8, (x + 1) grid / 8): with the blocked tile order, one compact group of tiles per
-// L2.  The grid is a multiple of 8.  The barrier at the top of each item ends every wave's
-// reads of the buffers before the next item's first loads.
-__global__ __launch_bounds__(INT, 2) void k_contract_img(ContractBatch bt) {
+// Static schedule over the batch's items (no item counter).  Workgroups are dealt to the 8 XCDs
+// round robin (workgroup b to XCD b mod 8), so each pass over a grid's worth of items gives
+// XCD x the contiguous run of items [x grid / 8, (x + 1) grid / 8): with the blocked tile
+// order, one compact group of tiles per L2.  The grid is a multiple of 8.  The barrier at the
+// top of each item ends every wave's reads of the buffers before the next item's first loads.
+__global__ __launch_bounds__(INT, 1) void k_contract_img(ContractBatch bt) {
   __shared__ __align__(16) uint4 sa[IUS];
   __shared__ __align__(16) uint4 sb[IUS];
+  __shared__ __align__(16) uint4 sc[IUS];
   const long long n = bt.item0[bt.nprob];
   const int per_xcd = gridDim.x / 8;
   const int slot = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
@@ -595,7 +607,7 @@ __global__ __launch_bounds__(INT, 2) void k_contract_img(ContractBatch bt) {
     const int rem = (int)(local % per_job);
     double2* acc = p.acc + (size_t)job * p.ksplit * p.ngp * p.ngp;
     tile_bf16x3_img((const uint4*)p.aimg, (const uint4*)p.bimg, p.nk, p.ngp, p.ksplit, acc, rem % p.ntl,
-                    rem / p.ntl, sa, sb);
+                    rem / p.ntl, sa, sb, sc);
   }
 }
 
@@ -778,8 +790,8 @@ hipError_t launch_contract_batch(int mode, const ContractBatch& bt, int* counter
       if (!bt.p[b].aimg || !bt.p[b].bimg || bt.p[b].nk % 16 != 0) return hipErrorInvalidValue;
     (void)counter;
     long long items = bt.item0[bt.nprob];
-    const int g2 = (int)std::min<long long>((items + 7) / 8 * 8, 2LL * 256);
-    k_contract_img<<<std::max(g2, 8), INT, 0, st>>>(bt);
+    const int g1 = (int)std::min<long long>((items + 7) / 8 * 8, 256LL);
+    k_contract_img<<<std::max(g1, 8), INT, 0, st>>>(bt);
   } else if (mode == 0)
     k_contract_batch<0, 64><<<grid, 64 * TileGeo<64>::NW, 0, st>>>(bt, counter);
   else if (mode == 1)

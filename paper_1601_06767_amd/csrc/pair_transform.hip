@@ -291,7 +291,15 @@ constexpr int auto_variant() {
   return planes_min_blocks<T, R, K>();
 }
 
-template <typename T, int ND, int R, int K, int TV, bool LEAN = false>
+// Two register sets for the staged rows (PF2, loads two steps ahead of their use) where that
+// was measured faster per 32k-pair launch: the 128^3 grid (float64 two-valence K 25: 78.6
+// against 88.1 ms per 16k pairs; float32 four-valence K 25: 62.1 against 74.0 ms).  On 72^3 it
+// gains nothing (float64 K 15: 17.3 against 17.4 ms) or loses (float32 four-valence K 15: 12.6
+// against 9.0 ms), and on 96^3 float64 it spills (91 against 68 ms).
+template <int ND>
+constexpr bool kSplitPf2 = ND == 128;
+
+template <typename T, int ND, int R, int K, int TV, bool LEAN = false, bool PF2 = false>
 __global__ __launch_bounds__(128 * TV, LEAN ? 2 : 1) void k_pair_planes_split(const cx<T>* __restrict__ psi_v,
                                                                          const cx<T>* __restrict__ psi_c, int nvs,
                                                                          int ncs, const cx<T>* __restrict__ twk,
@@ -354,8 +362,7 @@ __global__ __launch_bounds__(128 * TV, LEAN ? 2 : 1) void k_pair_planes_split(co
     voff[i] = (unsigned)(((size_t)(row / kRows) * ND * NPL + (size_t)(row % kRows) * ND + a) * sizeof(V));
     slot[i] = h * (e1 < CH ? (int)L::chunk : (int)L::vchunk) + row * L::rp + a;
   }
-  V pf[PER];
-  auto fetch = [&](int st) {
+  auto fetch = [&](int st, V (&pf)[PER]) {
     const int g2 = st / SL, t = st % SL;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
@@ -371,7 +378,7 @@ __global__ __launch_bounds__(128 * TV, LEAN ? 2 : 1) void k_pair_planes_split(co
       pf[i] = x;
     }
   };
-  auto stash = [&](int buf) {
+  auto stash = [&](int buf, const V (&pf)[PER]) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int ew = wave * 64 + NT * i;
@@ -392,45 +399,27 @@ __global__ __launch_bounds__(128 * TV, LEAN ? 2 : 1) void k_pair_planes_split(co
     for (int j = 0; j < K; ++j) s_q[tid * K + j] = V{T(0), T(0)};
   }
 
-  fetch(0);
-  stash(0);
-  __syncthreads();
-
-  for (int b2 = 0; b2 < S2; ++b2) {
-    V acc[K];
+  // stage 1 of one chunk step: products, R-point DFT and the twiddled sum into acc
+  auto step1 = [&](int st, int t, V (&acc)[K]) {
+    const int b = hf ? SL + t : t;
+    const int buf = LEAN ? 0 : (st & 1);
+    if (hf == 0 || t < SH) {
+      const V* rc = s_c + (buf * 2 + hf) * L::chunk + (cl * kRows + a2) * L::rp;
+      const V* rv = s_v + (buf * 2 + hf) * L::vchunk + (wv * kRows + a2) * L::rp;
+      V x[R];
 #pragma unroll
-    for (int j = 0; j < K; ++j) acc[j] = V{T(0), T(0)};
-#pragma unroll 1
-    for (int t = 0; t < SL; ++t) {
-      const int st = b2 * SL + t;
-      if (st + 1 < NSTEP) fetch(st + 1);
-      const int b = hf ? SL + t : t;
-      const int buf = LEAN ? 0 : (st & 1);
-      if (hf == 0 || t < SH) {
-        const V* rc = s_c + (buf * 2 + hf) * L::chunk + (cl * kRows + a2) * L::rp;
-        const V* rv = s_v + (buf * 2 + hf) * L::vchunk + (wv * kRows + a2) * L::rp;
-        V x[R];
+      for (int a = 0; a < R; ++a) x[a] = cmulc(rv[a], rc[a]);
+      dft<R>(x);
 #pragma unroll
-        for (int a = 0; a < R; ++a) x[a] = cmulc(rv[a], rc[a]);
-        dft<R>(x);
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const int n = j - RCH;
-          const V tv = twk[b * K + j];
-          cmac(acc[j], tv, x[((n % R) + R) % R]);
-        }
+      for (int j = 0; j < K; ++j) {
+        const int n = j - RCH;
+        const V tv = twk[b * K + j];
+        cmac(acc[j], tv, x[((n % R) + R) % R]);
       }
-      if (LEAN) {
-        // one buffer: every wave is done with it before the next chunk overwrites it
-        if (st + 1 < NSTEP) {
-          __syncthreads();
-          stash(0);
-        }
-      } else if (st + 1 < NSTEP) {
-        stash((st + 1) & 1);
-      }
-      __syncthreads();
     }
+  };
+  // end of an x2 group: the two halves' Z added in LDS, then stage 2 of the group
+  auto group_end = [&](int b2, const V (&acc)[K]) {
     V* z = s_z + ((wv * kTC + cl) * kRows + a2) * K;
     if (hf == 1) {
 #pragma unroll
@@ -477,6 +466,74 @@ __global__ __launch_bounds__(128 * TV, LEAN ? 2 : 1) void k_pair_planes_split(co
       }
     }
     // s_z is rewritten only after the SL barriers of the next group's stage 1
+  };
+
+  if constexpr (LEAN || !PF2) {
+    // one register set: the rows of the next step are loaded at the start of a step and
+    // stored to LDS at its end (lean form: one LDS buffer, so after a barrier)
+    V pf[PER];
+    fetch(0, pf);
+    stash(0, pf);
+    __syncthreads();
+    for (int b2 = 0; b2 < S2; ++b2) {
+      V acc[K];
+#pragma unroll
+      for (int j = 0; j < K; ++j) acc[j] = V{T(0), T(0)};
+#pragma unroll 1
+      for (int t = 0; t < SL; ++t) {
+        const int st = b2 * SL + t;
+        if (st + 1 < NSTEP) fetch(st + 1, pf);
+        step1(st, t, acc);
+        if (LEAN) {
+          if (st + 1 < NSTEP) {
+            __syncthreads();
+            stash(0, pf);
+          }
+        } else if (st + 1 < NSTEP) {
+          stash((st + 1) & 1, pf);
+        }
+        __syncthreads();
+      }
+      group_end(b2, acc);
+    }
+  } else {
+    // Two LDS buffers and two register sets: the rows of step s travel in set s mod 2, loaded
+    // two steps ahead of their use and stored to LDS one step ahead, so that each load has a
+    // whole step to arrive.  Steps are unrolled over one x2 group (and the groups in pairs, so
+    // that every set index is a constant); the loads past the last step repeat it, unused.
+    V pf[2][PER];
+    fetch(0, pf[0]);
+    stash(0, pf[0]);
+    fetch(min(1, NSTEP - 1), pf[1]);
+    __syncthreads();
+    auto group = [&](int b2, auto par) {
+      constexpr int P = decltype(par)::value;   // parity of the group's first step
+      V acc[K];
+#pragma unroll
+      for (int j = 0; j < K; ++j) acc[j] = V{T(0), T(0)};
+      // one step whose rows are in set Q
+      auto one = [&](int t, auto set) {
+        constexpr int Q = decltype(set)::value;
+        const int st = b2 * SL + t;
+        fetch(min(st + 2, NSTEP - 1), pf[Q]);
+        step1(st, t, acc);
+        stash((st + 1) & 1, pf[Q ^ 1]);
+        __syncthreads();
+      };
+      // steps in pairs, the loop kept rolled so that no step's loads are hoisted into another
+      int t = 0;
+#pragma unroll 1
+      for (; t + 2 <= SL; t += 2) {
+        one(t, std::integral_constant<int, P>{});
+        one(t + 1, std::integral_constant<int, P ^ 1>{});
+      }
+      if constexpr (SL & 1) one(t, std::integral_constant<int, P>{});
+      group_end(b2, acc);
+    };
+    for (int b2 = 0; b2 < S2; b2 += 2) {
+      group(b2, std::integral_constant<int, 0>{});
+      if (b2 + 1 < S2) group(b2 + 1, std::integral_constant<int, SL & 1>{});
+    }
   }
   const int p1 = (x1 % S) * R + x1 / S;
 #pragma unroll
@@ -981,14 +1038,14 @@ hipError_t run_planes(const Geom& g, const void* psi_v, const void* psi_c, int n
   if constexpr (split_fits<T, R, K, 4>()) {
     if (variant == 3) {
       const int nblk = ND * (nvs / 4) * (ncs / kTC);
-      k_pair_planes_split<T, ND, R, K, 4><<<nblk, 512, 0, st>>>(pv, pc, nvs, ncs, tw, (cx<T>*)q);
+      k_pair_planes_split<T, ND, R, K, 4, false, kSplitPf2<ND>><<<nblk, 512, 0, st>>>(pv, pc, nvs, ncs, tw, (cx<T>*)q);
       return hipGetLastError();
     }
   }
   if constexpr (split_fits<T, R, K, 2>()) {
     if (variant == 4) {
       const int nblk = ND * (nvs / 2) * (ncs / kTC);
-      k_pair_planes_split<T, ND, R, K, 2><<<nblk, 256, 0, st>>>(pv, pc, nvs, ncs, tw, (cx<T>*)q);
+      k_pair_planes_split<T, ND, R, K, 2, false, kSplitPf2<ND>><<<nblk, 256, 0, st>>>(pv, pc, nvs, ncs, tw, (cx<T>*)q);
       return hipGetLastError();
     }
   }
