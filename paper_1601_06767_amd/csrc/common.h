@@ -90,13 +90,46 @@ template <int R> constexpr int bitrev(int i) {
   return r;
 }
 
+// One butterfly (u, t) -> (u + w t, u - w t), w = exp(+2 pi i M / L).  Where w is not a power of
+// i, the larger of its two components g is factored out: w t = g (y + i z) with y, z formed by one
+// FMA each from the ratio of the smaller to the larger component (at most 1 in size), and then
+// u +- g (y + i z) takes four FMAs: six operations where the rotation followed by the sum and
+// difference takes eight.
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <int L, int M, typename V> __device__ __forceinline__ void bfly2(V& u, V& t) {
+  constexpr int m = ((M % L) + L) % L;
+  if constexpr (m == 0 || 4 * m == L || 2 * m == L || 4 * m == 3 * L) {
+    const V r = rot<L, M>(t);
+    const V a = u;
+    u = cadd(a, r);
+    t = csub(a, r);
+  } else {
+    using T = decltype(t.x);
+    constexpr double c = root32_c(m * (32 / L));
+    constexpr double s = root32_s(m * (32 / L));
+    constexpr bool cbig = (c < 0 ? -c : c) >= (s < 0 ? -s : s);
+    constexpr T g = T(cbig ? c : s);
+    constexpr T q = T(cbig ? s / c : c / s);
+    T y, z;
+    if constexpr (cbig) {   // w t = c ((tr - q ti) + i (ti + q tr)), q = s / c
+      y = fma_t(-q, t.y, t.x);
+      z = fma_t(q, t.x, t.y);
+    } else {                // w t = s ((q tr - ti) + i (tr + q ti)), q = c / s
+      y = fma_t(q, t.x, -t.y);
+      z = fma_t(q, t.y, t.x);
+    }
+    const V a = u;
+    u = V{fma_t(g, y, a.x), fma_t(g, z, a.y)};
+    t = V{fma_t(-g, y, a.x), fma_t(-g, z, a.y)};
+  }
+}
+
 template <int R, int L, int I, int J, typename V> __device__ __forceinline__ void bfly(V* x) {
   if constexpr (I < R) {
     if constexpr (J < L / 2) {
-      V u = x[I + J];
-      V t = rot<L, J>(x[I + J + L / 2]);
-      x[I + J] = cadd(u, t);
-      x[I + J + L / 2] = csub(u, t);
+      bfly2<L, J>(x[I + J], x[I + J + L / 2]);
       bfly<R, L, I, J + 1>(x);
     } else {
       bfly<R, L, I + L, 0>(x);
