@@ -73,17 +73,26 @@ KERNEL_OF_STAGE = {"planes": ("pair_transform.hip", ("k_pair_planes<{t}, 72, 8, 
                    "contract": ("contract.hip", "k_contract_batch<{m},")}
 
 
+def sources_unchanged(tr, src):
+    """True when the kernel's source file and the shared device headers recorded beside it are
+    byte-identical to the ones the counters were taken with."""
+    import hashlib
+    for name in [src] + [n for n in tr["sources"] if n.endswith(".h")]:
+        with open(os.path.join(ROOT, "paper_1601_06767_amd", "csrc", name), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != tr["sources"][name]:
+                return False
+    return True
+
+
 def measured_traffic(stage, mode):
     """HBM bytes per launch of the stage's kernel from the committed FETCH_SIZE / WRITE_SIZE
     summary, or None when that kernel's source changed since the counters were taken."""
-    import hashlib
     try:
         with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
             tr = json.load(f)
         src, pat = KERNEL_OF_STAGE[stage]
-        with open(os.path.join(ROOT, "paper_1601_06767_amd", "csrc", src), "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest() != tr["sources"][src]:
-                return None
+        if not sources_unchanged(tr, src):
+            return None
         pats = pat if isinstance(pat, tuple) else (pat,)
         keys = tuple(p.format(t="double" if mode == "fp64" else "float", m={"fp64": 0, "fp32": 1, "bf16x3": 2}[mode])
                      for p in pats)
@@ -102,13 +111,11 @@ def measured_traffic(stage, mode):
 def traffic_for(prefixes, src):
     """HBM bytes per dispatch of the first kernel in profiles/traffic.json whose name starts with
     one of the prefixes, or None when its source file changed since the counters were taken."""
-    import hashlib
     try:
         with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
             tr = json.load(f)
-        with open(os.path.join(ROOT, "paper_1601_06767_amd", "csrc", src), "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest() != tr["sources"][src]:
-                return None
+        if not sources_unchanged(tr, src):
+            return None
         for k, v in tr["kernels"].items():
             if k.startswith(tuple(prefixes)):
                 return {"read_bytes": v["read_bytes_per_dispatch"], "write_bytes": v["write_bytes_per_dispatch"],
