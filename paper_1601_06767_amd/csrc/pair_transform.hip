@@ -264,6 +264,15 @@ __device__ __forceinline__ int dl_block(int qb) { return (qb >> 1) * 136 + (qb &
 
 constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
 
+// Threads of a finish workgroup: the K^2 lines of the pair in one pass (measured in float32 at
+// 128^3 K 25: 640 threads 4.90 ms per 32k pairs, 512: 5.51, 320: 5.57, 256 (three passes, the
+// last 44% full): 5.89, 128: 7.9; at 72^3 K 15, 256 threads (one pass) and 640 take the same
+// time).  In float64 above 512 lines, two passes: one pass would hold three waves per SIMD to
+// 168 registers and spill.
+template <typename T, int K>
+constexpr int kFinishThreads =
+    sizeof(T) == 8 && K * K > 512 ? ((K * K + 1) / 2 + 63) / 64 * 64 : (K * K + 63) / 64 * 64;
+
 
 // Automatic form (measured per 32k-pair launch on one MI355X).  float64: the lean
 // two-valence kernel where it is built (72^3 K 17: 19.9 against 34.3 ms for the plain
@@ -962,7 +971,7 @@ __global__ __launch_bounds__(256) void k_pair_finish_gen(const cx<T>* __restrict
 }
 
 template <typename T, int ND, int R, int K>
-__global__ __launch_bounds__(256) void k_pair_finish(const cx<T>* __restrict__ q, const int32_t* __restrict__ chi_map,
+__global__ __launch_bounds__((kFinishThreads<T, K>)) void k_pair_finish(const cx<T>* __restrict__ q, const int32_t* __restrict__ chi_map,
                                                      int ng, int ngp, T scale, const cx<T>* __restrict__ twk,
                                                      cx<T>* __restrict__ m) {
   using V = cx<T>;
@@ -1061,7 +1070,7 @@ template <typename T, int ND, int R, int K>
 hipError_t run_finish(const Geom& g, const void* q, int npair, void* m, hipStream_t st) {
   const cx<T>* tw = std::is_same<T, double>::value ? (const cx<T>*)g.d_twk64 : (const cx<T>*)g.d_twk32;
   const T scale = T(1.0 / ((double)ND * ND * ND));
-  k_pair_finish<T, ND, R, K><<<npair, 256, 0, st>>>((const cx<T>*)q, g.d_chi_map, g.ng, g.ngp, scale, tw,
+  k_pair_finish<T, ND, R, K><<<npair, kFinishThreads<T, K>, 0, st>>>((const cx<T>*)q, g.d_chi_map, g.ng, g.ngp, scale, tw,
                                                     (cx<T>*)m);
   return hipGetLastError();
 }
