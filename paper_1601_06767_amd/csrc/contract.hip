@@ -98,7 +98,7 @@ __device__ __forceinline__ void tile_coords(int t, int* ti, int* tj) {
 }
 
 // The same lower triangle in 8 x 8 super-blocks of tiles (super-blocks in the order above,
-// tiles row by row inside each): a run of consecutive indices covers few distinct tile rows
+// tiles column by column inside the off-diagonal ones): a run of consecutive indices covers few distinct tile rows
 // and columns, so the workgroups of one XCD that take such a run share most operand rows in
 // their L2.
 __device__ __forceinline__ void tile_coords_blocked(int t, int nt, int* ti, int* tj) {
@@ -116,9 +116,10 @@ __device__ __forceinline__ void tile_coords_blocked(int t, int nt, int* ti, int*
           while ((i + 1) * (i + 2) / 2 <= t) ++i;
           *ti = r0 + i;
           *tj = c0 + t - i * (i + 1) / 2;
-        } else {
-          *ti = r0 + t / nc;
-          *tj = c0 + t % nc;
+        } else {   // column by column: a run of 32 covers 8 tile rows (A, 128 B per row and
+                   // stage) and 4 tile columns (B, 192 B per row and stage)
+          *ti = r0 + t % nr;
+          *tj = c0 + t / nr;
         }
         return;
       }
