@@ -308,9 +308,10 @@ gw_status enqueue_build(gw_ctx* ctx, const gw_chi0_problem* probs, int nprob, in
   // overlapped).  The float64 and float32 contractions fill the register file, so the next
   // chunk's transforms queue behind them (no gain measured; capping the contraction at one
   // workgroup per CU made float64 slower, 519 -> 558 ms).  The static split-BF16x3 build reads
-  // row images with two 80 KB-LDS workgroups per CU, which leave nothing for the transforms:
-  // no gain either (72^3, 8 chunks of 32k pairs: 101.2 ms overlapped, 100.9 alone; 128^3,
-  // 4 chunks: 473 / 475 ms), so overlap is left to the register-staged form.
+  // row images with workgroups that fill each CU's LDS (measured with two 80 KB workgroups per
+  // CU; the current form takes 120 KB in one), which leave nothing for the transforms: no gain
+  // either (72^3, 8 chunks of 32k pairs: 101.2 ms overlapped, 100.9 alone; 128^3, 4 chunks:
+  // 473 / 475 ms), so overlap is left to the register-staged form.
   int max_ngp = 0;
   for (const ProbPlan& q : L.pp) max_ngp = std::max(max_ngp, q.p->geom->g.ngp);
   const bool ovl =
