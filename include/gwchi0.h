@@ -41,7 +41,9 @@ extern "C" {
 typedef enum {
   GW_OK = 0,
   GW_EINVAL = -1,        /* bad argument: shapes, ranges, aliasing, workspace too small */
-  GW_ENOMEM = -2,        /* a library-internal allocation failed (set-up calls only) */
+  GW_ENOMEM = -2,        /* a library-internal allocation failed (set-up calls only; for tests,
+                            GW_FAULT=alloc:N in the environment fails the N-th device allocation
+                            of each gw_ctx_create / gw_geom_create call) */
   GW_EDEVICE = -3,       /* a HIP runtime call failed */
   GW_ESINGULAR = -4,     /* a pivot of the dielectric matrix was zero or non-finite */
   GW_EUNSUPPORTED = -5   /* a size or mode with no compiled kernel */

@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <unordered_set>
@@ -22,6 +23,19 @@ namespace {
 
 std::string g_create_error;
 std::atomic<unsigned long long> g_geom_ids{0};
+
+// Device allocation of the set-up calls.  GW_FAULT=alloc:N in the environment makes the N-th
+// such allocation of the call fail (counted from 1 within each gw_ctx_create or gw_geom_create
+// call), so that tests reach every failure path of set-up without exhausting the device.
+int fault_alloc_index() {
+  const char* f = std::getenv("GW_FAULT");
+  if (!f || std::strncmp(f, "alloc:", 6) != 0) return 0;
+  return std::atoi(f + 6);
+}
+hipError_t setup_alloc(void** p, size_t bytes, int* count, int fail_at) {
+  if (++*count == fail_at) return hipErrorOutOfMemory;
+  return hipMalloc(p, bytes);
+}
 
 size_t round_up(size_t x, size_t m) { return (x + m - 1) / m * m; }
 
@@ -172,8 +186,10 @@ gw_status gw_ctx_create(int device, void* hip_stream, gw_ctx** out) {
   (void)hipSetDevice(device);
   // the scratch of the allocation-free inverse: its address on this device, looked up once
   hipError_t e = gw::noalloc_scratch_init(device);
-  if (e == hipSuccess) e = hipMalloc(&c->d_pivot_flag, sizeof(int));
-  if (e == hipSuccess) e = hipMalloc(&c->d_check_flag, sizeof(int));
+  int nalloc = 0;
+  const int fail_at = fault_alloc_index();
+  if (e == hipSuccess) e = setup_alloc((void**)&c->d_pivot_flag, sizeof(int), &nalloc, fail_at);
+  if (e == hipSuccess) e = setup_alloc((void**)&c->d_check_flag, sizeof(int), &nalloc, fail_at);
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_check_flag, sizeof(int), hipHostMallocDefault);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
   for (int i = 0; i < 2 && e == hipSuccess; ++i) {
@@ -319,12 +335,14 @@ gw_status gw_geom_create(gw_ctx* ctx, const int n_fft[3], const double* cell, co
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(ctx->device);
   hipError_t e = hipSuccess;
-  e = e == hipSuccess ? hipMalloc(&g.d_wf_map, wf_map.size() * 4) : e;
-  e = e == hipSuccess ? hipMalloc(&g.d_chi_map, chi_map.size() * 4) : e;
-  e = e == hipSuccess ? hipMalloc(&g.d_tw64, nd * sizeof(double2)) : e;
-  e = e == hipSuccess ? hipMalloc(&g.d_tw32, nd * sizeof(float2)) : e;
-  e = e == hipSuccess ? hipMalloc(&g.d_twk64, ntwk * sizeof(double2)) : e;
-  e = e == hipSuccess ? hipMalloc(&g.d_twk32, ntwk * sizeof(float2)) : e;
+  int nalloc = 0;
+  const int fail_at = fault_alloc_index();
+  e = e == hipSuccess ? setup_alloc((void**)&g.d_wf_map, wf_map.size() * 4, &nalloc, fail_at) : e;
+  e = e == hipSuccess ? setup_alloc((void**)&g.d_chi_map, chi_map.size() * 4, &nalloc, fail_at) : e;
+  e = e == hipSuccess ? setup_alloc((void**)&g.d_tw64, nd * sizeof(double2), &nalloc, fail_at) : e;
+  e = e == hipSuccess ? setup_alloc((void**)&g.d_tw32, nd * sizeof(float2), &nalloc, fail_at) : e;
+  e = e == hipSuccess ? setup_alloc((void**)&g.d_twk64, ntwk * sizeof(double2), &nalloc, fail_at) : e;
+  e = e == hipSuccess ? setup_alloc((void**)&g.d_twk32, ntwk * sizeof(float2), &nalloc, fail_at) : e;
   if (e == hipSuccess) e = hipMemcpy(g.d_wf_map, wf_map.data(), wf_map.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(g.d_chi_map, chi_map.data(), chi_map.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(g.d_tw64, tw64.data(), nd * sizeof(double2), hipMemcpyHostToDevice);
