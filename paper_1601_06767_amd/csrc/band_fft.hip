@@ -64,11 +64,17 @@ __device__ __forceinline__ void line_split(int rw, int nd, int b0, int bstep, co
 }
 
 constexpr int kMaxNd = 128;
+// Threads of a k_band_ab workgroup.  Its LDS (the x3 slab) allows two or three workgroups per
+// CU, so larger workgroups keep more waves in flight for the latency-bound gathers and line
+// sums: per 576-band call, 128^3 takes 13.5 ms with 1024 threads, 14.2 with 576 and 18.6 with
+// 256; 96^3 3.0 / 3.2 / 3.1 ms and 72^3 (float64) 1.74 / 1.92 / 2.04 ms with 576 / 1024 / 256.
+constexpr int kBandAbThreads = 1024;   // the launch bound
+inline int band_ab_threads(int nd) { return nd >= 128 ? 1024 : 576; }
 
 // One workgroup per (band slot, j1).  R3 = the x3 line split (g.line.R), the x2 split is
 // fixed at kRows (x2 = b2 + S2 a2, the row groups of the pair kernel).
 template <typename T, int R3>
-__global__ __launch_bounds__(256) void k_band_ab(const double2* __restrict__ coef, int npw,
+__global__ __launch_bounds__(kBandAbThreads) void k_band_ab(const double2* __restrict__ coef, int npw,
                                                  const int32_t* __restrict__ band_idx, int band0, int nvalid, int nrows,
                                                  const int32_t* __restrict__ wf_map, int rw, int nd,
                                                  const cx<T>* __restrict__ tw, cx<T>* __restrict__ tB) {
@@ -180,10 +186,10 @@ hipError_t launch_band_to_real(const Geom& g, const double2* coef, int nrows, co
   const hipError_t ea = g.line.R == 8 ? allow_lds<T, 8>() : allow_lds<T, 16>();
   if (ea != hipSuccess) return ea;
   if (g.line.R == 8)
-    k_band_ab<T, 8><<<grid, 256, lds, st>>>(coef, g.npw, band_idx, band0, nvalid, nrows, g.d_wf_map, g.rw, nd, tw,
+    k_band_ab<T, 8><<<grid, band_ab_threads(nd), lds, st>>>(coef, g.npw, band_idx, band0, nvalid, nrows, g.d_wf_map, g.rw, nd, tw,
                                              (cx<T>*)tB);
   else if (g.line.R == 16)
-    k_band_ab<T, 16><<<grid, 256, lds, st>>>(coef, g.npw, band_idx, band0, nvalid, nrows, g.d_wf_map, g.rw, nd, tw,
+    k_band_ab<T, 16><<<grid, band_ab_threads(nd), lds, st>>>(coef, g.npw, band_idx, band0, nvalid, nrows, g.d_wf_map, g.rw, nd, tw,
                                               (cx<T>*)tB);
   else
     return hipErrorInvalidValue;
